@@ -1,0 +1,637 @@
+"""Plain FP64 CPU oracle of the Tensor Network randomized SVD (TNrSVD).
+
+TEST INFRASTRUCTURE ONLY.  This module is imported by ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``; the
+GPU library neither links nor calls it, and it imports nothing from the GPU
+package.  Everything is numpy float64; LAPACK (through ``numpy.linalg.qr`` and
+``numpy.linalg.svd``) is used only as a step where the paper itself calls for
+a QR or an SVD.
+
+Source: Batselier, Yu, Daniel, Wong, "Computing low-rank approximations of
+large-scale matrices with the Tensor Network randomized SVD" (arXiv 1707.07803).
+
+Orientation (a reading of the paper, recorded in the design notes): the paper
+puts the K-column leg of the random MPO, of Y and of Q on the FIRST core and
+sweeps right-to-left (lemma on random MPOs in Sec. 5.1, Algorithms 5.2 and
+5.3).  This oracle uses the mirror image: the K leg sits on the LAST core and
+the orthogonalisation sweeps run left-to-right.  Reversing the core order of
+an MPO only permutes the rows and columns of the matrix it represents, so the
+singular values are unchanged; ``tnrsvd_paper_orientation`` below implements
+the paper's own orientation and the tests check that the two agree.
+
+Layouts (C order, 0-based):
+  * MPO core i of A:           (R_i, I_i, J_i, R_{i+1}),  R_1 = R_{d+1} = 1
+  * MPS-like core (Y, Q, Z, B^T, U, V): (r_i, n_i, r_{i+1}); the last core is
+    (r_d, n_d, K) -- its right leg is the K column leg.
+  * Row/column multi-indices are little-endian as in eq. (1): the index of the
+    first core varies fastest, [i_1 ... i_d] = i_1 + I_1 i_2 + I_1 I_2 i_3 + ...
+  * Product cores of an MPO with an MPS combine ranks as p = a * r + c, where
+    a is A's rank index and c the MPS rank index.
+
+Parity status of each function is stated in its docstring; the pins live in
+``tests/test_oracle_*.py``.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "multi_index", "mpo_to_dense", "mps_to_dense", "kron_chain",
+    "rank_bounds", "merge_plan", "merge_tail",
+    "splitmix64", "gaussian_counter", "omega_from_seed", "omega_as_mps",
+    "mpo_times_mps", "mpo_t_times_mps", "mpo_add", "mps_gram", "mps_norm",
+    "lq_nonneg", "qr_nonneg", "svd_signfix", "choose_rank",
+    "round_sweep", "tnrsvd", "TNrSVDResult", "dense_rsvd",
+    "tnrsvd_paper_orientation", "reverse_mpo",
+]
+
+# --------------------------------------------------------------------------
+# Sec. 2: multi-indices, reshaping, Kronecker products
+# --------------------------------------------------------------------------
+
+def multi_index(idx: Sequence[int], dims: Sequence[int]) -> int:
+    """Linear index of the multi-index [i_1 i_2 ... i_d], eq. (1), 0-based.
+
+    The first index varies fastest (MATLAB column-major convention).
+    Pinned by the 4x3x2 reshape and vectorisation examples of Sec. 2.
+    """
+    lin, stride = 0, 1
+    for i, n in zip(idx, dims):
+        if not 0 <= i < n:
+            raise IndexError("index out of range")
+        lin += i * stride
+        stride *= n
+    return lin
+
+
+def kron_chain(mats: Sequence[np.ndarray]) -> np.ndarray:
+    """A^(d) kron ... kron A^(1) for mats = [A^(1), ..., A^(d)] (Theorem 3.1).
+
+    The first core is the LAST Kronecker factor.
+    """
+    out = np.ones((1, 1))
+    for m in mats:
+        out = np.kron(m, out)
+    return out
+
+
+def mpo_to_dense(cores: Sequence[np.ndarray]) -> np.ndarray:
+    """Contract an MPO into the (prod I) x (prod J) matrix it represents (Sec. 3).
+
+    Entry ([i_1..i_d], [j_1..j_d]) is A_1[:, i_1, j_1, :] A_2[:, i_2, j_2, :] ...
+    with little-endian multi-indices (eq. 1).  Pinned by Theorem 3.1 (rank-1
+    MPO equals the reversed Kronecker product) and by the 2 x 6 example of
+    Sec. 4.2.
+    """
+    c0 = np.asarray(cores[0], dtype=np.float64)
+    if c0.shape[0] != 1:
+        raise ValueError("first MPO rank must be 1")
+    rows, cols = c0.shape[1], c0.shape[2]
+    T = c0.reshape(rows, cols, c0.shape[3])
+    for c in cores[1:]:
+        c = np.asarray(c, dtype=np.float64)
+        r, I, J, r2 = c.shape
+        if r != T.shape[2]:
+            raise ValueError("rank mismatch")
+        # new row = old_row + rows * x, new col = old_col + cols * y
+        N = np.einsum("abr,rxys->xaybs", T, c)
+        rows, cols = rows * I, cols * J
+        T = N.reshape(rows, cols, r2)
+    if T.shape[2] != 1:
+        raise ValueError("last MPO rank must be 1")
+    return T[:, :, 0]
+
+
+def mps_to_dense(cores: Sequence[np.ndarray]) -> np.ndarray:
+    """Contract an MPS-like chain (last core carries the K leg) to (prod n) x K."""
+    c0 = np.asarray(cores[0], dtype=np.float64)
+    if c0.shape[0] != 1:
+        raise ValueError("first rank must be 1")
+    rows = c0.shape[1]
+    T = c0.reshape(rows, c0.shape[2])
+    for c in cores[1:]:
+        c = np.asarray(c, dtype=np.float64)
+        r, n, r2 = c.shape
+        if r != T.shape[1]:
+            raise ValueError("rank mismatch")
+        N = np.einsum("ar,rxs->xas", T, c)
+        rows *= n
+        T = N.reshape(rows, r2)
+    return T
+
+
+def rank_bounds(rows: Sequence[int], cols: Sequence[int]) -> List[int]:
+    """Upper bounds on the canonical MPO ranks R_2..R_d (Theorem 3.2).
+
+    R_k <= min(prod_{i<k} I_i J_i, prod_{i>=k} I_i J_i).
+    """
+    d = len(rows)
+    s = [r * c for r, c in zip(rows, cols)]
+    out = []
+    for k in range(1, d):
+        out.append(min(math.prod(s[:k]), math.prod(s[k:])))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Merging the cores at the K end (Sec. 6.3 contracts the first cores so that
+# the K-core is at least K x K; mirrored here to the last cores)
+# --------------------------------------------------------------------------
+
+def merge_plan(rows: Sequence[int], cols: Sequence[int], K: int) -> int:
+    """Smallest m such that the last m cores give prod I >= K and prod J >= K.
+
+    The random-MPO lemma of Sec. 5.1 needs K <= J of the K-core, Algorithm 5.2
+    needs I >= K on that core and Algorithm 5.3 needs J >= K.  Raises
+    ValueError when even the whole MPO is too small.
+    """
+    d = len(rows)
+    pi, pj = 1, 1
+    for m in range(1, d + 1):
+        pi *= rows[d - m]
+        pj *= cols[d - m]
+        if pi >= K and pj >= K:
+            return m
+    raise ValueError("prod(I) or prod(J) is smaller than K")
+
+
+def merge_tail(cores: Sequence[np.ndarray], m: int) -> List[np.ndarray]:
+    """Contract the last m MPO cores into one core (R, prod I, prod J, 1).
+
+    The merged row index is little-endian within the group (first merged core
+    fastest), which keeps the global multi-index of eq. (1) unchanged.
+    """
+    cores = [np.asarray(c, dtype=np.float64) for c in cores]
+    d = len(cores)
+    if not 1 <= m <= d:
+        raise ValueError("bad merge count")
+    head = cores[: d - m]
+    T = cores[d - m]
+    for c in cores[d - m + 1:]:
+        a, I1, J1, _ = T.shape
+        _, I2, J2, b = c.shape
+        N = np.einsum("axyr,rXYb->aXxYyb", T, c)
+        T = N.reshape(a, I2 * I1, J2 * J1, b)
+    return head + [T]
+
+
+# --------------------------------------------------------------------------
+# Random test matrix in MPO form (lemma on random MPOs, Sec. 5.1)
+# --------------------------------------------------------------------------
+
+_MASK64 = (1 << 64) - 1
+_GOLDEN = 0x9E3779B97F4A7C15
+
+
+def splitmix64(seed: int, n: int) -> int:
+    """n-th output (0-based) of SplitMix64 (Steele, Lea, Flood 2014), counter form.
+
+    state_n = seed + (n + 1) * 0x9E3779B97F4A7C15 (mod 2^64), then the
+    published finaliser: xor-shift 30, multiply 0xBF58476D1CE4E5B9,
+    xor-shift 27, multiply 0x94D049BB133111EB, xor-shift 31.
+    """
+    z = (seed + (n + 1) * _GOLDEN) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def gaussian_counter(seed: int, n: int) -> float:
+    """n-th standard normal of the counter-based stream (Box and Muller 1958).
+
+    Pair k = n // 2 uses u1 = (splitmix64(seed, 2k) >> 11 + 1) * 2^-53 in (0, 1]
+    and u2 = (splitmix64(seed, 2k+1) >> 11) * 2^-53 in [0, 1); even n takes
+    sqrt(-2 ln u1) cos(2 pi u2), odd n the sine.  Uses the platform libm
+    through Python's math module.
+    """
+    k = n // 2
+    u1 = ((splitmix64(seed, 2 * k) >> 11) + 1) * (2.0 ** -53)
+    u2 = (splitmix64(seed, 2 * k + 1) >> 11) * (2.0 ** -53)
+    rad = math.sqrt(-2.0 * math.log(u1))
+    ang = 2.0 * math.pi * u2
+    return rad * (math.cos(ang) if n % 2 == 0 else math.sin(ang))
+
+
+def omega_from_seed(cols: Sequence[int], K: int, seed: int
+                    ) -> Tuple[List[np.ndarray], np.ndarray]:
+    """Rank-1 random MPO of the lemma in Sec. 5.1 (mirrored: matrix on the last core).
+
+    Returns ([omega_1, ..., omega_{d-1}], Omega_d) with omega_i of length J_i
+    and Omega_d of shape (J_d, K).  Draw order: omega_1 ... omega_{d-1}, then
+    Omega_d in C order, one counter value per entry.
+    """
+    n = 0
+    vecs = []
+    for J in cols[:-1]:
+        vecs.append(np.array([gaussian_counter(seed, n + t) for t in range(J)]))
+        n += J
+    Jd = cols[-1]
+    last = np.array([gaussian_counter(seed, n + t) for t in range(Jd * K)])
+    return vecs, last.reshape(Jd, K)
+
+
+def omega_as_mps(vecs: Sequence[np.ndarray], last: np.ndarray) -> List[np.ndarray]:
+    """Rank-1 MPS-like cores of Omega: (1, J_i, 1) and (1, J_d, K)."""
+    cores = [np.asarray(v, dtype=np.float64).reshape(1, -1, 1) for v in vecs]
+    cores.append(np.asarray(last, dtype=np.float64).reshape(1, *last.shape))
+    return cores
+
+
+# --------------------------------------------------------------------------
+# Matrix multiplication in MPO form (Sec. 5.2)
+# --------------------------------------------------------------------------
+
+def mpo_times_mps(A: Sequence[np.ndarray], X: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Cores of A X: sum over the column index j_i of every core (Sec. 5.2).
+
+    Y_i[(a,c), x, (b,e)] = sum_y A_i[a,x,y,b] X_i[c,y,e];
+    on the last core e is the K leg and A's right rank is 1.
+    Ranks multiply: R_i r_i.
+    """
+    if len(A) != len(X):
+        raise ValueError("core count mismatch")
+    out = []
+    d = len(A)
+    for i, (a, x) in enumerate(zip(A, X)):
+        R, I, J, R2 = a.shape
+        r, Jx, r2 = x.shape
+        if Jx != J:
+            raise ValueError("inner dimension mismatch")
+        Y = np.einsum("axyb,cye->acxbe", a, x)
+        if i == d - 1:
+            if R2 != 1:
+                raise ValueError("last MPO rank must be 1")
+            out.append(Y.reshape(R * r, I, r2))
+        else:
+            out.append(Y.reshape(R * r, I, R2 * r2))
+    return out
+
+
+def mpo_t_times_mps(A: Sequence[np.ndarray], X: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Cores of A^T X: sum over the row index i_i of every core (Sec. 5.2).
+
+    Z_i[(a,c), y, (b,e)] = sum_x A_i[a,x,y,b] X_i[c,x,e].
+    """
+    if len(A) != len(X):
+        raise ValueError("core count mismatch")
+    out = []
+    d = len(A)
+    for i, (a, x) in enumerate(zip(A, X)):
+        R, I, J, R2 = a.shape
+        r, Ix, r2 = x.shape
+        if Ix != I:
+            raise ValueError("inner dimension mismatch")
+        Z = np.einsum("axyb,cxe->acybe", a, x)
+        if i == d - 1:
+            out.append(Z.reshape(R * r, J, r2))
+        else:
+            out.append(Z.reshape(R * r, J, R2 * r2))
+    return out
+
+
+def mpo_add(A: Sequence[np.ndarray], B: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """MPO addition: ranks add, cores are block diagonal (Sec. 3).
+
+    The first core concatenates along its right rank, the last along its left
+    rank, inner cores are block diagonal.  Works for MPO (4-way) cores.
+    """
+    d = len(A)
+    out = []
+    for i, (a, b) in enumerate(zip(A, B)):
+        ra, I, J, ra2 = a.shape
+        rb, _, _, rb2 = b.shape
+        if d == 1:
+            out.append(a + b)
+        elif i == 0:
+            out.append(np.concatenate([a, b], axis=3))
+        elif i == d - 1:
+            out.append(np.concatenate([a, b], axis=0))
+        else:
+            c = np.zeros((ra + rb, I, J, ra2 + rb2))
+            c[:ra, :, :, :ra2] = a
+            c[ra:, :, :, ra2:] = b
+            out.append(c)
+    return out
+
+
+def mps_gram(X: Sequence[np.ndarray], Y: Sequence[np.ndarray]) -> np.ndarray:
+    """X^T Y (K_x x K_y) of two MPS-like chains by transfer matrices, no densify."""
+    E = np.ones((1, 1))
+    for x, y in zip(X, Y):
+        # E[c, e] with c rank of X, e rank of Y
+        E = np.einsum("ce,cxa,exb->ab", E, x, y)
+    return E
+
+
+def mps_norm(X: Sequence[np.ndarray]) -> float:
+    """Frobenius norm of an MPS-like chain (including its K leg)."""
+    return float(math.sqrt(max(np.trace(mps_gram(X, X)), 0.0)))
+
+
+# --------------------------------------------------------------------------
+# Small dense factorisations with fixed gauges
+# --------------------------------------------------------------------------
+
+def qr_nonneg(M: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Economy Householder QR (LAPACK) with diag(R) >= 0 (reading AMB-4).
+
+    Q is m x k, R is k x n, k = min(m, n).
+    """
+    Q, R = np.linalg.qr(M, mode="reduced")
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Q * s[None, :], R * s[:, None]
+
+
+def lq_nonneg(M: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Economy LQ, M = L Q with orthonormal rows of Q and diag(L) >= 0."""
+    Qt, Rt = qr_nonneg(M.T)
+    return Rt.T, Qt.T
+
+
+def svd_signfix(M: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Economy SVD M = U diag(S) Vt with a fixed sign per singular pair.
+
+    The paper leaves singular-vector signs free; here each left singular
+    vector is flipped (with its right partner) so that its entry of largest
+    magnitude (the first one on exact ties) is positive.
+    """
+    U, S, Vt = np.linalg.svd(M, full_matrices=False)
+    if U.shape[1]:
+        piv = np.argmax(np.abs(U), axis=0)
+        s = np.sign(U[piv, np.arange(U.shape[1])])
+        s[s == 0] = 1.0
+        U = U * s[None, :]
+        Vt = Vt * s[:, None]
+    return U, S, Vt
+
+
+def choose_rank(S: np.ndarray, delta: float, rmax: int) -> int:
+    """Rank kept at one bond of the rounding sweep (reading AMB-5).
+
+    Smallest rho >= 1 whose discarded tail satisfies sum_{l >= rho} S_l^2 <=
+    delta^2, then capped at rmax when rmax > 0.  With delta = 0 only exact
+    zeros are dropped.
+    """
+    n = len(S)
+    if n == 0:
+        return 0
+    sq = S.astype(np.float64) ** 2
+    tail = np.concatenate([np.cumsum(sq[::-1])[::-1], [0.0]])  # tail[rho]
+    rho = n
+    for cand in range(1, n + 1):
+        if tail[cand] <= delta * delta:
+            rho = cand
+            break
+    if rmax > 0:
+        rho = min(rho, rmax)
+    return max(rho, 1)
+
+
+# --------------------------------------------------------------------------
+# Rounding fused with the orthogonalisation sweep (Sec. 3 rounding of
+# Oseledets' TT-rounding; Algorithms 5.2/5.3 and the integration described in
+# Sec. 5.4), mirrored to run left-to-right
+# --------------------------------------------------------------------------
+
+def round_sweep(cores: Sequence[np.ndarray], eps: float, rmax: int,
+                last: str = "qr"):
+    """ROUND followed by the orthogonalisation of an MPS-like chain.
+
+    Step 1, right-to-left: LQ of every core (p_i x n_i p_{i+1}); the L factor
+    is absorbed into the left neighbour, leaving cores 2..d with orthonormal
+    rows.
+    Step 2: delta = eps * ||Y||_F / sqrt(d - 1).
+    Step 3, left-to-right: SVD of the (s_i n_i) x p_{i+1} panel of the carried
+    factor times core i; the first rho columns of U become core i of the
+    result and diag(S) Vt is carried right.  The K leg is never truncated.
+    Step 4, last core: 'qr' -> economy QR with diag(R) >= 0 gives Q_d and the
+    K x K R (Algorithm 5.2, mirrored); 'svd' -> SVD gives V_d, sigma and W
+    (Algorithm 5.3, mirrored).
+
+    Returns a dict with 'cores', 'ranks' (the bond ranks kept), 'norm', and
+    'R' or ('sigma', 'W').
+    """
+    C = [np.array(c, dtype=np.float64, copy=True) for c in cores]
+    d = len(C)
+    if C[0].shape[0] != 1:
+        raise ValueError("first rank must be 1")
+    for i in range(d - 1, 0, -1):
+        p, n, q = C[i].shape
+        L, Qr = lq_nonneg(C[i].reshape(p, n * q))
+        k = L.shape[1]
+        C[i] = Qr.reshape(k, n, q)
+        C[i - 1] = np.tensordot(C[i - 1], L, axes=(2, 0))
+    nrm = float(np.linalg.norm(C[0]))
+    delta = eps * nrm / math.sqrt(d - 1) if d > 1 else 0.0
+    T = np.ones((1, 1))
+    ranks = [1]
+    for i in range(d - 1):
+        M = np.tensordot(T, C[i], axes=(1, 0))
+        s, n, q = M.shape
+        U, S, Vt = svd_signfix(M.reshape(s * n, q))
+        rho = choose_rank(S, delta, rmax)
+        C[i] = U[:, :rho].reshape(s, n, rho)
+        T = S[:rho, None] * Vt[:rho]
+        ranks.append(rho)
+    M = np.tensordot(T, C[d - 1], axes=(1, 0))
+    s, n, K = M.shape
+    out = {"norm": nrm, "ranks": ranks}
+    if last == "qr":
+        Q, R = qr_nonneg(M.reshape(s * n, K))
+        C[d - 1] = Q.reshape(s, n, Q.shape[1])
+        out["R"] = R
+    elif last == "svd":
+        X, S, Wt = svd_signfix(M.reshape(s * n, K))
+        C[d - 1] = X.reshape(s, n, X.shape[1])
+        out["sigma"] = S
+        out["W"] = Wt.T
+    else:
+        raise ValueError("last must be 'qr' or 'svd'")
+    out["cores"] = C
+    return out
+
+
+# --------------------------------------------------------------------------
+# TNrSVD: Algorithm 5.1 with the subspace iteration of Algorithm 5.4
+# --------------------------------------------------------------------------
+
+@dataclass
+class TNrSVDResult:
+    sigma: np.ndarray                 # top-k singular values, descending
+    U: List[np.ndarray]               # MPS-like cores, last (r, I_d, k)
+    V: List[np.ndarray]               # MPS-like cores, last (s, J_d, k)
+    sigma_all: np.ndarray             # all K values of the last-core SVD
+    W: np.ndarray                     # K x K
+    Q: List[np.ndarray]               # final orthonormal basis cores
+    merged: List[np.ndarray]          # A after merging
+    ranks: List[List[int]] = field(default_factory=list)  # per rounding
+    Y0: Optional[List[np.ndarray]] = None   # first product A Omega (gauge free)
+
+
+def tnrsvd(A_cores: Sequence[np.ndarray], k: int, p: int, q: int,
+           omega: Optional[Tuple[Sequence[np.ndarray], np.ndarray]] = None,
+           seed: Optional[int] = None, eps: float = 0.0, rmax: int = 0,
+           merge: bool = True) -> TNrSVDResult:
+    """TNrSVD of an MPO matrix A (Algorithm 5.1 in MPO form, Sec. 5).
+
+    1. merge the last cores so that the K-core has I, J >= K (Sec. 6.3);
+    2. Omega: rank-1 random MPO (lemma of Sec. 5.1), given or from ``seed``;
+    3. Y = A Omega (Sec. 5.2); Q = ORTH(ROUND(Y)) (Algorithm 5.2 fused with
+       rounding, Sec. 5.4);
+    4. q times: Y = A^T Q, Q = ORTH(ROUND(Y)); Y = A Q, Q = ORTH(ROUND(Y))
+       (Algorithm 5.4);
+    5. B^T = A^T Q; ROUND and sweep it; SVD of the last core gives sigma, V
+       and W (Algorithm 5.3 mirrored); U = Q W on the last core (Sec. 5.4);
+    6. keep the first k = K - p values and vectors (oversampling, Sec. 5.1).
+    """
+    K = k + p
+    A = [np.asarray(c, dtype=np.float64) for c in A_cores]
+    rows = [c.shape[1] for c in A]
+    cols = [c.shape[2] for c in A]
+    if merge:
+        m = merge_plan(rows, cols, K)
+        A = merge_tail(A, m)
+    else:
+        if A[-1].shape[1] < K or A[-1].shape[2] < K:
+            raise ValueError("last core smaller than K")
+    cols_m = [c.shape[2] for c in A]
+    if omega is None:
+        if seed is None:
+            raise ValueError("need omega or seed")
+        omega = omega_from_seed(cols_m, K, seed)
+    Om = omega_as_mps(*omega)
+    ranks = []
+    Y = mpo_times_mps(A, Om)
+    Y0 = [y.copy() for y in Y]
+    r = round_sweep(Y, eps, rmax, "qr")
+    ranks.append(r["ranks"])
+    Q = r["cores"]
+    for _ in range(q):
+        Z = mpo_t_times_mps(A, Q)
+        r = round_sweep(Z, eps, rmax, "qr")
+        ranks.append(r["ranks"])
+        Y = mpo_times_mps(A, r["cores"])
+        r = round_sweep(Y, eps, rmax, "qr")
+        ranks.append(r["ranks"])
+        Q = r["cores"]
+    Bt = mpo_t_times_mps(A, Q)
+    r = round_sweep(Bt, eps, rmax, "svd")
+    ranks.append(r["ranks"])
+    sig = r["sigma"]
+    W = r["W"]
+    V = r["cores"]
+    U = [c.copy() for c in Q[:-1]]
+    U.append(np.einsum("cxk,kj->cxj", Q[-1], W))
+    Uk = U[:-1] + [U[-1][:, :, :k]]
+    Vk = V[:-1] + [V[-1][:, :, :k]]
+    return TNrSVDResult(sigma=sig[:k].copy(), U=Uk, V=Vk, sigma_all=sig, W=W,
+                        Q=Q, merged=A, ranks=ranks, Y0=Y0)
+
+
+def dense_rsvd(A: np.ndarray, Omega: np.ndarray, q: int):
+    """Algorithm 5.1 on dense matrices with re-orthogonalisation (Algorithm 5.4).
+
+    Y = A Omega, Q = qr(Y); q times {Z = A^T Q, Q_z = qr(Z); Y = A Q_z,
+    Q = qr(Y)}; B = Q^T A = W S V^T; U = Q W.  Used only to pin the MPO
+    pipeline on small matrices.
+    """
+    Q, _ = qr_nonneg(A @ Omega)
+    for _ in range(q):
+        Qz, _ = qr_nonneg(A.T @ Q)
+        Q, _ = qr_nonneg(A @ Qz)
+    B = Q.T @ A
+    W, S, Vt = np.linalg.svd(B, full_matrices=False)
+    return Q @ W, S, Vt.T
+
+
+# --------------------------------------------------------------------------
+# The paper's own orientation (K leg on the first core, right-to-left sweeps)
+# --------------------------------------------------------------------------
+
+def reverse_mpo(cores: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Reverse the core order of an MPO (swapping each core's rank legs)."""
+    return [np.ascontiguousarray(np.transpose(c, (3, 1, 2, 0))) for c in cores[::-1]]
+
+
+def _paper_round_orth(C: List[np.ndarray], eps: float, rmax: int, last: str):
+    """Rounding + Algorithm 5.2 / 5.3 in the paper's orientation.
+
+    Cores are (r, n, r') with the K leg stored as the FIRST core's left leg,
+    shape (K, n_1, r_2).  Left-to-right QR orthogonalisation, then a
+    right-to-left truncated-SVD sweep whose last step (core 1) is the
+    K x (n_1 r_2) RQ or SVD of Algorithms 5.2 / 5.3.
+    """
+    C = [c.copy() for c in C]
+    d = len(C)
+    for i in range(d - 1):
+        p, n, r2 = C[i].shape
+        Q, R = qr_nonneg(C[i].reshape(p * n, r2))
+        C[i] = Q.reshape(p, n, Q.shape[1])
+        C[i + 1] = np.tensordot(R, C[i + 1], axes=(1, 0))
+    nrm = float(np.linalg.norm(C[d - 1]))
+    delta = eps * nrm / math.sqrt(d - 1) if d > 1 else 0.0
+    T = np.ones((1, 1))
+    for i in range(d - 1, 0, -1):
+        M = np.tensordot(C[i], T, axes=(2, 0))
+        p, n, s = M.shape
+        # SVD of the p x (n s) unfolding; keep rows of Vt as the new core
+        U, S, Vt = np.linalg.svd(M.reshape(p, n * s), full_matrices=False)
+        rho = choose_rank(S, delta, rmax)
+        C[i] = Vt[:rho].reshape(rho, n, s)
+        T = U[:, :rho] * S[None, :rho]
+    M = np.tensordot(C[0], T, axes=(2, 0))   # (K, n_1, s)
+    K, n, s = M.shape
+    A1 = M.reshape(K, n * s)
+    if last == "qr":
+        # A1 = R Q1 with Q1 orthonormal rows (RQ factorisation)
+        L, Qr = lq_nonneg(A1)
+        C[0] = Qr.reshape(Qr.shape[0], n, s)
+        return C, L
+    X, S, Vt = np.linalg.svd(A1, full_matrices=False)
+    C[0] = Vt.reshape(Vt.shape[0], n, s)
+    return C, S
+
+
+def tnrsvd_paper_orientation(A_cores: Sequence[np.ndarray], k: int, p: int,
+                             q: int, omega_first: np.ndarray,
+                             omega_vecs: Sequence[np.ndarray],
+                             eps: float = 0.0, rmax: int = 0) -> np.ndarray:
+    """Singular values of TNrSVD with the K leg on the FIRST core (as printed).
+
+    A_cores must already have a first core with I_1, J_1 >= K.  omega_first
+    is J_1 x K, omega_vecs are the vectors of cores 2..d.  Returns the top k
+    singular values.  Used to pin the mirrored orientation of ``tnrsvd``.
+    """
+    K = k + p
+    A = [np.asarray(c, dtype=np.float64) for c in A_cores]
+    d = len(A)
+
+    def times(X, transpose):
+        out = []
+        for i, (a, x) in enumerate(zip(A, X)):
+            R, I, J, R2 = a.shape
+            r, n, r2 = x.shape
+            if transpose:
+                Z = np.einsum("axyb,cxe->acybe", a, x)
+                out.append(Z.reshape(R * r, J, R2 * r2))
+            else:
+                Z = np.einsum("axyb,cye->acxbe", a, x)
+                out.append(Z.reshape(R * r, I, R2 * r2))
+        return out
+
+    # The K leg rides on the first core's left leg: shape (K, J_1, 1).
+    Om = [np.ascontiguousarray(omega_first.T).reshape(K, -1, 1)]
+    Om += [np.asarray(v, dtype=np.float64).reshape(1, -1, 1) for v in omega_vecs]
+    assert len(Om) == d
+    Q, _ = _paper_round_orth(times(Om, False), eps, rmax, "qr")
+    for _ in range(q):
+        Qz, _ = _paper_round_orth(times(Q, True), eps, rmax, "qr")
+        Q, _ = _paper_round_orth(times(Qz, False), eps, rmax, "qr")
+    _, S = _paper_round_orth(times(Q, True), eps, rmax, "svd")
+    return S[:k]
