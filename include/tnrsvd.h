@@ -1,0 +1,233 @@
+/*
+ * tnrsvd.h -- C ABI of the MI355X (gfx950) Tensor Network randomized SVD.
+ *
+ * Method: Batselier, Yu, Daniel, Wong, "Computing low-rank approximations of
+ * large-scale matrices with the Tensor Network randomized SVD" (arXiv
+ * 1707.07803): the randomized SVD of Algorithm 5.1 carried out entirely in
+ * MPO form (Sec. 5), with the subspace iteration of Algorithm 5.4, the MPO
+ * products of Sec. 5.2, the thin QR / economical SVD sweeps of Algorithms 5.2
+ * and 5.3, and the SVD-based rounding of Sec. 3 fused into those sweeps.
+ *
+ * Orientation.  The paper carries the K columns of the random MPO, of Y and
+ * of Q on the FIRST core and sweeps right-to-left.  This library uses the
+ * mirror image: the K leg rides on the LAST core and the orthogonalisation
+ * sweeps run left-to-right.  Singular values are identical; singular vectors
+ * are those of the matrix with the same (little-endian, eq. (1)) row and
+ * column multi-indices.
+ *
+ * Layouts (all C order, 0-based, little-endian multi-indices as in eq. (1)):
+ *   A core i       (R_i, I_i, J_i, R_{i+1}),  R_0 = R_d = 1 (i = 0..d-1)
+ *   basis core i   (r_i, n_i, r_{i+1}); the last core is (r_{d-1}, n_{d-1}, K)
+ *                  where n = I (row space: Q, U) or n = J (column space: V)
+ *   product rank   p = a * r + c  (a: A rank index, c: basis rank index)
+ *
+ * Precision.  Contractions run in the precision chosen in tnrsvd_opts
+ * (FP64, FP32, or BF16 inputs with FP32 accumulation); every QR, SVD and
+ * rank decision of the sweeps runs in FP64.
+ *
+ * Threading.  A handle is bound to one HIP device and one stream (borrowed,
+ * never synchronised except where noted).  Calls on one handle must not
+ * overlap; different handles are independent.  No call throws across the
+ * ABI; every entry point returns a tnrsvd_status and records a message that
+ * tnrsvd_last_error() returns (thread local).
+ */
+#ifndef TNRSVD_H
+#define TNRSVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tnrsvd_s* tnrsvd_t;
+
+typedef enum {
+  TNRSVD_OK = 0,
+  TNRSVD_E_INVALID = -1,   /* null pointer, bad enum, bad option value      */
+  TNRSVD_E_SHAPE = -2,     /* rank/dimension mismatch, K larger than prod I */
+                           /* or prod J, capacity exceeded                  */
+  TNRSVD_E_STATE = -3,     /* call out of the order of Algorithm 5.4        */
+  TNRSVD_E_NOMEM = -4,     /* device allocation failed (nothing leaked)     */
+  TNRSVD_E_DEVICE = -5,    /* HIP runtime error                             */
+  TNRSVD_E_NONFINITE = -6  /* NaN/Inf in an input core (only if checked)    */
+} tnrsvd_status;
+
+typedef enum {
+  TNRSVD_F64 = 0,          /* FP64 contractions                              */
+  TNRSVD_F32 = 1,          /* FP32 contractions, FP32 accumulation           */
+  TNRSVD_BF16 = 2          /* BF16 operands on MFMA, FP32 accumulation       */
+} tnrsvd_precision;
+
+/* One MPO matrix A of size (prod I) x (prod J) (Sec. 3). */
+typedef struct {
+  int d;                     /* number of cores, >= 1                        */
+  const int64_t* rank;       /* d+1 MPO ranks, rank[0] = rank[d] = 1         */
+  const int64_t* rows;       /* I_0 .. I_{d-1}                               */
+  const int64_t* cols;       /* J_0 .. J_{d-1}                               */
+  const void* const* core;   /* d DEVICE pointers, C-contiguous (R,I,J,R')   */
+  int dtype;                 /* TNRSVD_F64 (double) or TNRSVD_F32 (float)    */
+} tnrsvd_mpo;
+
+typedef struct {
+  int k;                     /* number of singular triplets returned, >= 1   */
+  int p;                     /* oversampling, >= 0; K = k + p                */
+  int q;                     /* power iterations used by tnrsvd_run          */
+  uint64_t seed;             /* seed of the counter-based random MPO         */
+  int precision;             /* tnrsvd_precision                             */
+  double round_tol;          /* rounding tolerance eps >= 0 (0: none)        */
+  int64_t max_rank;          /* rounding rank cap r_max (0: none)            */
+  int check_finite;          /* nonzero: scan input cores for NaN/Inf        */
+  void* stream;              /* hipStream_t, borrowed; NULL = null stream    */
+} tnrsvd_opts;
+
+/*
+ * tnrsvd_create -- validate, plan and stage `batch` independent MPOs.
+ *
+ * For each MPO the smallest number m of trailing cores whose row and column
+ * products both reach K = k + p is contracted into one core on the device
+ * (the paper merges the leading cores so that the K-core satisfies
+ * K <= J (random-MPO lemma, Sec. 5.1), I >= K (Algorithm 5.2) and J >= K
+ * (Algorithm 5.3); Sec. 6.3 merges 5 and 7 cores).  Cores are copied into a
+ * library-owned device slab in the contraction precision, so the caller may
+ * free its buffers once this call returns.  The random MPO Omega (rank 1:
+ * one Gaussian vector per core and a J x K Gaussian matrix on the merged
+ * core, Sec. 5.1) is drawn on the device from the counter-based SplitMix64 +
+ * Box-Muller stream seeded by opts->seed; MPO b uses seed + b.
+ *
+ * Ownership: *out receives a handle that must be released by
+ * tnrsvd_destroy.  The call synchronises the stream once (planning reads no
+ * device data, but the staging copies must finish before return).
+ * Errors: E_INVALID (nulls, k < 1, p < 0, q < 0, bad precision/dtype,
+ * negative tolerance), E_SHAPE (rank[0] or rank[d] != 1, non-positive
+ * dimension, prod I < K or prod J < K), E_NONFINITE (check_finite set and a
+ * core holds NaN/Inf), E_NOMEM, E_DEVICE.
+ */
+tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
+                            const tnrsvd_opts* opts);
+
+/*
+ * tnrsvd_mult -- one MPO product of Sec. 5.2 for every MPO of the handle.
+ *   op 0: Y = A X, where X is Omega on the first call and afterwards the
+ *         column-space basis produced by the last tnrsvd_orthogonalize;
+ *   op 1: Z = A^T Q, where Q is the row-space basis of the last
+ *         tnrsvd_orthogonalize.
+ * Per core, the product sums over the shared mode index; ranks multiply
+ * (R_i r_i).  Enqueued on the stream, no synchronisation.
+ * Errors: E_INVALID (op not 0/1), E_STATE (a product is already pending, or
+ * the current basis lives in the wrong space).
+ */
+tnrsvd_status tnrsvd_mult(tnrsvd_t h, int op);
+
+/*
+ * tnrsvd_orthogonalize -- ROUND + thin QR of the pending product
+ * (Algorithm 5.2 fused with the rounding of Sec. 3 as described in Sec. 5.4,
+ * mirrored): a right-to-left LQ sweep, then a left-to-right truncated-SVD
+ * sweep (tolerance eps ||Y||_F / sqrt(d-1) per bond, cap r_max, the K leg
+ * never truncated, rank decisions in FP64), ending in an FP64 Householder QR
+ * of the last core with diag(R) >= 0.  The result becomes the current basis
+ * (left-orthonormal cores).  Enqueued on the stream.
+ * Errors: E_STATE (no pending product).
+ */
+tnrsvd_status tnrsvd_orthogonalize(tnrsvd_t h);
+
+/*
+ * tnrsvd_project -- B^T = A^T Q (B = Q^T A of Algorithm 5.1) with the
+ * current row-space basis Q.  Enqueued on the stream.
+ * Errors: E_STATE (no row-space basis, or a product is pending).
+ */
+tnrsvd_status tnrsvd_project(tnrsvd_t h);
+
+/*
+ * tnrsvd_solve -- economical SVD of B in MPO form (Algorithm 5.3 fused with
+ * the rounding, mirrored): ROUND and sweep B^T to its last core, FP64
+ * one-sided Jacobi SVD of that core giving sigma (descending), W (K x K) and
+ * V; then U = Q W on the last core of Q (Sec. 5.4).  Keeps the first k.
+ * sigma: HOST buffer of batch*k doubles (MPO b at sigma + b*k) or NULL; when
+ * non-NULL the call synchronises the stream to copy it out.
+ * Errors: E_STATE (tnrsvd_project has not run).
+ */
+tnrsvd_status tnrsvd_solve(tnrsvd_t h, double* sigma);
+
+/*
+ * tnrsvd_run -- the whole sequence: mult(0), orthogonalize,
+ * q x {mult(1), orthogonalize, mult(0), orthogonalize}, project, solve
+ * (Algorithm 5.4 then Algorithm 5.1).  May be called again on the same
+ * handle; every call restarts from Omega.  sigma as in tnrsvd_solve.
+ */
+tnrsvd_status tnrsvd_run(tnrsvd_t h, double* sigma);
+
+/*
+ * tnrsvd_get_factor -- borrow a device pointer to one core of a result.
+ *   which 0: U (row space, last core (r, I, k)), available after solve;
+ *   which 1: V (column space, last core (s, J, k)), after solve;
+ *   which 2: the current basis (Q after an orthogonalize; last core (r,n,K));
+ *   which 3: the first product Y = A Omega of the last run (last (R,I,K)),
+ *            valid until the next tnrsvd_mult.
+ * shape receives (r, n, r', 1) and *dtype TNRSVD_F64 or TNRSVD_F32: U and V
+ * are FP64, the basis and Y are stored in the contraction type (FP32 for
+ * the FP32 and BF16 modes).  The pointer stays valid until the next call
+ * on the handle other than a getter.  The call synchronises the stream
+ * (ranks are read from the device).
+ * Errors: E_INVALID (b, which or core out of range), E_STATE (not available).
+ */
+tnrsvd_status tnrsvd_get_factor(tnrsvd_t h, int b, int which, int core,
+                                const void** dev_ptr, int64_t shape[4], int* dtype);
+
+/*
+ * tnrsvd_copy_factor -- copy one core described by tnrsvd_get_factor into a
+ * caller-owned DEVICE buffer dst (shape[0]*shape[1]*shape[2] elements of the
+ * reported dtype), enqueued on the handle's stream and then synchronised.
+ * Same arguments and errors as tnrsvd_get_factor; dst must not be NULL.
+ */
+tnrsvd_status tnrsvd_copy_factor(tnrsvd_t h, int b, int which, int core, void* dst);
+
+/*
+ * tnrsvd_get_omega / tnrsvd_set_omega -- read or replace Omega of MPO b in
+ * FP64, as the concatenation omega_0 (J_0 values), ..., omega_{d'-2}, then
+ * the J_{d'-1} x K matrix of the merged core in C order; *n (get) receives
+ * the count, d' being the merged core count.  set_omega copies host_in
+ * (that many doubles) to the device and synchronises the stream.
+ */
+tnrsvd_status tnrsvd_get_omega(tnrsvd_t h, int b, double* host_out, int64_t* n);
+tnrsvd_status tnrsvd_set_omega(tnrsvd_t h, int b, const double* host_in);
+
+/*
+ * tnrsvd_get_ranks -- bond ranks of the current basis of MPO b: d'+1 values
+ * r_0 = 1, ..., r_{d'} = K written to host_out (synchronises the stream).
+ * *d_merged receives d'.
+ */
+tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merged);
+
+/*
+ * Measurement aids.
+ *
+ * tnrsvd_profile -- enable (nonzero) or disable (0) per-launch timing: while
+ * enabled, every kernel launch of the handle is bracketed by two HIP events
+ * recorded on the handle's stream.  Enabling clears earlier records.
+ * tnrsvd_profile_read -- synchronise the stream and return, for one kernel
+ * kind, the summed event time (ms) and the launch count since enabling.
+ * Kernel kinds: 0 contraction (Sec. 5.2 products), 1 right-to-left LQ sweep,
+ * 2 left-to-right truncation/QR/SVD sweep, 3 U = Q W, 4 Omega load, 5 Y copy.
+ * tnrsvd_get_product_ranks -- product ranks P_0..P_d (P_d = K) of the last
+ * product and the ranks rho_0..rho_d left by its right-to-left sweep (valid
+ * after the sweep); synchronises the stream.  Either pointer may be NULL.
+ */
+tnrsvd_status tnrsvd_profile(tnrsvd_t h, int enable);
+tnrsvd_status tnrsvd_profile_read(tnrsvd_t h, int kernel, double* total_ms, int64_t* launches);
+tnrsvd_status tnrsvd_get_product_ranks(tnrsvd_t h, int b, int64_t* P_out, int64_t* rho_out);
+
+/* tnrsvd_destroy -- free every device buffer of the handle (NULL is a no-op). */
+tnrsvd_status tnrsvd_destroy(tnrsvd_t h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* tnrsvd_last_error(void);
+
+/* Library version string. */
+const char* tnrsvd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNRSVD_H */

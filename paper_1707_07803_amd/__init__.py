@@ -1,0 +1,13 @@
+"""MI355X (gfx950) Tensor Network randomized SVD (arXiv 1707.07803).
+
+The hot path -- MPO x random-MPO contraction, FP64 rounding + Householder QR
+sweeps, projection and the small SVD of the last core -- runs in the HIP
+kernels of ``libtnrsvd.so`` behind the C ABI of ``include/tnrsvd.h``.  This
+package holds the build script and a thin ctypes binding.
+"""
+
+from .tnrsvd import (TNrSVD, TNrSVDError, solve, load_library, omega_flat,  # noqa: F401
+                     LIB_PATH, EXPORTS, PRECISIONS)
+
+__all__ = ["TNrSVD", "TNrSVDError", "solve", "load_library", "omega_flat", "LIB_PATH",
+           "EXPORTS", "PRECISIONS"]

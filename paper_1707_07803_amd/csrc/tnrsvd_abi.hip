@@ -1,0 +1,842 @@
+// Host runtime behind include/tnrsvd.h: validation, merge plan, capacity plan,
+// device slabs, the call-order state machine of Algorithm 5.4, and launches.
+// No step of the method runs on the host: shapes are planned here, all
+// arithmetic runs in the kernels of kernels_contract.hip / kernels_sweep.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tnrsvd.h"
+#include "tnrsvd_internal.h"
+
+
+using namespace tnr;
+
+namespace {
+
+thread_local std::string g_err;
+
+tnrsvd_status fail(tnrsvd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+constexpr int64_t kSat = int64_t(1) << 40;   // saturation of mode-size products
+constexpr int64_t kHardCap = 4096;           // largest bond rank a plan may reserve
+
+inline int64_t sat_mul(int64_t a, int64_t b) {
+  if (a >= kSat || b >= kSat) return kSat;
+  const int64_t r = a * b;
+  return r > kSat ? kSat : r;
+}
+
+enum Space { kNone = 0, kRow = 1, kCol = 2 };
+
+constexpr int kKinds = 6;  // contract, rl, lr, form_u, load_omega, copy_y0
+
+}  // namespace
+
+struct tnrsvd_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int batch = 0;
+  int dtype = 0;         // contraction storage: 0 double, 1 float
+  tnrsvd_opts opts{};
+  std::vector<MpoDesc> mh;
+  std::vector<CoreDesc> ch;
+  std::vector<int> core_mpo;
+  int ncores = 0, max_d = 0;
+  int64_t max_core_out = 1, max_om = 1, max_y0 = 1;
+  int vcap = 64, scap = 64;
+  int64_t tcap = 1, mcap_s = 1, ucap = 1;
+  // device buffers
+  MpoDesc* mpos_d = nullptr;
+  CoreDesc* cores_d = nullptr;
+  int* core_mpo_d = nullptr;
+  int *xr = nullptr, *vr = nullptr, *pr = nullptr, *rho = nullptr, *err = nullptr;
+  void *A = nullptr, *X = nullptr, *Z = nullptr, *Y0 = nullptr;
+  double *W = nullptr, *L = nullptr, *tau = nullptr, *scratch = nullptr, *outs = nullptr,
+         *om = nullptr, *U = nullptr, *V = nullptr;
+  std::vector<void*> allocs;
+  // state machine
+  int space = kNone;     // where the current basis lives
+  int pending = -1;      // op of a pending product, -1 none
+  bool projected = false;
+  bool solved = false;
+  bool y0_valid = false;
+  bool first_product = true;
+  // measurement: event pairs per kernel kind
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[kKinds];
+};
+
+namespace {
+
+template <typename P>
+tnrsvd_status dalloc(tnrsvd_s* h, P** out, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  const hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TNRSVD_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  }
+  h->allocs.push_back(p);
+  *out = (P*)p;
+  return TNRSVD_OK;
+}
+
+void release(tnrsvd_s* h) {
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+}
+
+tnrsvd_status dev_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TNRSVD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  }
+  return TNRSVD_OK;
+}
+
+#define TRY(x)                               \
+  do {                                       \
+    const tnrsvd_status st_ = (x);           \
+    if (st_ != TNRSVD_OK) return st_;        \
+  } while (0)
+
+// Validate one MPO and return the merge count m (last m cores become one).
+tnrsvd_status plan_mpo(const tnrsvd_mpo& a, int K, int* m_out) {
+  if (a.d < 1) return fail(TNRSVD_E_SHAPE, "d must be >= 1");
+  if (!a.rank || !a.rows || !a.cols || !a.core)
+    return fail(TNRSVD_E_INVALID, "null rank/rows/cols/core array");
+  if (a.dtype != TNRSVD_F64 && a.dtype != TNRSVD_F32)
+    return fail(TNRSVD_E_INVALID, "core dtype must be TNRSVD_F64 or TNRSVD_F32");
+  if (a.rank[0] != 1 || a.rank[a.d] != 1)
+    return fail(TNRSVD_E_SHAPE, "rank[0] and rank[d] must be 1");
+  for (int i = 0; i < a.d; ++i) {
+    if (a.rows[i] < 1 || a.cols[i] < 1 || a.rank[i + 1] < 1)
+      return fail(TNRSVD_E_SHAPE, "core %d: non-positive dimension or rank", i);
+    if (a.rank[i] > 65536 || a.rows[i] > 65536 || a.cols[i] > 65536)
+      return fail(TNRSVD_E_SHAPE, "core %d: dimension too large", i);
+    if (!a.core[i]) return fail(TNRSVD_E_INVALID, "core %d: null pointer", i);
+  }
+  int64_t pi = 1, pj = 1;
+  for (int m = 1; m <= a.d; ++m) {
+    pi = sat_mul(pi, a.rows[a.d - m]);
+    pj = sat_mul(pj, a.cols[a.d - m]);
+    if (pi >= K && pj >= K) {
+      *m_out = m;
+      return TNRSVD_OK;
+    }
+  }
+  return fail(TNRSVD_E_SHAPE, "prod(I) = %lld or prod(J) = %lld is smaller than K = %d",
+              (long long)pi, (long long)pj, K);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tnrsvd_last_error(void) { return g_err.c_str(); }
+
+const char* tnrsvd_version(void) { return "tnrsvd-gfx950 0.1"; }
+
+tnrsvd_status tnrsvd_destroy(tnrsvd_t h) {
+  if (!h) return TNRSVD_OK;
+  (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  release(h);
+  delete h;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
+                            const tnrsvd_opts* o) {
+  g_err.clear();
+  if (!out || !mpos || !o) return fail(TNRSVD_E_INVALID, "null argument");
+  *out = nullptr;
+  if (batch < 1) return fail(TNRSVD_E_INVALID, "batch must be >= 1");
+  if (o->k < 1 || o->p < 0 || o->q < 0)
+    return fail(TNRSVD_E_INVALID, "need k >= 1, p >= 0, q >= 0");
+  const int K = o->k + o->p;
+  if (K > kMaxK) return fail(TNRSVD_E_INVALID, "K = k + p must be <= %d", kMaxK);
+  if (o->precision != TNRSVD_F64 && o->precision != TNRSVD_F32 && o->precision != TNRSVD_BF16)
+    return fail(TNRSVD_E_INVALID, "unknown precision %d", o->precision);
+  if (!(o->round_tol >= 0.0) || !std::isfinite(o->round_tol))
+    return fail(TNRSVD_E_INVALID, "round_tol must be finite and >= 0");
+  if (o->max_rank < 0) return fail(TNRSVD_E_INVALID, "max_rank must be >= 0");
+  if (o->precision == TNRSVD_BF16)
+    return fail(TNRSVD_E_INVALID, "BF16 contractions are not available in this build");
+
+  std::vector<int> merge(batch);
+  for (int b = 0; b < batch; ++b) TRY(plan_mpo(mpos[b], K, &merge[b]));
+
+  tnrsvd_s* h = new (std::nothrow) tnrsvd_s();
+  if (!h) return fail(TNRSVD_E_NOMEM, "host allocation failed");
+  h->batch = batch;
+  h->opts = *o;
+  h->stream = (hipStream_t)o->stream;
+  h->dtype = (o->precision == TNRSVD_F64) ? 0 : 1;
+  (void)hipGetDevice(&h->device);
+  const int64_t rmax = o->max_rank;
+
+  // ---- capacity plan -----------------------------------------------------
+  int64_t a_tot = 0, x_tot = 0, z_tot = 0, w_tot = 0, l_tot = 0, t_tot = 0, y_tot = 0,
+          u_tot = 0, om_tot = 0, s_tot = 0, out_tot = 0;
+  int r_tot = 0;
+  int64_t tcap = 1, mcap_s = 1, ucap = 1;
+  int vcap = 64, scap = K;
+  for (int b = 0; b < batch; ++b) {
+    const tnrsvd_mpo& a = mpos[b];
+    const int m = merge[b];
+    const int dm = a.d - m + 1;
+    std::vector<int64_t> I(dm), J(dm), R(dm + 1);
+    for (int i = 0; i < dm - 1; ++i) {
+      I[i] = a.rows[i];
+      J[i] = a.cols[i];
+      R[i] = a.rank[i];
+    }
+    I[dm - 1] = 1;
+    J[dm - 1] = 1;
+    for (int i = dm - 1; i < a.d; ++i) {
+      I[dm - 1] *= a.rows[i];
+      J[dm - 1] *= a.cols[i];
+    }
+    R[dm - 1] = a.rank[dm - 1];
+    R[dm] = 1;
+    if (I[dm - 1] > 65536 || J[dm - 1] > 65536) {
+      delete h;
+      return fail(TNRSVD_E_SHAPE, "merged core too large (%lld x %lld)", (long long)I[dm - 1],
+                  (long long)J[dm - 1]);
+    }
+    // bond capacities of the basis: Theorem 3.2 style bounds, the cap, growth
+    std::vector<int64_t> xc(dm + 1);
+    xc[0] = 1;
+    xc[dm] = K;
+    for (int i = 1; i < dm; ++i) {
+      int64_t li = 1, lj = 1, ri = K, rj = K;
+      for (int j = 0; j < i; ++j) {
+        li = sat_mul(li, I[j]);
+        lj = sat_mul(lj, J[j]);
+      }
+      for (int j = i; j < dm; ++j) {
+        ri = sat_mul(ri, I[j]);
+        rj = sat_mul(rj, J[j]);
+      }
+      int64_t cap = std::min(std::max(li, lj), std::max(ri, rj));
+      if (rmax > 0) cap = std::min<int64_t>(cap, rmax);
+      // without a cap, ranks of the rounded products are bounded by R^(2q+2)
+      int64_t g = 1;
+      for (int t = 0; t < 2 * o->q + 2; ++t) g = sat_mul(g, R[i]);
+      cap = std::min(cap, std::max<int64_t>(g, 1));
+      if (cap > kHardCap) {
+        delete h;
+        return fail(TNRSVD_E_SHAPE,
+                    "MPO %d bond %d would need rank capacity %lld > %lld; set max_rank", b, i,
+                    (long long)cap, (long long)kHardCap);
+      }
+      xc[i] = cap;
+    }
+    MpoDesc md{};
+    md.d = dm;
+    md.K = K;
+    md.c0 = (int)h->ch.size();
+    md.r0 = r_tot;
+    r_tot += dm + 1;
+    md.om_off = om_tot;
+    int64_t omn = 0;
+    for (int i = 0; i < dm - 1; ++i) omn += J[i];
+    omn += J[dm - 1] * K;
+    om_tot += omn;
+    h->max_om = std::max(h->max_om, omn);
+    int64_t mpo_t = 1, mpo_m = 1, mpo_u = 1;
+    int mpo_v = 64;
+    for (int i = 0; i < dm; ++i) {
+      CoreDesc cd{};
+      cd.I = (int)I[i];
+      cd.J = (int)J[i];
+      cd.RA = (int)R[i];
+      cd.RA2 = (int)R[i + 1];
+      cd.xcap = (int)xc[i];
+      cd.xcap2 = (int)xc[i + 1];
+      const int64_t nmax = std::max(I[i], J[i]);
+      const int64_t P = R[i] * xc[i], P2 = R[i + 1] * xc[i + 1];
+      cd.a_off = a_tot;
+      a_tot += R[i] * I[i] * J[i] * R[i + 1];
+      cd.x_off = x_tot;
+      cd.u_off = x_tot;
+      x_tot += xc[i] * nmax * xc[i + 1];
+      cd.z_off = z_tot;
+      z_tot += P * nmax * P2;
+      cd.w_off = w_tot;
+      w_tot += nmax * P2 * P;
+      cd.l_off = l_tot;
+      l_tot += P * P;
+      cd.tau_off = t_tot;
+      t_tot += P;
+      cd.y0_off = y_tot;
+      y_tot += R[i] * I[i] * R[i + 1] * (i == dm - 1 ? K : 1);
+      h->max_core_out = std::max(h->max_core_out, P * nmax * P2);
+      mpo_t = std::max(mpo_t, xc[i] * P);
+      mpo_t = std::max(mpo_t, xc[i + 1] * P2);
+      mpo_m = std::max(mpo_m, xc[i] * nmax * P2);
+      mpo_v = (int)std::max<int64_t>(mpo_v, nmax * P2);
+      const int64_t nv = xc[i] * nmax;
+      if (i < dm - 1) {
+        scap = (int)std::max<int64_t>(scap, nv);
+        mpo_u = std::max(mpo_u, nv * nv);
+      } else {
+        mpo_v = (int)std::max<int64_t>(mpo_v, nv);
+        mpo_u = std::max(mpo_u, 2 * nv * K + K + (int64_t)K * K);
+      }
+      h->ch.push_back(cd);
+      h->core_mpo.push_back(b);
+    }
+    md.s_off = s_tot;
+    md.s_len = mpo_t + mpo_m + mpo_u;
+    s_tot += md.s_len;
+    md.out_off = out_tot;
+    out_tot += K + 2 * (int64_t)K * K;
+    md.mcap = mpo_v;
+    md.pcap = 0;
+    tcap = std::max(tcap, mpo_t);
+    mcap_s = std::max(mcap_s, mpo_m);
+    ucap = std::max(ucap, mpo_u);
+    vcap = std::max(vcap, mpo_v);
+    h->max_d = std::max(h->max_d, dm);
+    h->mh.push_back(md);
+  }
+  // every MPO's scratch uses the global maxima so the kernels share one layout
+  s_tot = 0;
+  for (auto& md : h->mh) {
+    md.s_off = s_tot;
+    md.s_len = tcap + mcap_s + ucap;
+    s_tot += md.s_len;
+  }
+  h->ncores = (int)h->ch.size();
+  h->vcap = vcap;
+  h->scap = scap;
+  h->tcap = tcap;
+  h->mcap_s = mcap_s;
+  h->ucap = ucap;
+  const size_t lds = sizeof(double) * ((size_t)vcap + kSweepThreads / 64 + 3 * (size_t)scap) +
+                     sizeof(int) * ((size_t)scap + 8);
+  if (lds > 64 * 1024) {
+    delete h;
+    return fail(TNRSVD_E_SHAPE, "sweep needs %zu bytes of LDS (> 64 KiB); lower max_rank", lds);
+  }
+  const size_t esz = h->dtype == 0 ? sizeof(double) : sizeof(float);
+
+  // ---- allocation ---------------------------------------------------------
+  tnrsvd_status st = TNRSVD_OK;
+#define ALLOC(ptr, bytes)                         \
+  do {                                            \
+    st = dalloc(h, &(ptr), (bytes));              \
+    if (st != TNRSVD_OK) {                        \
+      release(h);                                 \
+      delete h;                                   \
+      return st;                                  \
+    }                                             \
+  } while (0)
+  ALLOC(h->mpos_d, sizeof(MpoDesc) * batch);
+  ALLOC(h->cores_d, sizeof(CoreDesc) * h->ncores);
+  ALLOC(h->core_mpo_d, sizeof(int) * h->ncores);
+  ALLOC(h->xr, sizeof(int) * r_tot);
+  ALLOC(h->vr, sizeof(int) * r_tot);
+  ALLOC(h->pr, sizeof(int) * r_tot);
+  ALLOC(h->rho, sizeof(int) * r_tot);
+  ALLOC(h->err, sizeof(int) * 4);
+  ALLOC(h->A, esz * a_tot);
+  ALLOC(h->X, esz * x_tot);
+  ALLOC(h->Z, esz * z_tot);
+  ALLOC(h->Y0, esz * y_tot);
+  ALLOC(h->W, sizeof(double) * w_tot);
+  ALLOC(h->L, sizeof(double) * l_tot);
+  ALLOC(h->tau, sizeof(double) * t_tot);
+  ALLOC(h->scratch, sizeof(double) * s_tot);
+  ALLOC(h->outs, sizeof(double) * out_tot);
+  ALLOC(h->om, sizeof(double) * om_tot);
+  ALLOC(h->U, sizeof(double) * x_tot);
+  ALLOC(h->V, sizeof(double) * x_tot);
+#undef ALLOC
+  hipStream_t s = h->stream;
+  auto fail_dev = [&](hipError_t e, const char* what) {
+    const tnrsvd_status r = dev_check(e, what);
+    release(h);
+    delete h;
+    return r;
+  };
+  hipError_t e;
+  if ((e = hipMemcpyAsync(h->mpos_d, h->mh.data(), sizeof(MpoDesc) * batch,
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return fail_dev(e, "upload MPO descriptors");
+  if ((e = hipMemcpyAsync(h->cores_d, h->ch.data(), sizeof(CoreDesc) * h->ncores,
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return fail_dev(e, "upload core descriptors");
+  if ((e = hipMemcpyAsync(h->core_mpo_d, h->core_mpo.data(), sizeof(int) * h->ncores,
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return fail_dev(e, "upload core map");
+  if ((e = hipMemsetAsync(h->err, 0, sizeof(int) * 4, s)) != hipSuccess)
+    return fail_dev(e, "clear error flags");
+
+  // ---- stage A: copy/convert leading cores, merge the trailing ones (FP64) --
+  int64_t tmp_need = 1;
+  for (int b = 0; b < batch; ++b) {
+    const tnrsvd_mpo& a = mpos[b];
+    const int m = merge[b];
+    if (m > 1) {
+      int64_t acc = a.rank[a.d - m];
+      int64_t in = 1, jn = 1;
+      for (int i = a.d - m; i < a.d; ++i) {
+        in *= a.rows[i];
+        jn *= a.cols[i];
+        tmp_need = std::max(tmp_need, a.rank[i] * a.rows[i] * a.cols[i] * a.rank[i + 1]);
+        tmp_need = std::max(tmp_need, acc * in * jn * a.rank[i + 1]);
+      }
+    }
+  }
+  double *t0 = nullptr, *t1 = nullptr, *t2 = nullptr;
+  if ((e = hipMalloc(&t0, sizeof(double) * tmp_need)) != hipSuccess ||
+      (e = hipMalloc(&t1, sizeof(double) * tmp_need)) != hipSuccess ||
+      (e = hipMalloc(&t2, sizeof(double) * tmp_need)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (t0) (void)hipFree(t0);
+    if (t1) (void)hipFree(t1);
+    release(h);
+    delete h;
+    return fail(TNRSVD_E_NOMEM, "merge staging allocation failed");
+  }
+  int* fin = h->err + 2;
+  for (int b = 0; b < batch && e == hipSuccess; ++b) {
+    const tnrsvd_mpo& a = mpos[b];
+    const MpoDesc& md = h->mh[b];
+    const int m = merge[b];
+    const int dm = md.d;
+    char* Abase = (char*)h->A;
+    if (o->check_finite) {
+      for (int i = 0; i < a.d && e == hipSuccess; ++i)
+        e = launch_check_finite(a.core[i], a.dtype,
+                                a.rank[i] * a.rows[i] * a.cols[i] * a.rank[i + 1], fin, s);
+    }
+    for (int i = 0; i < dm - 1 && e == hipSuccess; ++i) {
+      const CoreDesc& cd = h->ch[md.c0 + i];
+      e = launch_convert_core(a.core[i], a.dtype, Abase + esz * cd.a_off, h->dtype,
+                              a.rank[i] * a.rows[i] * a.cols[i] * a.rank[i + 1], s);
+    }
+    const CoreDesc& cl = h->ch[md.c0 + dm - 1];
+    const int f = a.d - m;
+    if (m == 1) {
+      if (e == hipSuccess)
+        e = launch_convert_core(a.core[f], a.dtype, Abase + esz * cl.a_off, h->dtype,
+                                a.rank[f] * a.rows[f] * a.cols[f] * a.rank[f + 1], s);
+    } else {
+      // T <- core f (FP64); repeatedly T <- merge(T, core j)
+      int64_t ra = a.rank[f], ti = a.rows[f], tj = a.cols[f], tb = a.rank[f + 1];
+      if (e == hipSuccess) e = launch_convert_core(a.core[f], a.dtype, t0, 0, ra * ti * tj * tb, s);
+      double* cur = t0;
+      double* nxt = t1;
+      for (int j = f + 1; j < a.d && e == hipSuccess; ++j) {
+        e = launch_convert_core(a.core[j], a.dtype, t2, 0,
+                                a.rank[j] * a.rows[j] * a.cols[j] * a.rank[j + 1], s);
+        if (e != hipSuccess) break;
+        e = launch_merge_pair(cur, t2, nxt, (int)ra, (int)ti, (int)tj, (int)tb, (int)a.rows[j],
+                              (int)a.cols[j], (int)a.rank[j + 1], s);
+        ti *= a.rows[j];
+        tj *= a.cols[j];
+        tb = a.rank[j + 1];
+        std::swap(cur, nxt);
+      }
+      if (e == hipSuccess)
+        e = launch_convert_core(cur, 0, Abase + esz * cl.a_off, h->dtype, ra * ti * tj * tb, s);
+    }
+  }
+  if (e == hipSuccess) e = launch_omega(h->mpos_d, h->cores_d, batch, o->seed, h->om, h->max_om, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(t0);
+  (void)hipFree(t1);
+  (void)hipFree(t2);
+  if (e != hipSuccess) return fail_dev(e, "staging the MPO cores");
+  if (o->check_finite) {
+    int flag = 0;
+    if ((e = hipMemcpy(&flag, fin, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+      return fail_dev(e, "read finite flag");
+    if (flag) {
+      release(h);
+      delete h;
+      return fail(TNRSVD_E_NONFINITE, "an input core holds NaN or Inf");
+    }
+  }
+  *out = h;
+  return TNRSVD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hipEvent_t next_event(tnrsvd_t h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Bracket one launch with events when profiling is enabled.
+struct Timed {
+  tnrsvd_t h;
+  int kind;
+  hipEvent_t a = nullptr;
+  Timed(tnrsvd_t hh, int k) : h(hh), kind(k) {
+    if (h->profiling) {
+      a = next_event(h);
+      if (a) (void)hipEventRecord(a, h->stream);
+    }
+  }
+  ~Timed() {
+    if (h->profiling && a) {
+      hipEvent_t b = next_event(h);
+      if (b) {
+        (void)hipEventRecord(b, h->stream);
+        h->ev_pairs[kind].push_back({a, b});
+      }
+    }
+  }
+};
+
+tnrsvd_status check_handle(tnrsvd_t h) {
+  g_err.clear();
+  if (!h) return fail(TNRSVD_E_INVALID, "null handle");
+  return TNRSVD_OK;
+}
+
+tnrsvd_status load_omega(tnrsvd_t h) {
+  Timed tm(h, 4);
+  hipError_t e = launch_load_omega(h->mpos_d, h->cores_d, h->batch, h->om, h->xr, h->X, h->dtype,
+                                   h->max_d, h->max_om, h->stream);
+  TRY(dev_check(e, "load Omega"));
+  h->space = kCol;
+  h->first_product = true;
+  h->projected = false;
+  h->solved = false;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status do_mult(tnrsvd_t h, int op) {
+  hipError_t e;
+  {
+    Timed tm(h, 0);
+    e = launch_contract(h->mpos_d, h->cores_d, h->core_mpo_d, h->ncores, h->xr, h->pr,
+                                 h->A, h->X, h->Z, h->dtype, op, h->max_core_out, h->err,
+                                 h->stream);
+  }
+  TRY(dev_check(e, "contract"));
+  if (op == 0 && h->first_product) {
+    Timed tm(h, 5);
+    e = launch_copy_y0(h->mpos_d, h->cores_d, h->core_mpo_d, h->ncores, h->pr, h->Z, h->Y0,
+                       h->dtype, h->max_core_out, h->stream);
+    TRY(dev_check(e, "copy Y0"));
+    h->y0_valid = true;
+  }
+  h->first_product = false;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
+  hipError_t e;
+  {
+    Timed tm(h, 1);
+    e = launch_rl_pass(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->rho, h->Z, h->dtype, h->W,
+                       h->L, h->tau, h->vcap, h->scap, h->err, h->stream);
+  }
+  TRY(dev_check(e, "right-to-left sweep"));
+  Timed tm(h, 2);
+  SweepOpts so;
+  so.eps = h->opts.round_tol;
+  so.rmax = (int)h->opts.max_rank;
+  so.mode = mode;
+  void* out = mode == 0 ? h->X : (void*)h->V;
+  const int odt = mode == 0 ? h->dtype : 0;
+  int* rout = mode == 0 ? h->xr : h->vr;
+  e = launch_lr_pass(h->mpos_d, h->cores_d, h->batch, op, h->rho, rout, h->W, h->tau,
+                     h->scratch, out, odt, h->outs, so, h->vcap, h->scap, h->tcap, h->mcap_s,
+                     h->ucap, h->err, h->stream);
+  return dev_check(e, "left-to-right sweep");
+}
+
+tnrsvd_status read_sigma(tnrsvd_t h, double* sigma) {
+  const int k = h->opts.k;
+  std::vector<double> tmp;
+  for (int b = 0; b < h->batch; ++b) {
+    hipError_t e = hipMemcpyAsync(sigma + (int64_t)b * k, h->outs + h->mh[b].out_off,
+                                  sizeof(double) * k, hipMemcpyDeviceToHost, h->stream);
+    TRY(dev_check(e, "copy sigma"));
+  }
+  int flags[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(flags, h->err, sizeof(flags), hipMemcpyDeviceToHost, h->stream);
+  TRY(dev_check(e, "copy error flags"));
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  if (flags[0] & 2) return fail(TNRSVD_E_SHAPE, "a bond rank exceeded its planned capacity");
+  if (flags[0] & 4) return fail(TNRSVD_E_SHAPE, "a kernel met shapes beyond its planned capacity");
+  return TNRSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tnrsvd_status tnrsvd_mult(tnrsvd_t h, int op) {
+  TRY(check_handle(h));
+  if (op != 0 && op != 1) return fail(TNRSVD_E_INVALID, "op must be 0 (A X) or 1 (A^T X)");
+  if (h->pending >= 0 || h->projected)
+    return fail(TNRSVD_E_STATE, "a product is pending; call tnrsvd_orthogonalize or tnrsvd_solve");
+  if (h->space == kNone || h->solved) {
+    if (op != 0) return fail(TNRSVD_E_STATE, "the first product must be Y = A Omega (op 0)");
+    TRY(load_omega(h));
+  }
+  if (op == 0 && h->space != kCol)
+    return fail(TNRSVD_E_STATE, "Y = A X needs a column-space basis (Omega or an A^T Q result)");
+  if (op == 1 && h->space != kRow)
+    return fail(TNRSVD_E_STATE, "Z = A^T Q needs a row-space basis");
+  TRY(do_mult(h, op));
+  h->pending = op;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_orthogonalize(tnrsvd_t h) {
+  TRY(check_handle(h));
+  if (h->pending < 0) return fail(TNRSVD_E_STATE, "no pending product to orthogonalize");
+  TRY(do_sweep(h, h->pending, 0));
+  h->space = h->pending == 0 ? kRow : kCol;
+  h->pending = -1;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_project(tnrsvd_t h) {
+  TRY(check_handle(h));
+  if (h->pending >= 0) return fail(TNRSVD_E_STATE, "a product is pending");
+  if (h->space != kRow || h->solved)
+    return fail(TNRSVD_E_STATE, "projection needs the row-space basis Q of an orthogonalized A X");
+  TRY(do_mult(h, 1));
+  h->projected = true;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_solve(tnrsvd_t h, double* sigma) {
+  TRY(check_handle(h));
+  if (!h->projected) return fail(TNRSVD_E_STATE, "tnrsvd_project has not run");
+  TRY(do_sweep(h, 1, 1));
+  hipError_t e;
+  {
+    Timed tm(h, 3);
+    e = launch_form_u(h->mpos_d, h->cores_d, h->core_mpo_d, h->ncores, h->xr, h->X,
+                               h->dtype, h->outs, h->U, h->max_core_out, h->err, h->stream);
+  }
+  TRY(dev_check(e, "form U"));
+  h->projected = false;
+  h->solved = true;
+  if (sigma) TRY(read_sigma(h, sigma));
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_run(tnrsvd_t h, double* sigma) {
+  TRY(check_handle(h));
+  h->pending = -1;
+  h->projected = false;
+  h->solved = false;
+  h->space = kNone;
+  TRY(tnrsvd_mult(h, 0));
+  TRY(tnrsvd_orthogonalize(h));
+  for (int t = 0; t < h->opts.q; ++t) {
+    TRY(tnrsvd_mult(h, 1));
+    TRY(tnrsvd_orthogonalize(h));
+    TRY(tnrsvd_mult(h, 0));
+    TRY(tnrsvd_orthogonalize(h));
+  }
+  TRY(tnrsvd_project(h));
+  return tnrsvd_solve(h, sigma);
+}
+
+tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merged) {
+  TRY(check_handle(h));
+  if (b < 0 || b >= h->batch) return fail(TNRSVD_E_INVALID, "MPO index out of range");
+  const MpoDesc& md = h->mh[b];
+  if (d_merged) *d_merged = md.d;
+  if (!host_out) return TNRSVD_OK;
+  std::vector<int> tmp(md.d + 1);
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  TRY(dev_check(hipMemcpy(tmp.data(), h->xr + md.r0, sizeof(int) * (md.d + 1),
+                          hipMemcpyDeviceToHost),
+                "copy ranks"));
+  for (int i = 0; i <= md.d; ++i) host_out[i] = tmp[i];
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_get_factor(tnrsvd_t h, int b, int which, int core, const void** dev_ptr,
+                                int64_t shape[4], int* dtype) {
+  TRY(check_handle(h));
+  if (b < 0 || b >= h->batch) return fail(TNRSVD_E_INVALID, "MPO index out of range");
+  const MpoDesc& md = h->mh[b];
+  if (core < 0 || core >= md.d) return fail(TNRSVD_E_INVALID, "core index out of range");
+  if (which < 0 || which > 3) return fail(TNRSVD_E_INVALID, "which must be 0..3");
+  if ((which == 0 || which == 1) && !h->solved)
+    return fail(TNRSVD_E_STATE, "U and V are available after tnrsvd_solve");
+  if (which == 2 && h->space == kNone) return fail(TNRSVD_E_STATE, "no basis yet");
+  if (which == 3 && !h->y0_valid) return fail(TNRSVD_E_STATE, "no first product yet");
+  const CoreDesc& cd = h->ch[md.c0 + core];
+  std::vector<int> r(md.d + 1);
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  const int* src = which == 3 ? nullptr : (which == 1 ? h->vr : h->xr);
+  if (src)
+    TRY(dev_check(hipMemcpy(r.data(), src + md.r0, sizeof(int) * (md.d + 1),
+                            hipMemcpyDeviceToHost),
+                  "copy ranks"));
+  const size_t esz = h->dtype == 0 ? sizeof(double) : sizeof(float);
+  int64_t n;
+  if (which == 0) {
+    n = cd.I;
+  } else if (which == 1) {
+    n = cd.J;
+  } else if (which == 2) {
+    n = h->space == kRow ? cd.I : cd.J;
+  } else {
+    n = cd.I;
+  }
+  if (which == 3) {
+    shape[0] = cd.RA;
+    shape[1] = cd.I;
+    shape[2] = core == md.d - 1 ? md.K : cd.RA2;
+    shape[3] = 1;
+    *dev_ptr = (const char*)h->Y0 + esz * cd.y0_off;
+    *dtype = h->dtype == 0 ? TNRSVD_F64 : TNRSVD_F32;
+    return TNRSVD_OK;
+  }
+  shape[0] = r[core];
+  shape[1] = n;
+  shape[2] = r[core + 1];
+  shape[3] = 1;
+  if (which == 0) {
+    *dev_ptr = h->U + cd.u_off;
+    *dtype = TNRSVD_F64;
+  } else if (which == 1) {
+    *dev_ptr = h->V + cd.u_off;
+    *dtype = TNRSVD_F64;
+  } else {
+    *dev_ptr = (const char*)h->X + esz * cd.x_off;
+    *dtype = h->dtype == 0 ? TNRSVD_F64 : TNRSVD_F32;
+  }
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_copy_factor(tnrsvd_t h, int b, int which, int core, void* dst) {
+  const void* src = nullptr;
+  int64_t shape[4];
+  int dt = 0;
+  TRY(tnrsvd_get_factor(h, b, which, core, &src, shape, &dt));
+  if (!dst) return fail(TNRSVD_E_INVALID, "null destination");
+  const size_t bytes = (size_t)(shape[0] * shape[1] * shape[2]) *
+                       (dt == TNRSVD_F64 ? sizeof(double) : sizeof(float));
+  TRY(dev_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream),
+                "copy factor"));
+  return dev_check(hipStreamSynchronize(h->stream), "synchronise");
+}
+
+tnrsvd_status tnrsvd_get_omega(tnrsvd_t h, int b, double* host_out, int64_t* n) {
+  TRY(check_handle(h));
+  if (b < 0 || b >= h->batch) return fail(TNRSVD_E_INVALID, "MPO index out of range");
+  const MpoDesc& md = h->mh[b];
+  int64_t cnt = 0;
+  for (int i = 0; i < md.d - 1; ++i) cnt += h->ch[md.c0 + i].J;
+  cnt += (int64_t)h->ch[md.c0 + md.d - 1].J * md.K;
+  if (n) *n = cnt;
+  if (!host_out) return TNRSVD_OK;
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  return dev_check(hipMemcpy(host_out, h->om + md.om_off, sizeof(double) * cnt,
+                             hipMemcpyDeviceToHost),
+                   "copy Omega");
+}
+
+tnrsvd_status tnrsvd_set_omega(tnrsvd_t h, int b, const double* host_in) {
+  TRY(check_handle(h));
+  if (b < 0 || b >= h->batch) return fail(TNRSVD_E_INVALID, "MPO index out of range");
+  if (!host_in) return fail(TNRSVD_E_INVALID, "null Omega");
+  const MpoDesc& md = h->mh[b];
+  int64_t cnt = 0;
+  for (int i = 0; i < md.d - 1; ++i) cnt += h->ch[md.c0 + i].J;
+  cnt += (int64_t)h->ch[md.c0 + md.d - 1].J * md.K;
+  TRY(dev_check(hipMemcpyAsync(h->om + md.om_off, host_in, sizeof(double) * cnt,
+                               hipMemcpyHostToDevice, h->stream),
+                "copy Omega"));
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  h->space = kNone;
+  h->pending = -1;
+  h->projected = false;
+  h->solved = false;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_profile(tnrsvd_t h, int enable) {
+  TRY(check_handle(h));
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  for (auto& v : h->ev_pairs) v.clear();
+  h->ev_used = 0;
+  h->profiling = enable != 0;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_profile_read(tnrsvd_t h, int kernel, double* total_ms, int64_t* launches) {
+  TRY(check_handle(h));
+  if (kernel < 0 || kernel >= kKinds) return fail(TNRSVD_E_INVALID, "kernel kind out of range");
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  double tot = 0.0;
+  for (auto& pr : h->ev_pairs[kernel]) {
+    float ms = 0.f;
+    TRY(dev_check(hipEventElapsedTime(&ms, pr.first, pr.second), "event time"));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)h->ev_pairs[kernel].size();
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_get_product_ranks(tnrsvd_t h, int b, int64_t* P_out, int64_t* rho_out) {
+  TRY(check_handle(h));
+  if (b < 0 || b >= h->batch) return fail(TNRSVD_E_INVALID, "MPO index out of range");
+  const MpoDesc& md = h->mh[b];
+  std::vector<int> tmp(md.d + 1);
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  if (P_out) {
+    TRY(dev_check(hipMemcpy(tmp.data(), h->pr + md.r0, sizeof(int) * (md.d + 1),
+                            hipMemcpyDeviceToHost),
+                  "copy ranks"));
+    for (int i = 0; i <= md.d; ++i) P_out[i] = tmp[i];
+  }
+  if (rho_out) {
+    TRY(dev_check(hipMemcpy(tmp.data(), h->rho + md.r0, sizeof(int) * (md.d + 1),
+                            hipMemcpyDeviceToHost),
+                  "copy ranks"));
+    for (int i = 0; i <= md.d; ++i) rho_out[i] = tmp[i];
+  }
+  return TNRSVD_OK;
+}
+
+}  // extern "C"

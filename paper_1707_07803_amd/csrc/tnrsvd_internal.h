@@ -1,0 +1,98 @@
+// Internal declarations shared by the TNrSVD HIP sources (gfx950 only).
+//
+// Data model (all device resident, one slab per kind, offsets in elements):
+//   A slab    (T)      merged MPO cores of every MPO, (R, I, J, R')
+//   X slab    (T)      current basis cores (r, n, r'), last core (r, n, K)
+//   Z slab    (T)      product cores (P, n, P'), P = R * r, last core (P, n, K)
+//   W slab    (double) per core: the absorbed panel Zt = Z x_3 L, stored as
+//                      Zt^T in column-major (m x P, m = n * rho'), overwritten
+//                      in place by its Householder QR (R above, vectors below)
+//   L slab    (double) per core: the rho x P upper-trapezoidal R of that QR,
+//                      i.e. L^T of the LQ Zt = L Qt
+//   TAU slab  (double) per core: Householder scalars
+//   scratch   (double) per MPO: carried factor T, panel M, Jacobi vectors
+// Dynamic ranks live in device int arrays indexed by MpoDesc::r0 + bond, so a
+// whole solve is enqueued without reading anything back to the host.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tnr {
+
+// Per (MPO, merged core) static plan.
+struct CoreDesc {
+  int I, J;          // row / column mode sizes of the (merged) core
+  int RA, RA2;       // A ranks left / right (RA2 = 1 on the last core)
+  int xcap, xcap2;   // capacity of basis ranks left / right (xcap2 = K last)
+  int64_t a_off;     // A slab
+  int64_t x_off;     // X slab, capacity xcap * max(I,J) * xcap2
+  int64_t z_off;     // Z slab, capacity (RA*xcap) * max(I,J) * (RA2*xcap2)
+  int64_t w_off;     // W slab, capacity max(I,J) * (RA2*xcap2) * (RA*xcap)
+  int64_t l_off;     // L slab, capacity (RA*xcap)^2 (rho <= P)
+  int64_t tau_off;   // TAU slab, capacity RA*xcap
+  int64_t y0_off;    // Y0 slab (first product), capacity RA * I * RA2 * (xcap2 == K ? K : 1)
+  int64_t u_off;     // U / V output slab (double), capacity xcap * max(I,J) * xcap2
+};
+
+// Per MPO static plan.
+struct MpoDesc {
+  int d;             // merged core count
+  int K;             // k + p
+  int c0;            // first CoreDesc of this MPO
+  int r0;            // first bond slot of this MPO in the rank arrays (d + 1 slots)
+  int64_t om_off;    // Omega (double): sum_{i<d-1} J_i + J_{d-1} * K values
+  int64_t s_off;     // scratch (double) of this MPO
+  int64_t s_len;     // scratch length (doubles)
+  int64_t out_off;   // small outputs (double): sigma[K], W[K*K], R_K[K*K]
+  int mcap;          // max panel rows of this MPO (n * rho' over cores)
+  int pcap;          // max product rank of this MPO
+};
+
+// Rank arrays (device, int): one slot per bond, MpoDesc::r0 + i, i = 0..d.
+//   xr  : current basis ranks (xr[0] = 1, xr[d] = K)
+//   pr  : product ranks P_i = R_i * xr_i of the pending product (pr[d] = K)
+//   rho : ranks after the right-to-left LQ sweep (rho[d] = K)
+
+// Sweep options passed by value.
+struct SweepOpts {
+  double eps;        // rounding tolerance
+  int rmax;          // rank cap (0 = none)
+  int mode;          // 0: orthogonalise (QR of the last core), 1: solve (SVD)
+};
+
+constexpr int kSweepThreads = 512;
+constexpr int kMaxK = 256;
+
+}  // namespace tnr
+
+// Launchers implemented in the .hip sources, called from the ABI layer.
+namespace tnr {
+hipError_t launch_merge_pair(const double* Tin, const double* C, double* out, int a, int I1, int J1,
+                             int b, int I2, int J2, int b2, hipStream_t s);
+hipError_t launch_convert_core(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
+                               hipStream_t s);
+hipError_t launch_check_finite(const void* in, int dtype, int64_t n, int* flag, hipStream_t s);
+hipError_t launch_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch, uint64_t seed,
+                        double* om, int64_t max_len, hipStream_t s);
+hipError_t launch_load_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch,
+                             const double* om, int* xr, void* X, int dtype, int max_d,
+                             int64_t max_len, hipStream_t s);
+hipError_t launch_contract(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
+                           int ncores, const int* xr, int* pr, const void* A, const void* X,
+                           void* Z, int dtype, int op, int64_t max_out, int* err, hipStream_t s);
+hipError_t launch_copy_y0(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
+                          int ncores, const int* pr, const void* Z, void* Y0, int dtype,
+                          int64_t max_out, hipStream_t s);
+hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
+                          const int* pr, int* rho, const void* Z, int dtype, double* Wd,
+                          double* L, double* tau, int vcap, int scap, int* err, hipStream_t s);
+hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
+                          const int* rho, int* xr, const double* Wd, const double* tau,
+                          double* scratch, void* Xout, int out_dtype, double* outs, SweepOpts o,
+                          int vcap, int scap, int64_t tcap, int64_t mcap_s, int64_t ucap,
+                          int* err, hipStream_t s);
+hipError_t launch_form_u(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
+                         int ncores, const int* xr, const void* X, int dtype, const double* outs,
+                         double* U, int64_t max_out, int* err, hipStream_t s);
+}  // namespace tnr

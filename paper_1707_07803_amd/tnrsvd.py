@@ -1,0 +1,299 @@
+"""Thin ctypes binding of libtnrsvd.so (the C ABI declared in include/tnrsvd.h).
+
+Argument marshalling only: every step of TNrSVD runs in the HIP kernels of the
+library.  PyTorch provides device memory (input cores, output copies) and the
+stream.  Loading fails loudly when the library has not been built; there is no
+CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtnrsvd.so")
+
+F64, F32, BF16 = 0, 1, 2
+PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16}
+
+# the C function names exported by the library, in header order
+EXPORTS = [
+    "tnrsvd_create", "tnrsvd_mult", "tnrsvd_orthogonalize", "tnrsvd_project",
+    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_get_factor", "tnrsvd_copy_factor",
+    "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
+    "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
+    "tnrsvd_last_error", "tnrsvd_version",
+]
+
+# kernel kinds reported by tnrsvd_profile_read
+KERNELS = {"contract": 0, "rl_sweep": 1, "lr_sweep": 2, "form_u": 3, "load_omega": 4,
+           "copy_y0": 5}
+
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_STATE", -4: "E_NOMEM",
+          -5: "E_DEVICE", -6: "E_NONFINITE"}
+
+
+class TNrSVDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Mpo(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int),
+                ("rank", ctypes.POINTER(ctypes.c_int64)),
+                ("rows", ctypes.POINTER(ctypes.c_int64)),
+                ("cols", ctypes.POINTER(ctypes.c_int64)),
+                ("core", ctypes.POINTER(ctypes.c_void_p)),
+                ("dtype", ctypes.c_int)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("p", ctypes.c_int), ("q", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("precision", ctypes.c_int),
+                ("round_tol", ctypes.c_double), ("max_rank", ctypes.c_int64),
+                ("check_finite", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtnrsvd.so and declare the C signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_1707_07803_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(path)
+    H = ctypes.c_void_p
+    I = ctypes.c_int
+    L.tnrsvd_create.argtypes = [ctypes.POINTER(H), I, ctypes.POINTER(_Mpo), ctypes.POINTER(_Opts)]
+    L.tnrsvd_mult.argtypes = [H, I]
+    L.tnrsvd_orthogonalize.argtypes = [H]
+    L.tnrsvd_project.argtypes = [H]
+    L.tnrsvd_solve.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
+    L.tnrsvd_run.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
+    L.tnrsvd_get_factor.argtypes = [H, I, I, I, ctypes.POINTER(ctypes.c_void_p),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I)]
+    L.tnrsvd_copy_factor.argtypes = [H, I, I, I, ctypes.c_void_p]
+    L.tnrsvd_get_omega.argtypes = [H, I, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64)]
+    L.tnrsvd_set_omega.argtypes = [H, I, ctypes.POINTER(ctypes.c_double)]
+    L.tnrsvd_get_ranks.argtypes = [H, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I)]
+    L.tnrsvd_destroy.argtypes = [H]
+    L.tnrsvd_profile.argtypes = [H, I]
+    L.tnrsvd_profile_read.argtypes = [H, I, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    L.tnrsvd_get_product_ranks.argtypes = [H, I, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int64)]
+    L.tnrsvd_last_error.restype = ctypes.c_char_p
+    L.tnrsvd_last_error.argtypes = []
+    L.tnrsvd_version.restype = ctypes.c_char_p
+    L.tnrsvd_version.argtypes = []
+    for name in EXPORTS:
+        if name not in ("tnrsvd_last_error", "tnrsvd_version"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        msg = _lib.tnrsvd_last_error().decode(errors="replace")
+        raise TNrSVDError(status, msg)
+
+
+def _dptr(a, *, ntype) -> List[float]:
+    return (ntype * len(a))(*a)
+
+
+class TNrSVD:
+    """One handle of the C ABI: a batch of MPOs staged on the current HIP device.
+
+    mpos: list of MPOs, each a list of device tensors (R, I, J, R') in float64
+    or float32 (C-contiguous).  The cores are copied (and the trailing ones
+    merged) inside the library, so the tensors may be freed afterwards.
+    """
+
+    def __init__(self, mpos, k: int, p: int = 0, q: int = 0, seed: int = 0,
+                 precision: str = "f64", round_tol: float = 0.0, max_rank: int = 0,
+                 check_finite: bool = False, stream=None):
+        import torch
+        L = load_library()
+        if isinstance(mpos[0], torch.Tensor):
+            mpos = [mpos]
+        self.k, self.p, self.q = k, p, q
+        self.K = k + p
+        self.batch = len(mpos)
+        self.precision = precision
+        keep = []
+        structs = (_Mpo * self.batch)()
+        for b, cores in enumerate(mpos):
+            ds = {c.dtype for c in cores}
+            if len(ds) != 1 or next(iter(ds)) not in (torch.float64, torch.float32):
+                raise TNrSVDError(-1, "cores must all be float64 or all float32")
+            for c in cores:
+                if not c.is_cuda or not c.is_contiguous() or c.dim() != 4:
+                    raise TNrSVDError(-1, "cores must be contiguous 4-way device tensors")
+            d = len(cores)
+            rank = [int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores]
+            for i in range(1, d):
+                if int(cores[i].shape[0]) != rank[i]:
+                    raise TNrSVDError(-2, f"rank mismatch between cores {i - 1} and {i}")
+            rows = [int(c.shape[1]) for c in cores]
+            cols = [int(c.shape[2]) for c in cores]
+            ra = (ctypes.c_int64 * (d + 1))(*rank)
+            ro = (ctypes.c_int64 * d)(*rows)
+            co = (ctypes.c_int64 * d)(*cols)
+            pt = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+            keep += [ra, ro, co, pt, cores]
+            structs[b].d = d
+            structs[b].rank = ra
+            structs[b].rows = ro
+            structs[b].cols = co
+            structs[b].core = pt
+            structs[b].dtype = F64 if cores[0].dtype == torch.float64 else F32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        opts = _Opts(k=k, p=p, q=q, seed=seed, precision=PRECISIONS[precision],
+                     round_tol=float(round_tol), max_rank=int(max_rank),
+                     check_finite=1 if check_finite else 0,
+                     stream=ctypes.c_void_p(stream.cuda_stream))
+        h = ctypes.c_void_p()
+        _check(L.tnrsvd_create(ctypes.byref(h), self.batch, structs, ctypes.byref(opts)))
+        self._h = h
+        self._lib = L
+
+    # -- Algorithm 5.4 / 5.1 steps ------------------------------------------
+    def mult(self, op: int):
+        _check(self._lib.tnrsvd_mult(self._h, op))
+
+    def orthogonalize(self):
+        _check(self._lib.tnrsvd_orthogonalize(self._h))
+
+    def project(self):
+        _check(self._lib.tnrsvd_project(self._h))
+
+    def solve(self, want_sigma: bool = True) -> Optional[np.ndarray]:
+        if not want_sigma:
+            _check(self._lib.tnrsvd_solve(self._h, None))
+            return None
+        out = np.zeros(self.batch * self.k, dtype=np.float64)
+        _check(self._lib.tnrsvd_solve(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(self.batch, self.k)
+
+    def run(self, want_sigma: bool = True) -> Optional[np.ndarray]:
+        if not want_sigma:
+            _check(self._lib.tnrsvd_run(self._h, None))
+            return None
+        out = np.zeros(self.batch * self.k, dtype=np.float64)
+        _check(self._lib.tnrsvd_run(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(self.batch, self.k)
+
+    # -- getters --------------------------------------------------------------
+    def ranks(self, b: int = 0) -> List[int]:
+        dm = ctypes.c_int()
+        _check(self._lib.tnrsvd_get_ranks(self._h, b, None, ctypes.byref(dm)))
+        buf = (ctypes.c_int64 * (dm.value + 1))()
+        _check(self._lib.tnrsvd_get_ranks(self._h, b, buf, ctypes.byref(dm)))
+        return list(buf)
+
+    def d_merged(self, b: int = 0) -> int:
+        dm = ctypes.c_int()
+        _check(self._lib.tnrsvd_get_ranks(self._h, b, None, ctypes.byref(dm)))
+        return dm.value
+
+    def factor(self, which: int, b: int = 0):
+        """Copies of the cores of U (0), V (1), the current basis (2) or Y = A Omega (3)."""
+        import torch
+        out = []
+        for core in range(self.d_merged(b)):
+            ptr = ctypes.c_void_p()
+            shape = (ctypes.c_int64 * 4)()
+            dt = ctypes.c_int()
+            _check(self._lib.tnrsvd_get_factor(self._h, b, which, core, ctypes.byref(ptr), shape,
+                                               ctypes.byref(dt)))
+            t = torch.empty((shape[0], shape[1], shape[2]),
+                            dtype=torch.float64 if dt.value == F64 else torch.float32,
+                            device="cuda")
+            _check(self._lib.tnrsvd_copy_factor(self._h, b, which, core, ctypes.c_void_p(t.data_ptr())))
+            out.append(t)
+        return out
+
+    def omega(self, b: int = 0) -> np.ndarray:
+        n = ctypes.c_int64()
+        _check(self._lib.tnrsvd_get_omega(self._h, b, None, ctypes.byref(n)))
+        buf = np.zeros(n.value, dtype=np.float64)
+        _check(self._lib.tnrsvd_get_omega(self._h, b, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          ctypes.byref(n)))
+        return buf
+
+    def set_omega(self, values, b: int = 0):
+        buf = np.ascontiguousarray(values, dtype=np.float64)
+        n = ctypes.c_int64()
+        _check(self._lib.tnrsvd_get_omega(self._h, b, None, ctypes.byref(n)))
+        if buf.size != n.value:
+            raise TNrSVDError(-2, f"Omega needs {n.value} values, got {buf.size}")
+        _check(self._lib.tnrsvd_set_omega(self._h, b, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def product_ranks(self, b: int = 0):
+        """(P_0..P_d, rho_0..rho_d) of the last product and of its right-to-left sweep."""
+        d = self.d_merged(b)
+        P = (ctypes.c_int64 * (d + 1))()
+        R = (ctypes.c_int64 * (d + 1))()
+        _check(self._lib.tnrsvd_get_product_ranks(self._h, b, P, R))
+        return list(P), list(R)
+
+    def profile(self, enable: bool = True):
+        _check(self._lib.tnrsvd_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, kernel: str):
+        """(total ms, launches) of one kernel kind since profiling was enabled."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self._lib.tnrsvd_profile_read(self._h, KERNELS[kernel], ctypes.byref(ms),
+                                             ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tnrsvd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def omega_flat(vecs: Sequence[np.ndarray], last: np.ndarray) -> np.ndarray:
+    """Concatenate Omega's factors in the order tnrsvd_set_omega expects."""
+    return np.concatenate([np.ravel(v) for v in vecs] + [np.ravel(np.asarray(last))])
+
+
+def solve(cores, k: int, p: int = 0, q: int = 0, seed: int = 0, precision: str = "f64",
+          round_tol: float = 0.0, max_rank: int = 0, omega=None):
+    """One TNrSVD solve: returns (sigma[k], U cores, V cores) with U, V in FP64."""
+    with TNrSVD(cores, k, p, q, seed, precision, round_tol, max_rank) as h:
+        if omega is not None:
+            h.set_omega(omega)
+        sig = h.run()[0]
+        U = h.factor(0)
+        V = h.factor(1)
+    U[-1] = U[-1][:, :, :k].contiguous()
+    V[-1] = V[-1][:, :, :k].contiguous()
+    return sig, U, V
