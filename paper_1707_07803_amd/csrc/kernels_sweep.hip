@@ -22,16 +22,36 @@ namespace {
 constexpr int NT = kSweepThreads;
 constexpr int NW = NT / 64;
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// DPP move of a double (both 32-bit halves), zero where the source lane is invalid.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xf, true);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xf, true);
+  return __hiloint2double(h2, l2);
 }
+
+// Sum over the 64 lanes of a wave, returned to every lane: shift-adds within
+// each row of 16 lanes, row broadcasts 15 and 31 to fold the four rows into
+// lane 63, then a read of lane 63.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0x111>(v);          // row_shr:1
+  v += dpp_d<0x112>(v);          // row_shr:2
+  v += dpp_d<0x114>(v);          // row_shr:4
+  v += dpp_d<0x118>(v);          // row_shr:8
+  v += dpp_d<0x142, 0xa>(v);     // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);     // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Sum over the workgroup; every thread receives the total.  `red` holds NW doubles.
 __device__ double block_sum(double v, double* red) {
   v = wave_sum(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = wave_id();
   __syncthreads();
   if (lane == 0) red[w] = v;
   __syncthreads();
@@ -47,7 +67,7 @@ __device__ double block_sum(double v, double* red) {
 // Each reflector maps its column x to +||x|| e_1, using Parlett's form of the
 // leading entry when x_1 > 0 so that no cancellation occurs.
 __device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   const int kmax = m < n ? m : n;
   for (int j = 0; j < kmax; ++j) {
     double* col = X + (int64_t)j * m;
@@ -107,7 +127,7 @@ __device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double
 // reflectors stored as by wg_geqr2 in V (ld m).  One wave per column of Y;
 // columns are independent, so no barrier is needed between reflectors.
 __device__ void wg_apply_q(const double* V, const double* tau, int m, int k, double* Y, int s) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = wave_id();
   for (int c = w; c < s; c += NW) {
     double* yc = Y + (int64_t)c * m;
     for (int j = k - 1; j >= 0; --j) {
@@ -137,14 +157,17 @@ __device__ void wg_apply_q(const double* V, const double* tau, int m, int k, dou
 // round-robin (circle) ordering so a round's pairs are disjoint and each is
 // handled by one wave.  Returns the number of sweeps.
 __device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* flag) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   for (int t = tid; t < nv * nv; t += NT) U[t] = ((t % nv) == (t / nv)) ? 1.0 : 0.0;
   __syncthreads();
   if (nv < 2) return 0;
-  const double tol = 2.220446049250313e-16 * sqrt((double)(len > 4 ? len : 4));
+  // Convergence threshold len * eps on |<b_p,b_q>| / (|b_p| |b_q|): above the
+  // rounding level of the computed inner products, so a converged pair is
+  // never rotated again and the sweep count stays small.
+  const double tol = 2.220446049250313e-16 * (double)(len > 16 ? len : 16);
   const int nn = nv + (nv & 1);
   int sweep = 0;
-  for (; sweep < 80; ++sweep) {
+  for (; sweep < 40; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();
     for (int rnd = 0; rnd < nn - 1; ++rnd) {
@@ -205,7 +228,7 @@ __device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* fl
 // Norms of the nv vectors, then a stable descending sort: sig[pos], perm[pos].
 __device__ void wg_norms_sorted(const double* B, int nv, int len, int ldb, double* sig, int* perm,
                                 double* nrm) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   for (int k = w; k < nv; k += NW) {
     const double* bk = B + (int64_t)k * ldb;
     double part = 0.0;
@@ -240,54 +263,380 @@ __device__ inline double sign_of_max(const double* x, int n, int stride) {
   return val < 0.0 ? -1.0 : 1.0;
 }
 
-struct LdsLayout {
-  double* v;      // Householder vector, vcap
-  double* red;    // NW
-  double* sig;    // scap
-  double* nrm;    // scap
-  double* sgn;    // scap
-  int* perm;      // scap
-  int* ibuf;      // 8 ints
-};
+// ---------------------------------------------------------------------------
+// Register-resident Householder QR (panels up to 256 x 128).
+// Layout: lane l of wave w is in 16-lane row g = l / 16 at position h = l % 16;
+// o = 4 w + g (0..63) owns columns o and o + 64 (slots u = 0, 1) and lane h
+// holds rows h + 16 t (t < 16) of them: x[t][u] = X[h + 16 t][o + 64 u].
+// A column's inner product is then a butterfly over one DPP row (4 steps,
+// every lane gets the sum), the four rows of a wave work on four columns at
+// once, and columns are dealt cyclically so the shrinking trailing matrix
+// stays balanced.  One barrier per column step: the owner row builds the
+// reflector and publishes it in a double-buffered LDS vector.
+// ---------------------------------------------------------------------------
+constexpr int QMR = 16;                // row slots    -> 256 rows
+constexpr int QNC = 2;                 // column slots -> 128 columns
+constexpr int QROWS = 16 * QMR;
+constexpr int QCOLS = 64 * QNC;
+constexpr int ARENA = 19456;           // doubles of static LDS per workgroup (152 KiB)
 
-__device__ inline LdsLayout carve(double* smem, int vcap, int scap) {
-  LdsLayout L;
-  L.v = smem;
-  L.red = L.v + vcap;
-  L.sig = L.red + NW;
-  L.nrm = L.sig + scap;
-  L.sgn = L.nrm + scap;
-  L.perm = (int*)(L.sgn + scap);
-  L.ibuf = L.perm + scap;
-  return L;
+// Sum over the 16 lanes of a DPP row; every lane of the row receives it.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  v += dpp_d<0x140>(v);   // row_mirror
+  return v;
+}
+
+// Owner-row part of one column step: build the reflector of column j (held in
+// slot UJ), write it into x and into the LDS vector v, and publish tau.
+template <int UJ>
+__device__ __forceinline__ void reg_reflector(double (&x)[QMR][QNC], int j, int m, int h,
+                                              bool mine, double* v, double* tbuf,
+                                              double* tau_g) {
+  double s2 = 0.0, al = 0.0;
+#pragma unroll
+  for (int t = 0; t < QMR; ++t) {
+    const int r = h + 16 * t;
+    const double c = x[t][UJ];
+    const double cm = (r > j && r < m) ? c : 0.0;
+    s2 += cm * cm;
+    al += (r == j) ? c : 0.0;
+  }
+  s2 = row16_sum(s2);
+  al = row16_sum(al);
+  if (!mine) return;
+  double tj, beta, inv_v0;
+  if (s2 == 0.0) {
+    inv_v0 = 0.0;
+    if (al >= 0.0) {
+      tj = 0.0;
+      beta = al;
+    } else {
+      tj = 2.0;
+      beta = -al;
+    }
+  } else {
+    const double nrm = sqrt(al * al + s2);
+    const double v0 = (al <= 0.0) ? al - nrm : -s2 / (al + nrm);
+    tj = 2.0 * v0 * v0 / (s2 + v0 * v0);
+    beta = nrm;
+    inv_v0 = 1.0 / v0;
+  }
+  // branch-free: every lane writes all its rows of v (zero above the pivot)
+#pragma unroll
+  for (int t = 0; t < QMR; ++t) {
+    const int r = h + 16 * t;
+    const double c = x[t][UJ];
+    const bool below = r > j && r < m;
+    const double vv = below ? c * inv_v0 : (r == j ? 1.0 : 0.0);
+    v[r] = vv;
+    x[t][UJ] = below ? vv : (r == j ? beta : c);
+  }
+  if (h == 0) {
+    *tbuf = tj;
+    *tau_g = tj;
+  }
+}
+
+__device__ void reg_geqr(double (&x)[QMR][QNC], int m, int n, double* vb, double* tb,
+                         double* tau_g) {
+  const int lane = threadIdx.x & 63, h = lane & 15, g = lane >> 4;
+  const int w = wave_id();
+  const int o = 4 * w + g;
+  const int kmax = m < n ? m : n;
+  for (int j = 0; j < kmax; ++j) {
+    const int buf = j & 1;
+    double* v = vb + buf * QROWS;
+    const int oj = j & 63;
+    if (w == (oj >> 2)) {
+      const bool mine = g == (oj & 3);
+      if (j < 64)
+        reg_reflector<0>(x, j, m, h, mine, v, tb + buf, tau_g + j);
+      else
+        reg_reflector<1>(x, j, m, h, mine, v, tb + buf, tau_g + j);
+    }
+    __syncthreads();
+    const double tj = tb[buf];
+    if (tj != 0.0) {
+      // Branch-free update: all 16 reads of v are issued together (rows above
+      // the pivot hold zeros there), inactive columns get a zero coefficient.
+      double vr[QMR];
+#pragma unroll
+      for (int t = 0; t < QMR; ++t) vr[t] = v[h + 16 * t];
+#pragma unroll
+      for (int u = 0; u < QNC; ++u) {
+        // some column of this wave in slot u lies right of j (wave uniform)
+        if (4 * w + 3 + 64 * u > j && 4 * w + 64 * u < n) {
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < QMR; ++t) acc += vr[t] * x[t][u];
+          acc = row16_sum(acc);
+          const int c = o + 64 * u;
+          const double f = (c > j && c < n) ? tj * acc : 0.0;
+#pragma unroll
+          for (int t = 0; t < QMR; ++t) x[t][u] -= f * vr[t];
+        }
+      }
+    }
+  }
+}
+
+// Store the factorised register panel: reflector entries below the diagonal
+// into V (column-major, ld ldv) and the kmax x n upper-trapezoidal R (row-major).
+__device__ void reg_store(const double (&x)[QMR][QNC], int m, int n, double* V, int ldv,
+                          double* R) {
+  const int lane = threadIdx.x & 63, h = lane & 15, g = lane >> 4;
+  const int o = 4 * wave_id() + g;
+  const int kmax = m < n ? m : n;
+#pragma unroll
+  for (int t = 0; t < QMR; ++t) {
+    const int r = h + 16 * t;
+#pragma unroll
+    for (int u = 0; u < QNC; ++u) {
+      const int c = o + 64 * u;
+      if (r < m && c < n) {
+        if (c < kmax && r > c) V[(int64_t)c * ldv + r] = x[t][u];
+        if (r < kmax) R[(int64_t)r * n + c] = (c >= r) ? x[t][u] : 0.0;
+      }
+    }
+  }
+}
+
+// Rows [r0, r0 + mr) of the last core's panel (no absorption):
+// x[t][u] = Z[p][r0 + r], the panel row being (y, kappa) of an m-row panel.
+template <typename T>
+__device__ void reg_load_plain(double (&x)[QMR][QNC], const T* __restrict__ Zc, int m, int P,
+                               int r0 = 0, int mr = -1) {
+  const int lane = threadIdx.x & 63, h = lane & 15, g = lane >> 4;
+  const int o = 4 * wave_id() + g;
+  if (mr < 0) mr = m;
+#pragma unroll
+  for (int t = 0; t < QMR; ++t) {
+    const int r = h + 16 * t;
+#pragma unroll
+    for (int u = 0; u < QNC; ++u) {
+      const int c = o + 64 * u;
+      x[t][u] = (r < mr && c < P) ? (double)Zc[(int64_t)c * m + r0 + r] : 0.0;
+    }
+  }
+}
+
+// Stack two upper-trapezoidal factors: rows [0, ka) from Ra, [ka, ka + kb) from Rb
+// (both row-major with n columns).
+__device__ void reg_load_stack(double (&x)[QMR][QNC], const double* Ra, int ka, const double* Rb,
+                               int kb, int n) {
+  const int lane = threadIdx.x & 63, h = lane & 15, g = lane >> 4;
+  const int o = 4 * wave_id() + g;
+#pragma unroll
+  for (int t = 0; t < QMR; ++t) {
+    const int r = h + 16 * t;
+#pragma unroll
+    for (int u = 0; u < QNC; ++u) {
+      const int c = o + 64 * u;
+      double val = 0.0;
+      if (c < n) {
+        if (r < ka)
+          val = Ra[(int64_t)r * n + c];
+        else if (r < ka + kb)
+          val = Rb[(int64_t)(r - ka) * n + c];
+      }
+      x[t][u] = val;
+    }
+  }
+}
+
+// Absorbed panel Zt^T = (Z x_3 L)^T in the padded layout: slot t holds
+// y = t / SPY and f = h + 16 (t % SPY) (each y block padded to 16 SPY rows):
+//   x[t][u] = sum_{q >= f} R[f][q] Z[p_u][y][q],  L = R^T (rho x Pn, row-major),
+// p_u = o + 64 u.  Chunks of q are staged in LDS as RT[q][f] and ZL[q][y][p].
+template <typename T, int SPY>
+__device__ void reg_absorb(double (&x)[QMR][QNC], const T* __restrict__ Zc, int P, int n, int Pn,
+                           const double* __restrict__ Rn, int rho, double* stage, int stage_cap) {
+  const int tid = threadIdx.x, lane = tid & 63, h = lane & 15, g = lane >> 4;
+  const int o = 4 * wave_id() + g;
+  constexpr int FP = 16 * SPY;
+  constexpr int NY = QMR / SPY;
+#pragma unroll
+  for (int t = 0; t < QMR; ++t)
+#pragma unroll
+    for (int u = 0; u < QNC; ++u) x[t][u] = 0.0;
+  const int per_q = FP + n * QCOLS;
+  int QC = stage_cap / per_q;
+  if (QC > 32) QC = 32;
+  double* RT = stage;
+  double* ZL = stage + QC * FP;
+  for (int q0 = 0; q0 < Pn; q0 += QC) {
+    const int qc = (Pn - q0) < QC ? (Pn - q0) : QC;
+    __syncthreads();
+    for (int e = tid; e < FP * qc; e += NT) {
+      const int f = e / qc, qq = e % qc;
+      const int q = q0 + qq;
+      RT[qq * FP + f] = (f < rho && q >= f) ? Rn[(int64_t)f * Pn + q] : 0.0;
+    }
+    for (int e = tid; e < QCOLS * n * qc; e += NT) {
+      const int qq = e % qc;
+      const int py = e / qc;
+      const int y = py % n, p = py / n;
+      ZL[(qq * n + y) * QCOLS + p] =
+          (p < P) ? (double)Zc[((int64_t)p * n + y) * Pn + q0 + qq] : 0.0;
+    }
+    __syncthreads();
+    for (int qq = 0; qq < qc; ++qq) {
+      double rv[SPY];
+#pragma unroll
+      for (int s = 0; s < SPY; ++s) rv[s] = RT[qq * FP + h + 16 * s];
+#pragma unroll
+      for (int y = 0; y < NY; ++y) {
+        if (y < n) {
+          const double* zp = ZL + (qq * n + y) * QCOLS + o;
+          double z[QNC];
+#pragma unroll
+          for (int u = 0; u < QNC; ++u) z[u] = zp[64 * u];
+#pragma unroll
+          for (int s = 0; s < SPY; ++s)
+#pragma unroll
+            for (int u = 0; u < QNC; ++u) x[y * SPY + s][u] += rv[s] * z[u];
+        }
+      }
+    }
+  }
+  __syncthreads();
 }
 
 template <typename T>
+__device__ void reg_absorb_dispatch(int spy, double (&x)[QMR][QNC], const T* Zc, int P, int n,
+                                    int Pn, const double* Rn, int rho, double* stage, int cap) {
+  switch (spy) {
+    case 1: reg_absorb<T, 1>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
+    case 2: reg_absorb<T, 2>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
+    case 4: reg_absorb<T, 4>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
+    case 8: reg_absorb<T, 8>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
+    default: reg_absorb<T, 16>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
+  }
+}
+
+// Flat-tree TSQR of a tall panel (m rows > 256, n <= 128 columns), run by the
+// right-to-left pass as a sequence of register QR jobs: leaf QRs of consecutive
+// 256-row chunks, each leaf's R merged into the running R by a QR of the two
+// stacked triangles.  Workspace layout (in the core's W slab):
+//   leaf c reflectors   W + c * 256 * n            (column-major, ld = rows of leaf c)
+//   merge c reflectors  W + (nc + c) * 256 * n     (ld = rows of merge c), c >= 1
+//   Racc, Rtmp          W + 2 nc 256 n, + n * n     (row-major)
+//   taus                W + (2 nc 256 + 2 n) n: leaf c at + c n, merge c at + (nc + c) n
+// The final R goes to the L slab; tsqr_apply replays the tree in the
+// left-to-right pass.
+
+// ---------------------------------------------------------------------------
+// Right-to-left pass: absorb + QR of every core, one workgroup per MPO.
+// ldm[i] records the row stride of one y block of core i's panel (rho_{i+1},
+// or its multiple of 64 when the padded register layout was used).
+// ---------------------------------------------------------------------------
+template <typename T>
 __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int op,
-                                                const int* pr, int* rho, const T* __restrict__ Z,
-                                                double* Wd, double* L, double* tau, int vcap,
-                                                int scap, int* err) {
-  extern __shared__ double smem[];
-  LdsLayout S = carve(smem, vcap, scap);
+                                                const int* pr, int* rho, int* ldm,
+                                                const T* __restrict__ Z, double* Wd, double* L,
+                                                double* tau, int* err) {
+  __shared__ double arena[ARENA];
+  double* vb = arena;                 // 2 * QROWS (register path) or m (global path)
+  double* tb = arena + ARENA - 32;    // 2 doubles
+  double* red = arena + ARENA - 16;   // NW doubles
   const int tid = threadIdx.x;
   const MpoDesc md = mpos[blockIdx.x];
   const int d = md.d;
   if (tid == 0) rho[md.r0 + d] = md.K;
   int rnext = md.K;
+  double x[QMR][QNC];   // the register panel shared by every register path
   for (int i = d - 1; i >= 0; --i) {
     const CoreDesc cd = cores[md.c0 + i];
     const int n = op == 0 ? cd.I : cd.J;
     const int P = pr[md.r0 + i];
     const int Pn = pr[md.r0 + i + 1];
     const int m = n * rnext;
-    // capacity guard (every value here is block uniform)
     if (P < 1 || P > cd.RA * cd.xcap || Pn < 1 || Pn > cd.RA2 * cd.xcap2 || rnext > Pn ||
-        m > vcap) {
+        m > ARENA - 64) {
       if (tid == 0) atomicOr(err, 4);
       return;
     }
     double* Xt = Wd + cd.w_off;
     const T* Zc = Z + cd.z_off;
+    const double* Rn = (i < d - 1) ? L + cores[md.c0 + i + 1].l_off : nullptr;
+    int spy = 1;   // 16-row slots per y block, a power of two
+    while (16 * spy < rnext) spy *= 2;
+    const bool reg_abs = i > 0 && i < d - 1 && P <= QCOLS && n * spy <= QMR && P <= m;
+    const bool reg_plain = i > 0 && i == d - 1 && P <= QCOLS && m <= QROWS;
+    const bool tsqr = i > 0 && i == d - 1 && P <= QCOLS && m > QROWS &&
+                      m <= 16 * QROWS;
+    if (reg_abs || reg_plain || tsqr) {
+      // Every register path is a sequence of jobs "load panel, QR, store"
+      // with a single QR call site: one job for an absorbed or plain panel,
+      // and for a tall panel the TSQR leaves and merges (leaf 0, leaf 1,
+      // merge 1, leaf 2, merge 2, ...).
+      const int nc = tsqr ? (m + QROWS - 1) / QROWS : 1;
+      const int njobs = tsqr ? 2 * nc - 1 : 1;
+      double* ws_tau = Xt + (int64_t)(2 * nc * QROWS + 2 * P) * P;
+      double* Racc = Xt + (int64_t)2 * nc * QROWS * P;
+      double* Rtmp = Racc + (int64_t)P * P;
+      int kacc = 0, kleaf = 0;
+      for (int job = 0; job < njobs; ++job) {
+        // job -> (leaf c) or (merge c): leaf 0 is job 0, then leaf c = job 2c - 1, merge c = job 2c
+        const bool merge = tsqr && job > 0 && (job % 2 == 0);
+        const int c = tsqr ? (job + 1) / 2 : 0;
+        int mrows, ldv;
+        double* Vdst;
+        double* Rdst;
+        double* taud;
+        if (!tsqr) {
+          if (reg_abs) {
+            reg_absorb_dispatch<T>(spy, x, Zc, P, n, Pn, Rn, rnext, arena + 2 * QROWS,
+                                   ARENA - 2 * QROWS - 64);
+            mrows = n * spy * 16;
+          } else {
+            reg_load_plain<T>(x, Zc, m, P);
+            mrows = m;
+          }
+          ldv = mrows;
+          Vdst = Xt;
+          Rdst = L + cd.l_off;
+          taud = tau + cd.tau_off;
+        } else if (!merge) {
+          const int r0 = c * QROWS;
+          mrows = (m - r0) < QROWS ? (m - r0) : QROWS;
+          reg_load_plain<T>(x, Zc, m, P, r0, mrows);
+          ldv = mrows;
+          Vdst = Xt + (int64_t)c * QROWS * P;
+          Rdst = c == 0 ? Racc : Rtmp;
+          taud = ws_tau + (int64_t)c * P;
+          kleaf = mrows < P ? mrows : P;
+        } else {
+          mrows = kacc + kleaf;
+          reg_load_stack(x, Racc, kacc, Rtmp, kleaf, P);
+          __syncthreads();
+          ldv = mrows;
+          Vdst = Xt + (int64_t)(nc + c) * QROWS * P;
+          Rdst = (job == njobs - 1) ? L + cd.l_off : Racc;
+          taud = ws_tau + (int64_t)(nc + c) * P;
+        }
+        reg_geqr(x, mrows, P, vb, tb, taud);
+        reg_store(x, mrows, P, Vdst, ldv, Rdst);
+        __syncthreads();
+        if (tsqr) {
+          if (job == 0)
+            kacc = kleaf;
+          else if (merge)
+            kacc = mrows < P ? mrows : P;
+        }
+      }
+      const int k = m < P ? m : P;
+      if (tid == 0) {
+        ldm[md.r0 + i] = tsqr ? -nc : (reg_abs ? spy * 16 : rnext);
+        rho[md.r0 + i] = k;
+      }
+      rnext = k;
+      __syncthreads();
+      continue;
+    }
     const int64_t tot = (int64_t)m * P;
     if (i == d - 1) {
       // last core: Zt = Z (the K leg is external), stored transposed
@@ -297,7 +646,6 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
       }
     } else {
       // Zt^T[(y, f), p] = sum_{q >= f} Z[p, y, q] R_{i+1}[f, q]   (L_{i+1} = R_{i+1}^T)
-      const double* Rn = L + cores[md.c0 + i + 1].l_off;
       for (int64_t o = tid; o < tot; o += NT) {
         const int p = (int)(o / m), jj = (int)(o % m);
         const int y = jj / rnext, f = jj % rnext;
@@ -308,9 +656,10 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
         Xt[o] = acc;
       }
     }
+    if (tid == 0) ldm[md.r0 + i] = rnext;
     __syncthreads();
     if (i == 0) break;
-    wg_geqr2(Xt, m, P, tau + cd.tau_off, S.v, S.red);
+    wg_geqr2(Xt, m, P, tau + cd.tau_off, vb, red);
     const int k = m < P ? m : P;
     double* Ro = L + cd.l_off;
     for (int64_t o = tid; o < (int64_t)k * P; o += NT) {
@@ -323,7 +672,197 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
   }
 }
 
-// Scratch layout of one MPO (doubles): T buffer, M panel, U / C / E buffers.
+// Cooperative copy of n doubles from global memory into LDS with eight loads
+// in flight per thread before the first store (hides L2 latency).
+__device__ __forceinline__ void stage_copy(double* dst, const double* __restrict__ src, int n) {
+  const int tid = threadIdx.x;
+  int e = tid;
+  for (; e + 7 * NT < n; e += 8 * NT) {
+    double a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = src[e + q * NT];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[e + q * NT] = a[q];
+  }
+  for (; e < n; e += NT) dst[e] = src[e];
+}
+
+// Y <- H_0 ... H_{k-1} Y with the reflectors streamed through LDS in chunks
+// (V in global memory, column-major ld m; Y column-major m x s, any memory).
+__device__ void wg_apply_q_staged(const double* __restrict__ V, const double* __restrict__ tau,
+                                  int m, int k, double* Y, int s, double* stage, int cap,
+                                  double* tstage) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = wave_id();
+  int CH = cap / m;
+  if (CH > 64) CH = 64;
+  if (CH < 1) CH = 1;
+  for (int hi = k; hi > 0; hi -= CH) {
+    const int lo = hi - CH > 0 ? hi - CH : 0;
+    const int cnt = hi - lo;
+    __syncthreads();
+    stage_copy(stage, V + (int64_t)lo * m, cnt * m);
+    for (int e = tid; e < cnt; e += NT) tstage[e] = tau[lo + e];
+    __syncthreads();
+    for (int c = w; c < s; c += NW) {
+      double* yc = Y + (int64_t)c * m;
+      for (int j = hi - 1; j >= lo; --j) {
+        const double tj = tstage[j - lo];
+        if (tj == 0.0) continue;
+        const double* vj = stage + (int64_t)(j - lo) * m;
+        const int r0 = j & ~63;
+        double part = 0.0;
+        for (int r = r0 + lane; r < m; r += 64) {
+          if (r == j) part += yc[r];
+          else if (r > j) part += vj[r] * yc[r];
+        }
+        part = wave_sum(part);
+        const double f = tj * part;
+        for (int r = r0 + lane; r < m; r += 64) {
+          if (r == j) yc[r] -= f;
+          else if (r > j) yc[r] -= f * vj[r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Y <- H_0 ... H_{k-1} Y with each column of Y held in the registers of one
+// wave (row r in lane r % 64, slot r / 64; m <= 64 * MT) and the reflectors
+// staged through LDS in chunks.  Rows keep their lane, so the only cross-lane
+// traffic is the wave reduction of each reflector's inner product.
+template <int MT>
+__device__ void wg_apply_q_reg(const double* __restrict__ V, const double* __restrict__ tau, int m,
+                               int k, double* Y, int s, double* stage, int cap, double* tstage,
+                               int ldy = -1) {
+  if (ldy < 0) ldy = m;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = wave_id();
+  int CH = cap / m;
+  if (CH > 64) CH = 64;
+  if (CH < 1) CH = 1;
+  for (int cb = 0; cb < s; cb += NW) {
+    const int c = cb + w;
+    const bool have = c < s;
+    double y[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const int r = lane + 64 * t;
+      y[t] = (have && r < m) ? Y[(int64_t)c * ldy + r] : 0.0;
+    }
+    for (int hi = k; hi > 0; hi -= CH) {
+      const int lo = hi - CH > 0 ? hi - CH : 0;
+      const int cnt = hi - lo;
+      __syncthreads();
+      stage_copy(stage, V + (int64_t)lo * m, cnt * m);
+      for (int e = tid; e < cnt; e += NT) tstage[e] = tau[lo + e];
+      __syncthreads();
+      if (have) {
+        for (int j = hi - 1; j >= lo; --j) {
+          const double tj = tstage[j - lo];
+          if (tj == 0.0) continue;
+          const double* vj = stage + (int64_t)(j - lo) * m;
+          // two passes over the staged vector (re-read from LDS) keep the
+          // register footprint at one column of Y
+          double part = 0.0;
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            const int r = lane + 64 * t;
+            const double raw = vj[r < m ? r : m - 1];   // in-bounds read, masked below
+            part += ((r > j && r < m) ? raw : (r == j ? 1.0 : 0.0)) * y[t];
+          }
+          part = wave_sum(part);
+          const double f = tj * part;
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            const int r = lane + 64 * t;
+            const double raw = vj[r < m ? r : m - 1];
+            y[t] -= f * ((r > j && r < m) ? raw : (r == j ? 1.0 : 0.0));
+          }
+        }
+      }
+    }
+    if (have) {
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const int r = lane + 64 * t;
+        if (r < m) Y[(int64_t)c * ldy + r] = y[t];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// M^T = Q_thin [T^T; 0] for a panel factorised by tsqr_panel (n columns, m rows,
+// nc chunks): the merges are applied in reverse, each splitting its output
+// between the running top block and the input of one leaf; then every leaf
+// applies its reflectors to its block of rows.  On entry Y (m x s,
+// column-major) holds [T^T; 0]; zbuf holds 2 n s doubles.
+__device__ void tsqr_apply(const double* ws, int m, int n, double* Y, int s, int nc,
+                           double* stage, int cap, double* tstage, double* zbuf) {
+  const int tid = threadIdx.x;
+  const double* ws_tau = ws + (int64_t)(2 * nc * QROWS + 2 * n) * n;
+  // k_acc after each leaf / merge, recomputed from the shapes
+  int kacc[16];
+  int kleaf[16];
+  for (int c = 0; c < nc; ++c) {
+    const int mc = (m - c * QROWS) < QROWS ? (m - c * QROWS) : QROWS;
+    kleaf[c] = mc < n ? mc : n;
+    if (c == 0)
+      kacc[0] = kleaf[0];
+    else
+      kacc[c] = (kacc[c - 1] + kleaf[c]) < n ? (kacc[c - 1] + kleaf[c]) : n;
+  }
+  // running top block: the first kacc[nc-1] rows of Y (= T^T), copied to zbuf
+  for (int c = nc - 1; c >= 1; --c) {
+    const int mr = kacc[c - 1] + kleaf[c];
+    // zbuf (mr x s) = [top (kacc[c] rows); 0]
+    for (int e = tid; e < mr * s; e += NT) {
+      const int col = e / mr, r = e % mr;
+      zbuf[e] = (r < kacc[c]) ? Y[(int64_t)col * m + r] : 0.0;
+    }
+    __syncthreads();
+    const int kk = mr < n ? mr : n;
+    wg_apply_q_reg<4>(ws + (int64_t)(nc + c) * QROWS * n, ws_tau + (int64_t)(nc + c) * n, mr, kk,
+                      zbuf, s, stage, cap, tstage);
+    // top kacc[c-1] rows back to the head of Y; the rest is leaf c's input,
+    // placed at the head of leaf c's row block
+    for (int e = tid; e < mr * s; e += NT) {
+      const int col = e / mr, r = e % mr;
+      if (r < kacc[c - 1])
+        Y[(int64_t)col * m + r] = zbuf[e];
+      else
+        Y[(int64_t)col * m + c * QROWS + (r - kacc[c - 1])] = zbuf[e];
+    }
+    __syncthreads();
+  }
+  // leaves: rows [c*256, c*256 + mc): [input (kleaf rows); 0] -> Q_c [input; 0]
+  for (int c = 0; c < nc; ++c) {
+    const int mc = (m - c * QROWS) < QROWS ? (m - c * QROWS) : QROWS;
+    double* Yc = Y + c * QROWS;
+    for (int e = tid; e < mc * s; e += NT) {
+      const int col = e / mc, r = e % mc;
+      if (r >= kleaf[c]) Yc[(int64_t)col * m + r] = 0.0;
+    }
+    __syncthreads();
+    wg_apply_q_reg<4>(ws + (int64_t)c * QROWS * n, ws_tau + (int64_t)c * n, mc, kleaf[c], Yc, s,
+                      stage, cap, tstage, m);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Left-to-right pass, one workgroup per MPO.  Panels live in LDS when they fit.
+// ---------------------------------------------------------------------------
+constexpr int LR_MB = 6144;   // M panel / Y
+constexpr int LR_VB = 6144;   // staged reflectors, E, W
+constexpr int LR_UB = 4096;   // Jacobi rotations, C
+constexpr int LR_SC = 990;    // sort / sign buffers (6144*2 + 4096 + 3*990 + 80 <= ARENA)
+
+static_assert(LR_MB + LR_VB + LR_UB + 3 * LR_SC + 16 + 64 <= ARENA, "left-to-right LDS carve");
+static_assert(ARENA == kSweepArena, "arena size shared with the host plan");
+static_assert(LR_SC == kSortCap, "sort capacity shared with the host plan");
+
 struct ScratchLayout {
   double* T;
   double* M;
@@ -332,14 +871,23 @@ struct ScratchLayout {
 
 template <typename TO>
 __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int op,
-                                                const int* rho, int* xr, const double* Wd,
-                                                const double* tau, double* scratch,
-                                                TO* __restrict__ Xout, double* outs,
-                                                SweepOpts so, int vcap, int scap,
-                                                int64_t tcap, int64_t mcap_s, int64_t ucap,
-                                                int* err) {
-  extern __shared__ double smem[];
-  LdsLayout S = carve(smem, vcap, scap);
+                                                const int* rho, const int* ldm, int* xr,
+                                                const double* Wd, const double* tau,
+                                                double* scratch, TO* __restrict__ Xout,
+                                                double* outs, SweepOpts so, int64_t tcap,
+                                                int64_t mcap_s, int64_t ucap, int* err) {
+  __shared__ double arena[ARENA];
+  __shared__ int iarena[LR_SC + 16];
+  double* Mb = arena;
+  double* Vb = Mb + LR_MB;
+  double* Ub = Vb + LR_VB;
+  double* sig = Ub + LR_UB;
+  double* nrmb = sig + LR_SC;
+  double* sgn = nrmb + LR_SC;
+  double* red = sgn + LR_SC;
+  double* tst = red + 16;           // 64 doubles of staged tau
+  int* perm = iarena;
+  int* ibuf = iarena + LR_SC;
   const int tid = threadIdx.x;
   const MpoDesc md = mpos[blockIdx.x];
   const int d = md.d, K = md.K;
@@ -353,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
   const double* X0 = Wd + c0.w_off;
   double part = 0.0;
   for (int t = tid; t < m0; t += NT) part += X0[t] * X0[t];
-  const double nrm = sqrt(block_sum(part, S.red));
+  const double nrm = sqrt(block_sum(part, red));
   const double delta = d > 1 ? so.eps * nrm / sqrt((double)(d - 1)) : 0.0;
   int s = 1;
   if (tid == 0) {
@@ -364,42 +912,55 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
     const CoreDesc cd = cores[md.c0 + i];
     const int n = op == 0 ? cd.I : cd.J;
     const int rn = (i == d - 1) ? K : rho[md.r0 + i + 1];
-    const int m = n * rn;
+    const int ldraw = (i == 0) ? rn : ldm[md.r0 + i];
+    const int ntree = ldraw < 0 ? -ldraw : 0;   // > 0: the panel was factorised by TSQR
+    const int ld = ldraw < 0 ? rn : ldraw;
+    const int mp = n * ld;
     const int ri = i == 0 ? 1 : rho[md.r0 + i];
     const int64_t nvg = (int64_t)s * n;
-    // capacity guard (every value here is block uniform)
     {
-      bool bad = s < 1 || s > cd.xcap || rn < 1 || rn > cd.RA2 * cd.xcap2 || m > vcap ||
-                 ri < 1 || ri > cd.RA * cd.xcap || (int64_t)s * m > mcap_s ||
-                 (int64_t)s * ri > tcap || K > scap;
+      bool bad = s < 1 || s > cd.xcap || rn < 1 || rn > cd.RA2 * cd.xcap2 || ld < rn ||
+                 ri < 1 || ri > cd.RA * cd.xcap || (int64_t)s * mp > mcap_s ||
+                 (int64_t)s * ri > tcap || K > LR_SC || mp > ARENA;
       if (i < d - 1)
-        bad = bad || nvg > scap || nvg * nvg > ucap || (int64_t)cd.xcap2 * rn > tcap;
+        bad = bad || nvg > LR_SC || nvg * nvg > ucap || (int64_t)cd.xcap2 * rn > tcap;
       else
-        bad = bad || nvg > vcap || 2 * nvg * K + K + (int64_t)K * K > ucap;
+        bad = bad || nvg > ARENA || 2 * nvg * K + K + (int64_t)K * K > ucap;
       if (bad) {
         if (tid == 0) atomicOr(err, 4);
         return;
       }
     }
-    double* M = SL.M;
+    const bool m_in_lds = (int64_t)s * mp <= LR_MB;
+    double* M = m_in_lds ? Mb : SL.M;
     if (i == 0) {
-      for (int t = tid; t < m; t += NT) M[t] = X0[t];
+      for (int t = tid; t < mp; t += NT) M[t] = X0[t];
       __syncthreads();
     } else {
-      // M^T (m x s, column-major) = H_0 ... H_{ri-1} [T^T; 0]
-      for (int64_t o = tid; o < (int64_t)m * s; o += NT) {
-        const int c = (int)(o / m), r = (int)(o % m);
+      // M^T (mp x s, column-major) = H_0 ... H_{ri-1} [T^T; 0]
+      for (int64_t o = tid; o < (int64_t)mp * s; o += NT) {
+        const int c = (int)(o / mp), r = (int)(o % mp);
         M[o] = (r < ri) ? SL.T[(int64_t)c * ri + r] : 0.0;
       }
       __syncthreads();
-      wg_apply_q(Wd + cd.w_off, tau + cd.tau_off, m, ri, M, s);
+      if (ntree > 0) {
+        tsqr_apply(Wd + cd.w_off, mp, ri, M, s, ntree, Vb, LR_VB, tst,
+                   ((int64_t)2 * ri * s <= LR_UB) ? Ub : SL.U);
+      } else if (mp <= 256)
+        wg_apply_q_reg<4>(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB, tst);
+      else if (mp <= 1024)
+        wg_apply_q_reg<16>(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB, tst);
+      else if (mp <= LR_VB)
+        wg_apply_q_staged(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB, tst);
+      else
+        wg_apply_q(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s);
     }
-    // M is now s x m row-major, i.e. the (s n) x rn panel, row (c, y) = c * n + y.
+    // M is now s x mp row-major: row (c, y) = c * n + y of the (s n) x rn panel, stride ld.
     const int nv = s * n;
     if (i < d - 1) {
-      double* U = SL.U;
-      wg_jacobi(M, nv, rn, rn, U, S.ibuf);
-      wg_norms_sorted(M, nv, rn, rn, S.sig, S.perm, S.nrm);
+      double* U = (nvg * nvg <= LR_UB) ? Ub : SL.U;
+      wg_jacobi(M, nv, rn, ld, U, ibuf);
+      wg_norms_sorted(M, nv, rn, ld, sig, perm, nrmb);
       if (tid == 0) {
         const int kk = nv < rn ? nv : rn;
         const double d2 = delta * delta;
@@ -407,42 +968,43 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         int rho_new = kk;
         // smallest rho >= 1 with sum_{l >= rho} sig_l^2 <= delta^2
         for (int cand = kk - 1; cand >= 1; --cand) {
-          tail += S.sig[cand] * S.sig[cand];
-          if (tail <= d2) rho_new = cand;
-          else break;
+          tail += sig[cand] * sig[cand];
+          if (tail <= d2)
+            rho_new = cand;
+          else
+            break;
         }
         if (so.rmax > 0 && rho_new > so.rmax) rho_new = so.rmax;
         if (rho_new < 1) rho_new = 1;
-        if (rho_new > cores[md.c0 + i].xcap2) {
+        if (rho_new > cd.xcap2) {
           atomicOr(err, 2);
-          rho_new = cores[md.c0 + i].xcap2;
+          rho_new = cd.xcap2;
         }
-        S.ibuf[1] = rho_new;
+        ibuf[1] = rho_new;
       }
       __syncthreads();
-      const int rnew = S.ibuf[1];
-      for (int k = tid; k < rnew; k += NT)
-        S.sgn[k] = sign_of_max(U + (int64_t)S.perm[k] * nv, nv, 1);
+      const int rnew = ibuf[1];
+      for (int k = tid; k < rnew; k += NT) sgn[k] = sign_of_max(U + (int64_t)perm[k] * nv, nv, 1);
       __syncthreads();
       TO* xo = Xout + cd.x_off;
       for (int64_t o = tid; o < (int64_t)nv * rnew; o += NT) {
         const int row = (int)(o / rnew), k = (int)(o % rnew);
-        xo[o] = (TO)(U[(int64_t)S.perm[k] * nv + row] * S.sgn[k]);
+        xo[o] = (TO)(U[(int64_t)perm[k] * nv + row] * sgn[k]);
       }
       for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
         const int k = (int)(o / rn), f = (int)(o % rn);
-        SL.T[o] = M[(int64_t)S.perm[k] * rn + f] * S.sgn[k];
+        SL.T[o] = M[(int64_t)perm[k] * ld + f] * sgn[k];
       }
       if (tid == 0) xr[md.r0 + i + 1] = rnew;
       s = rnew;
       __syncthreads();
     } else {
-      // last core: the (s n) x K panel, column-major copy C
-      double* C = SL.U;
+      // last core: the (s n) x K panel as a column-major copy C
       const int64_t ck = (int64_t)nv * K;
+      double* C = (ck <= LR_UB) ? Ub : SL.U;
       for (int64_t o = tid; o < ck; o += NT) {
         const int row = (int)(o % nv), kap = (int)(o / nv);
-        C[o] = M[(int64_t)row * K + kap];
+        C[o] = M[(int64_t)row * ld + kap];
       }
       __syncthreads();
       double* o_sig = outs + md.out_off;
@@ -451,9 +1013,10 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       TO* xo = Xout + cd.x_off;
       if (so.mode == 0) {
         // thin Householder QR (Algorithm 5.2, mirrored): Q_d and the K x K R
-        double* tauK = C + ck;
-        double* E = tauK + K;
-        wg_geqr2(C, nv, K, tauK, S.v, S.red);
+        double* tauK = sig;
+        double* E = (ck <= LR_VB) ? Vb : SL.U + ck + K;
+        double* vtmp = (ck <= LR_UB && nv <= LR_MB) ? Mb : SL.M;
+        wg_geqr2(C, nv, K, tauK, vtmp, red);
         for (int64_t o = tid; o < (int64_t)K * K; o += NT) {
           const int r = (int)(o / K), c = (int)(o % K);
           o_R[o] = (c >= r) ? C[(int64_t)c * nv + r] : 0.0;
@@ -470,21 +1033,20 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         }
       } else {
         // economical SVD (Algorithm 5.3, mirrored): C W = X diag(sigma)
-        double* Wr = C + ck;
-        wg_jacobi(C, K, nv, nv, Wr, S.ibuf);
-        wg_norms_sorted(C, K, nv, nv, S.sig, S.perm, S.nrm);
-        for (int k = tid; k < K; k += NT)
-          S.sgn[k] = sign_of_max(C + (int64_t)S.perm[k] * nv, nv, 1);
+        double* Wr = ((int64_t)K * K <= LR_VB) ? Vb : SL.U + ck;
+        wg_jacobi(C, K, nv, nv, Wr, ibuf);
+        wg_norms_sorted(C, K, nv, nv, sig, perm, nrmb);
+        for (int k = tid; k < K; k += NT) sgn[k] = sign_of_max(C + (int64_t)perm[k] * nv, nv, 1);
         __syncthreads();
-        for (int k = tid; k < K; k += NT) o_sig[k] = S.sig[k];
+        for (int k = tid; k < K; k += NT) o_sig[k] = sig[k];
         for (int64_t o = tid; o < (int64_t)K * K; o += NT) {
           const int kap = (int)(o / K), k = (int)(o % K);
-          o_W[o] = Wr[(int64_t)S.perm[k] * K + kap] * S.sgn[k];
+          o_W[o] = Wr[(int64_t)perm[k] * K + kap] * sgn[k];
         }
         for (int64_t o = tid; o < ck; o += NT) {
           const int row = (int)(o / K), k = (int)(o % K);
-          const double sk = S.sig[k];
-          const double val = C[(int64_t)S.perm[k] * nv + row] * S.sgn[k];
+          const double sk = sig[k];
+          const double val = C[(int64_t)perm[k] * nv + row] * sgn[k];
           xo[o] = (TO)(sk > 0.0 ? val / sk : 0.0);
         }
       }
@@ -496,34 +1058,28 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
 }  // namespace
 
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
-                          const int* pr, int* rho, const void* Z, int dtype, double* Wd,
-                          double* L, double* tau, int vcap, int scap, int* err, hipStream_t s) {
-  const size_t lds = sizeof(double) * ((size_t)vcap + NW + 3 * (size_t)scap) +
-                     sizeof(int) * ((size_t)scap + 8);
+                          const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
+                          double* L, double* tau, int* err, hipStream_t s) {
   if (dtype == 0)
-    k_rl_pass<double><<<batch, NT, lds, s>>>(mpos, cores, op, pr, rho, (const double*)Z, Wd, L,
-                                              tau, vcap, scap, err);
+    k_rl_pass<double><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const double*)Z, Wd, L,
+                                            tau, err);
   else
-    k_rl_pass<float><<<batch, NT, lds, s>>>(mpos, cores, op, pr, rho, (const float*)Z, Wd, L, tau,
-                                             vcap, scap, err);
+    k_rl_pass<float><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const float*)Z, Wd, L,
+                                           tau, err);
   return hipGetLastError();
 }
 
 hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
-                          const int* rho, int* xr, const double* Wd, const double* tau,
-                          double* scratch, void* Xout, int out_dtype, double* outs, SweepOpts o,
-                          int vcap, int scap, int64_t tcap, int64_t mcap_s, int64_t ucap,
+                          const int* rho, const int* ldm, int* xr, const double* Wd,
+                          const double* tau, double* scratch, void* Xout, int out_dtype,
+                          double* outs, SweepOpts o, int64_t tcap, int64_t mcap_s, int64_t ucap,
                           int* err, hipStream_t s) {
-  const size_t lds = sizeof(double) * ((size_t)vcap + NW + 3 * (size_t)scap) +
-                     sizeof(int) * ((size_t)scap + 8);
   if (out_dtype == 0)
-    k_lr_pass<double><<<batch, NT, lds, s>>>(mpos, cores, op, rho, xr, Wd, tau, scratch,
-                                              (double*)Xout, outs, o, vcap, scap, tcap, mcap_s,
-                                              ucap, err);
+    k_lr_pass<double><<<batch, NT, 0, s>>>(mpos, cores, op, rho, ldm, xr, Wd, tau, scratch,
+                                            (double*)Xout, outs, o, tcap, mcap_s, ucap, err);
   else
-    k_lr_pass<float><<<batch, NT, lds, s>>>(mpos, cores, op, rho, xr, Wd, tau, scratch,
-                                             (float*)Xout, outs, o, vcap, scap, tcap, mcap_s, ucap,
-                                             err);
+    k_lr_pass<float><<<batch, NT, 0, s>>>(mpos, cores, op, rho, ldm, xr, Wd, tau, scratch,
+                                           (float*)Xout, outs, o, tcap, mcap_s, ucap, err);
   return hipGetLastError();
 }
 

@@ -65,7 +65,8 @@ struct tnrsvd_s {
   MpoDesc* mpos_d = nullptr;
   CoreDesc* cores_d = nullptr;
   int* core_mpo_d = nullptr;
-  int *xr = nullptr, *vr = nullptr, *pr = nullptr, *rho = nullptr, *err = nullptr;
+  int *xr = nullptr, *vr = nullptr, *pr = nullptr, *rho = nullptr, *ldm = nullptr,
+      *err = nullptr;
   void *A = nullptr, *X = nullptr, *Z = nullptr, *Y0 = nullptr;
   double *W = nullptr, *L = nullptr, *tau = nullptr, *scratch = nullptr, *outs = nullptr,
          *om = nullptr, *U = nullptr, *V = nullptr;
@@ -276,6 +277,9 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
       cd.xcap2 = (int)xc[i + 1];
       const int64_t nmax = std::max(I[i], J[i]);
       const int64_t P = R[i] * xc[i], P2 = R[i + 1] * xc[i + 1];
+      // register panels pad each y block of rows to a power of two (>= 16)
+      int64_t P2pad = 16;
+      while (P2pad < P2) P2pad *= 2;
       cd.a_off = a_tot;
       a_tot += R[i] * I[i] * J[i] * R[i + 1];
       cd.x_off = x_tot;
@@ -284,7 +288,14 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
       cd.z_off = z_tot;
       z_tot += P * nmax * P2;
       cd.w_off = w_tot;
-      w_tot += nmax * P2 * P;
+      int64_t wneed = nmax * P2pad * P;
+      if (i == dm - 1) {
+        // a tall last-core panel may be factorised by TSQR: leaf + merge
+        // reflectors (2 nc blocks of 256 x P), two P x P factors, 2 nc taus
+        const int64_t nc = (nmax * K + 255) / 256;
+        wneed = std::max(wneed, (2 * nc * 256 + 2 * P) * P + 2 * nc * P);
+      }
+      w_tot += wneed;
       cd.l_off = l_tot;
       l_tot += P * P;
       cd.tau_off = t_tot;
@@ -294,7 +305,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
       h->max_core_out = std::max(h->max_core_out, P * nmax * P2);
       mpo_t = std::max(mpo_t, xc[i] * P);
       mpo_t = std::max(mpo_t, xc[i + 1] * P2);
-      mpo_m = std::max(mpo_m, xc[i] * nmax * P2);
+      mpo_m = std::max(mpo_m, xc[i] * nmax * P2pad);
       mpo_v = (int)std::max<int64_t>(mpo_v, nmax * P2);
       const int64_t nv = xc[i] * nmax;
       if (i < dm - 1) {
@@ -334,11 +345,11 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   h->tcap = tcap;
   h->mcap_s = mcap_s;
   h->ucap = ucap;
-  const size_t lds = sizeof(double) * ((size_t)vcap + kSweepThreads / 64 + 3 * (size_t)scap) +
-                     sizeof(int) * ((size_t)scap + 8);
-  if (lds > 64 * 1024) {
+  if (vcap > kSweepArena - 64 || scap > kSortCap) {
     delete h;
-    return fail(TNRSVD_E_SHAPE, "sweep needs %zu bytes of LDS (> 64 KiB); lower max_rank", lds);
+    return fail(TNRSVD_E_SHAPE,
+                "panels too large for one workgroup (rows %d, sorted vectors %d); lower max_rank",
+                vcap, scap);
   }
   const size_t esz = h->dtype == 0 ? sizeof(double) : sizeof(float);
 
@@ -360,6 +371,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   ALLOC(h->vr, sizeof(int) * r_tot);
   ALLOC(h->pr, sizeof(int) * r_tot);
   ALLOC(h->rho, sizeof(int) * r_tot);
+  ALLOC(h->ldm, sizeof(int) * r_tot);
   ALLOC(h->err, sizeof(int) * 4);
   ALLOC(h->A, esz * a_tot);
   ALLOC(h->X, esz * x_tot);
@@ -565,8 +577,8 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   hipError_t e;
   {
     Timed tm(h, 1);
-    e = launch_rl_pass(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->rho, h->Z, h->dtype, h->W,
-                       h->L, h->tau, h->vcap, h->scap, h->err, h->stream);
+    e = launch_rl_pass(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->rho, h->ldm, h->Z, h->dtype,
+                       h->W, h->L, h->tau, h->err, h->stream);
   }
   TRY(dev_check(e, "right-to-left sweep"));
   Timed tm(h, 2);
@@ -577,9 +589,9 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   void* out = mode == 0 ? h->X : (void*)h->V;
   const int odt = mode == 0 ? h->dtype : 0;
   int* rout = mode == 0 ? h->xr : h->vr;
-  e = launch_lr_pass(h->mpos_d, h->cores_d, h->batch, op, h->rho, rout, h->W, h->tau,
-                     h->scratch, out, odt, h->outs, so, h->vcap, h->scap, h->tcap, h->mcap_s,
-                     h->ucap, h->err, h->stream);
+  e = launch_lr_pass(h->mpos_d, h->cores_d, h->batch, op, h->rho, h->ldm, rout, h->W, h->tau,
+                     h->scratch, out, odt, h->outs, so, h->tcap, h->mcap_s, h->ucap, h->err,
+                     h->stream);
   return dev_check(e, "left-to-right sweep");
 }
 

@@ -61,8 +61,10 @@ struct SweepOpts {
   int mode;          // 0: orthogonalise (QR of the last core), 1: solve (SVD)
 };
 
-constexpr int kSweepThreads = 512;
+constexpr int kSweepThreads = 1024;
 constexpr int kMaxK = 256;
+constexpr int kSweepArena = 19456;   // doubles of static LDS per sweep workgroup
+constexpr int kSortCap = 990;        // largest panel row count the sweep sorts
 
 }  // namespace tnr
 
@@ -85,12 +87,12 @@ hipError_t launch_copy_y0(const MpoDesc* mpos, const CoreDesc* cores, const int*
                           int ncores, const int* pr, const void* Z, void* Y0, int dtype,
                           int64_t max_out, hipStream_t s);
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
-                          const int* pr, int* rho, const void* Z, int dtype, double* Wd,
-                          double* L, double* tau, int vcap, int scap, int* err, hipStream_t s);
+                          const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
+                          double* L, double* tau, int* err, hipStream_t s);
 hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
-                          const int* rho, int* xr, const double* Wd, const double* tau,
-                          double* scratch, void* Xout, int out_dtype, double* outs, SweepOpts o,
-                          int vcap, int scap, int64_t tcap, int64_t mcap_s, int64_t ucap,
+                          const int* rho, const int* ldm, int* xr, const double* Wd,
+                          const double* tau, double* scratch, void* Xout, int out_dtype,
+                          double* outs, SweepOpts o, int64_t tcap, int64_t mcap_s, int64_t ucap,
                           int* err, hipStream_t s);
 hipError_t launch_form_u(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
                          int ncores, const int* xr, const void* X, int dtype, const double* outs,
