@@ -13,6 +13,8 @@
 // pass.  Every row of a vector is always touched by the same lane (row r is
 // owned by lane r % 64), so no cross-lane read-after-write goes through memory
 // without a workgroup barrier.
+#include <type_traits>
+
 #include "tnrsvd_internal.h"
 
 namespace tnr {
@@ -47,6 +49,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Workgroup barrier that orders LDS only: global stores still in flight are
+// not waited for (a plain __syncthreads drains them, which costs an L2 round
+// trip).  Only for loops whose global writes nobody reads before the next full
+// barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 // Sum over the workgroup; every thread receives the total.  `red` holds NW doubles.
 __device__ double block_sum(double v, double* red) {
@@ -266,8 +276,8 @@ __device__ inline double sign_of_max(const double* x, int n, int stride) {
 // ---------------------------------------------------------------------------
 // Register-resident Householder QR (panels up to 256 x 128).
 // Layout: lane l of wave w is in 16-lane row g = l / 16 at position h = l % 16;
-// o = 4 w + g (0..63) owns columns o and o + 64 (slots u = 0, 1) and lane h
-// holds rows h + 16 t (t < 16) of them: x[t][u] = X[h + 16 t][o + 64 u].
+// o = 4 w + g (0 .. QOWN-1) owns columns o + QOWN u (slots u < QNC) and lane h
+// holds rows h + 16 t (t < 16) of them: x[t][u] = X[h + 16 t][o + QOWN u].
 // A column's inner product is then a butterfly over one DPP row (4 steps,
 // every lane gets the sum), the four rows of a wave work on four columns at
 // once, and columns are dealt cyclically so the shrinking trailing matrix
@@ -275,10 +285,13 @@ __device__ inline double sign_of_max(const double* x, int n, int stride) {
 // reflector and publishes it in a double-buffered LDS vector.
 // ---------------------------------------------------------------------------
 constexpr int QMR = 16;                // row slots    -> 256 rows
-constexpr int QNC = 2;                 // column slots -> 128 columns
+constexpr int QOWN = 4 * NW;           // column owners: four 16-lane rows per wave
+constexpr int QNC = 128 / QOWN;        // column slots -> 128 columns
 constexpr int QROWS = 16 * QMR;
-constexpr int QCOLS = 64 * QNC;
+constexpr int QCOLS = QOWN * QNC;
 constexpr int ARENA = 19456;           // doubles of static LDS per workgroup (152 KiB)
+static_assert(2 * QROWS + QCOLS + QCOLS * QCOLS <= ARENA - 32,
+              "register QR: reflector buffers, diagonal, R gather");
 
 // Sum over the 16 lanes of a DPP row; every lane of the row receives it.
 __device__ __forceinline__ double row16_sum(double v) {
@@ -289,24 +302,35 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-// Owner-row part of one column step: build the reflector of column j (held in
-// slot UJ), write it into x and into the LDS vector v, and publish tau.
-template <int UJ>
-__device__ __forceinline__ void reg_reflector(double (&x)[QMR][QNC], int j, int m, int h,
-                                              bool mine, double* v, double* tbuf,
-                                              double* tau_g) {
-  double s2 = 0.0, al = 0.0;
+// Compile-time loop: f(integral_constant<int, B>), ..., f(<E - 1>).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Householder reflector of column jj, held in col by the calling owner row
+// (Parlett's form: diag(R) >= 0, v[jj] = 1).  Writes v (zeros above the
+// diagonal, 1 on it) to LDS, tau to LDS and to tau_g, and the diagonal entry
+// of R to bt[jj].  Sums use two partial accumulators to keep the dependent
+// FP64 chain short.
+__device__ __forceinline__ void reg_reflect(const double (&col)[QMR], int jj, int m, int h,
+                                            double* v, double* tbs, double* tau_g, double* bt) {
+  double sq[2] = {0.0, 0.0}, dg[2] = {0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < QMR; ++t) {
     const int r = h + 16 * t;
-    const double c = x[t][UJ];
-    const double cm = (r > j && r < m) ? c : 0.0;
-    s2 += cm * cm;
-    al += (r == j) ? c : 0.0;
+    const double c = col[t];
+    const double cm = (r > jj && r < m) ? c : 0.0;
+    sq[t & 1] += cm * cm;
+    dg[t & 1] += (r == jj) ? c : 0.0;
   }
-  s2 = row16_sum(s2);
-  al = row16_sum(al);
-  if (!mine) return;
+  sq[0] += sq[1];
+  dg[0] += dg[1];
+  const double s2 = row16_sum(sq[0]);
+  const double al = row16_sum(dg[0]);
   double tj, beta, inv_v0;
   if (s2 == 0.0) {
     inv_v0 = 0.0;
@@ -320,129 +344,126 @@ __device__ __forceinline__ void reg_reflector(double (&x)[QMR][QNC], int j, int 
   } else {
     const double nrm = sqrt(al * al + s2);
     const double v0 = (al <= 0.0) ? al - nrm : -s2 / (al + nrm);
+    inv_v0 = 1.0 / v0;
     tj = 2.0 * v0 * v0 / (s2 + v0 * v0);
     beta = nrm;
-    inv_v0 = 1.0 / v0;
   }
-  // branch-free: every lane writes all its rows of v (zero above the pivot)
 #pragma unroll
   for (int t = 0; t < QMR; ++t) {
     const int r = h + 16 * t;
-    const double c = x[t][UJ];
-    const bool below = r > j && r < m;
-    const double vv = below ? c * inv_v0 : (r == j ? 1.0 : 0.0);
-    v[r] = vv;
-    x[t][UJ] = below ? vv : (r == j ? beta : c);
+    const bool below = r > jj && r < m;
+    v[r] = below ? col[t] * inv_v0 : (r == jj ? 1.0 : 0.0);
   }
   if (h == 0) {
-    *tbuf = tj;
-    *tau_g = tj;
+    tbs[0] = tj;
+    tau_g[jj] = tj;
+    bt[jj] = beta;
   }
 }
 
-__device__ void reg_geqr(double (&x)[QMR][QNC], int m, int n, double* vb, double* tb,
-                         double* tau_g) {
-  const int lane = threadIdx.x & 63, h = lane & 15, g = lane >> 4;
+// Householder QR of the register panel with one-step look-ahead: during the
+// update by reflector j, the row group holding column j + 1 builds reflector
+// j + 1 (into the other LDS buffer) as soon as that column is updated, so
+// building a reflector overlaps the other groups' updates.  A wave that does not hold column j + 1 copies reflector j from LDS
+// to V (column-major, ld ldv, whole column: zeros above the diagonal, 1 on
+// it).  R (row-major k x n, k = min(m, n), zero lower triangle) is read off the
+// registers at the end: rows above the diagonal of column c are final once
+// reflectors 0..c-1 are applied, the diagonal comes from bt.  It is gathered in
+// LDS (Rl, k n doubles) and written out coalesced.
+__device__ __forceinline__ void reg_geqr(double (&x)[QMR][QNC], int m, int n, double* vb,
+                                         double* tb, double* tau_g, double* V, int ldv,
+                                         double* R, double* bt, double* Rl) {
+  const int tid = threadIdx.x, lane = tid & 63, h = lane & 15, g = lane >> 4;
   const int w = wave_id();
   const int o = 4 * w + g;
   const int kmax = m < n ? m : n;
+  if (kmax > 0 && o == 0) {
+    double col[QMR];
+#pragma unroll
+    for (int t = 0; t < QMR; ++t) col[t] = x[t][0];
+    reg_reflect(col, 0, m, h, vb, tb, tau_g, bt);
+  }
   for (int j = 0; j < kmax; ++j) {
     const int buf = j & 1;
-    double* v = vb + buf * QROWS;
-    const int oj = j & 63;
-    if (w == (oj >> 2)) {
-      const bool mine = g == (oj & 3);
-      if (j < 64)
-        reg_reflector<0>(x, j, m, h, mine, v, tb + buf, tau_g + j);
-      else
-        reg_reflector<1>(x, j, m, h, mine, v, tb + buf, tau_g + j);
-    }
-    __syncthreads();
+    lds_barrier();
     const double tj = tb[buf];
-    if (tj != 0.0) {
-      // Branch-free update: all 16 reads of v are issued together (rows above
-      // the pivot hold zeros there), inactive columns get a zero coefficient.
-      double vr[QMR];
+    const double* vh = vb + buf * QROWS + h;
+    double* vnext = vb + (buf ^ 1) * QROWS;
+    const int jn = j + 1, on = jn % QOWN, un = jn / QOWN;
+    const bool la = jn < kmax && (on >> 2) == w;   // this wave holds column j + 1
+    if (!la && w == ((((j % QOWN) >> 2) + NW / 2) % NW)) {
+      // reflector j to global memory (rows lane + 64 k)
+      double* Vc = V + j * ldv;
 #pragma unroll
-      for (int t = 0; t < QMR; ++t) vr[t] = v[h + 16 * t];
-#pragma unroll
-      for (int u = 0; u < QNC; ++u) {
-        // some column of this wave in slot u lies right of j (wave uniform)
-        if (4 * w + 3 + 64 * u > j && 4 * w + 64 * u < n) {
-          double acc = 0.0;
-#pragma unroll
-          for (int t = 0; t < QMR; ++t) acc += vr[t] * x[t][u];
-          acc = row16_sum(acc);
-          const int c = o + 64 * u;
-          const double f = (c > j && c < n) ? tj * acc : 0.0;
-#pragma unroll
-          for (int t = 0; t < QMR; ++t) x[t][u] -= f * vr[t];
-        }
+      for (int k = 0; k < QROWS / 64; ++k) {
+        const int r = lane + 64 * k;
+        if (r < m) Vc[r] = vh[r - h];
       }
     }
+    static_for<0, QNC>([&](auto U) {
+      constexpr int u = decltype(U)::value;
+      // compiler-only fence: the reflector is re-read from LDS for every slot
+      // instead of being held in 16 more registers (no hardware wait)
+      asm volatile("" ::: "memory");
+      // some column of this wave in slot u lies right of j (wave uniform)
+      if (4 * w + 3 + QOWN * u > j && 4 * w + QOWN * u < n) {
+        const int c = o + QOWN * u;
+        if (tj != 0.0) {
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < QMR; ++t) acc += vh[16 * t] * x[t][u];
+          acc = row16_sum(acc);
+          const double f = (c > j && c < n) ? tj * acc : 0.0;
+#pragma unroll
+          for (int t = 0; t < QMR; ++t) x[t][u] -= f * vh[16 * t];
+        }
+        // look-ahead: column j + 1 is in slot u of this wave (wave uniform)
+        if (la && un == u && o == on) {
+          double col[QMR];
+#pragma unroll
+          for (int t = 0; t < QMR; ++t) col[t] = x[t][u];
+          reg_reflect(col, jn, m, h, vnext, tb + (buf ^ 1), tau_g, bt);
+        }
+      }
+    });
   }
-}
-
-// Store the factorised register panel: reflector entries below the diagonal
-// into V (column-major, ld ldv) and the kmax x n upper-trapezoidal R (row-major).
-__device__ void reg_store(const double (&x)[QMR][QNC], int m, int n, double* V, int ldv,
-                          double* R) {
-  const int lane = threadIdx.x & 63, h = lane & 15, g = lane >> 4;
-  const int o = 4 * wave_id() + g;
-  const int kmax = m < n ? m : n;
+  lds_barrier();
+  // R off the registers: rows above the diagonal as they stand, the diagonal
+  // from bt, zeros below
 #pragma unroll
   for (int t = 0; t < QMR; ++t) {
     const int r = h + 16 * t;
 #pragma unroll
     for (int u = 0; u < QNC; ++u) {
-      const int c = o + 64 * u;
-      if (r < m && c < n) {
-        if (c < kmax && r > c) V[(int64_t)c * ldv + r] = x[t][u];
-        if (r < kmax) R[(int64_t)r * n + c] = (c >= r) ? x[t][u] : 0.0;
-      }
+      const int c = o + QOWN * u;
+      if (r < kmax && c < n) Rl[r * n + c] = r < c ? x[t][u] : (r == c ? bt[c] : 0.0);
     }
   }
+  lds_barrier();
+  for (int e = tid; e < kmax * n; e += NT) R[e] = Rl[e];
 }
+
 
 // Rows [r0, r0 + mr) of the last core's panel (no absorption):
 // x[t][u] = Z[p][r0 + r], the panel row being (y, kappa) of an m-row panel.
 template <typename T>
-__device__ void reg_load_plain(double (&x)[QMR][QNC], const T* __restrict__ Zc, int m, int P,
+__device__ __forceinline__ void reg_load_plain(double (&x)[QMR][QNC], const T* __restrict__ Zc, int m, int P,
                                int r0 = 0, int mr = -1) {
   const int lane = threadIdx.x & 63, h = lane & 15, g = lane >> 4;
   const int o = 4 * wave_id() + g;
   if (mr < 0) mr = m;
+  // branch-free: every load has a clamped in-bounds address, so all of them
+  // are in flight before the first use; out-of-range elements are zeroed after
+  const T* base = Zc + r0;
 #pragma unroll
   for (int t = 0; t < QMR; ++t) {
     const int r = h + 16 * t;
 #pragma unroll
     for (int u = 0; u < QNC; ++u) {
-      const int c = o + 64 * u;
-      x[t][u] = (r < mr && c < P) ? (double)Zc[(int64_t)c * m + r0 + r] : 0.0;
-    }
-  }
-}
-
-// Stack two upper-trapezoidal factors: rows [0, ka) from Ra, [ka, ka + kb) from Rb
-// (both row-major with n columns).
-__device__ void reg_load_stack(double (&x)[QMR][QNC], const double* Ra, int ka, const double* Rb,
-                               int kb, int n) {
-  const int lane = threadIdx.x & 63, h = lane & 15, g = lane >> 4;
-  const int o = 4 * wave_id() + g;
-#pragma unroll
-  for (int t = 0; t < QMR; ++t) {
-    const int r = h + 16 * t;
-#pragma unroll
-    for (int u = 0; u < QNC; ++u) {
-      const int c = o + 64 * u;
-      double val = 0.0;
-      if (c < n) {
-        if (r < ka)
-          val = Ra[(int64_t)r * n + c];
-        else if (r < ka + kb)
-          val = Rb[(int64_t)(r - ka) * n + c];
-      }
-      x[t][u] = val;
+      const int c = o + QOWN * u;
+      const bool ok = r < mr && c < P;
+      const double val = (double)base[ok ? c * m + r : 0];   // 32-bit in-core index
+      x[t][u] = ok ? val : 0.0;
     }
   }
 }
@@ -450,9 +471,9 @@ __device__ void reg_load_stack(double (&x)[QMR][QNC], const double* Ra, int ka, 
 // Absorbed panel Zt^T = (Z x_3 L)^T in the padded layout: slot t holds
 // y = t / SPY and f = h + 16 (t % SPY) (each y block padded to 16 SPY rows):
 //   x[t][u] = sum_{q >= f} R[f][q] Z[p_u][y][q],  L = R^T (rho x Pn, row-major),
-// p_u = o + 64 u.  Chunks of q are staged in LDS as RT[q][f] and ZL[q][y][p].
+// p_u = o + QOWN u.  Chunks of q are staged in LDS as RT[q][f] and ZL[q][y][p].
 template <typename T, int SPY>
-__device__ void reg_absorb(double (&x)[QMR][QNC], const T* __restrict__ Zc, int P, int n, int Pn,
+__device__ __forceinline__ void reg_absorb(double (&x)[QMR][QNC], const T* __restrict__ Zc, int P, int n, int Pn,
                            const double* __restrict__ Rn, int rho, double* stage, int stage_cap) {
   const int tid = threadIdx.x, lane = tid & 63, h = lane & 15, g = lane >> 4;
   const int o = 4 * wave_id() + g;
@@ -470,19 +491,47 @@ __device__ void reg_absorb(double (&x)[QMR][QNC], const T* __restrict__ Zc, int 
   for (int q0 = 0; q0 < Pn; q0 += QC) {
     const int qc = (Pn - q0) < QC ? (Pn - q0) : QC;
     __syncthreads();
-    for (int e = tid; e < FP * qc; e += NT) {
-      const int f = e / qc, qq = e % qc;
-      const int q = q0 + qq;
-      RT[qq * FP + f] = (f < rho && q >= f) ? Rn[(int64_t)f * Pn + q] : 0.0;
+    // staging with eight clamped loads in flight per thread
+#pragma unroll 1
+    for (int e0 = 0; e0 < FP * qc; e0 += 8 * NT) {
+      double val[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + tid + k * NT;
+        const int f = e / qc, q = q0 + e % qc;
+        const bool ok = e < FP * qc && f < rho && q >= f;
+        const double raw = Rn[ok ? f * Pn + q : 0];
+        val[k] = ok ? raw : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + tid + k * NT;
+        if (e < FP * qc) RT[(e % qc) * FP + e / qc] = val[k];
+      }
     }
-    for (int e = tid; e < QCOLS * n * qc; e += NT) {
-      const int qq = e % qc;
-      const int py = e / qc;
-      const int y = py % n, p = py / n;
-      ZL[(qq * n + y) * QCOLS + p] =
-          (p < P) ? (double)Zc[((int64_t)p * n + y) * Pn + q0 + qq] : 0.0;
+#pragma unroll 1
+    for (int e0 = 0; e0 < QCOLS * n * qc; e0 += 8 * NT) {
+      double val[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + tid + k * NT;
+        const int qq = e % qc, py = e / qc;
+        const int y = py % n, p = py / n;
+        const bool ok = e < QCOLS * n * qc && p < P;
+        const double raw = (double)Zc[ok ? (p * n + y) * Pn + q0 + qq : 0];
+        val[k] = ok ? raw : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + tid + k * NT;
+        if (e < QCOLS * n * qc) {
+          const int qq = e % qc, py = e / qc;
+          ZL[(qq * n + py % n) * QCOLS + py / n] = val[k];
+        }
+      }
     }
     __syncthreads();
+#pragma unroll 1
     for (int qq = 0; qq < qc; ++qq) {
       double rv[SPY];
 #pragma unroll
@@ -493,7 +542,7 @@ __device__ void reg_absorb(double (&x)[QMR][QNC], const T* __restrict__ Zc, int 
           const double* zp = ZL + (qq * n + y) * QCOLS + o;
           double z[QNC];
 #pragma unroll
-          for (int u = 0; u < QNC; ++u) z[u] = zp[64 * u];
+          for (int u = 0; u < QNC; ++u) z[u] = zp[QOWN * u];
 #pragma unroll
           for (int s = 0; s < SPY; ++s)
 #pragma unroll
@@ -506,14 +555,13 @@ __device__ void reg_absorb(double (&x)[QMR][QNC], const T* __restrict__ Zc, int 
 }
 
 template <typename T>
-__device__ void reg_absorb_dispatch(int spy, double (&x)[QMR][QNC], const T* Zc, int P, int n,
+__device__ __forceinline__ void reg_absorb_dispatch(int spy, double (&x)[QMR][QNC], const T* Zc, int P, int n,
                                     int Pn, const double* Rn, int rho, double* stage, int cap) {
   switch (spy) {
     case 1: reg_absorb<T, 1>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
     case 2: reg_absorb<T, 2>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
     case 4: reg_absorb<T, 4>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
-    case 8: reg_absorb<T, 8>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
-    default: reg_absorb<T, 16>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
+    default: reg_absorb<T, 8>(x, Zc, P, n, Pn, Rn, rho, stage, cap); break;
   }
 }
 
@@ -533,7 +581,10 @@ __device__ void reg_absorb_dispatch(int spy, double (&x)[QMR][QNC], const T* Zc,
 // ldm[i] records the row stride of one y block of core i's panel (rho_{i+1},
 // or its multiple of 64 when the padded register layout was used).
 // ---------------------------------------------------------------------------
-template <typename T>
+// PH 0 handles the last core only (plain register panel, TSQR or the global
+// path); PH 1 handles cores d-2 .. 0 (absorption).  Splitting the pass keeps
+// each kernel's register footprint to the paths it can take.
+template <typename T, int PH>
 __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int op,
                                                 const int* pr, int* rho, int* ldm,
                                                 const T* __restrict__ Z, double* Wd, double* L,
@@ -545,10 +596,11 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
   const int tid = threadIdx.x;
   const MpoDesc md = mpos[blockIdx.x];
   const int d = md.d;
-  if (tid == 0) rho[md.r0 + d] = md.K;
-  int rnext = md.K;
-  double x[QMR][QNC];   // the register panel shared by every register path
-  for (int i = d - 1; i >= 0; --i) {
+  if (PH == 0 && tid == 0) rho[md.r0 + d] = md.K;
+  int rnext = PH == 0 ? md.K : rho[md.r0 + d - 1];
+  const int i_first = PH == 0 ? d - 1 : d - 2;
+  const int i_last = PH == 0 ? d - 1 : 0;
+  for (int i = i_first; i >= i_last; --i) {
     const CoreDesc cd = cores[md.c0 + i];
     const int n = op == 0 ? cd.I : cd.J;
     const int P = pr[md.r0 + i];
@@ -564,10 +616,10 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
     const double* Rn = (i < d - 1) ? L + cores[md.c0 + i + 1].l_off : nullptr;
     int spy = 1;   // 16-row slots per y block, a power of two
     while (16 * spy < rnext) spy *= 2;
-    const bool reg_abs = i > 0 && i < d - 1 && P <= QCOLS && n * spy <= QMR && P <= m;
-    const bool reg_plain = i > 0 && i == d - 1 && P <= QCOLS && m <= QROWS;
-    const bool tsqr = i > 0 && i == d - 1 && P <= QCOLS && m > QROWS &&
-                      m <= 16 * QROWS;
+    const bool reg_abs = PH == 1 && i > 0 && i < d - 1 && P <= QCOLS && spy <= 8 &&
+                         n * spy <= QMR && P <= m;
+    const bool reg_plain = PH == 0 && i > 0 && P <= QCOLS && m <= QROWS;
+    const bool tsqr = PH == 0 && i > 0 && P <= QCOLS && m > QROWS && m <= 16 * QROWS;
     if (reg_abs || reg_plain || tsqr) {
       // Every register path is a sequence of jobs "load panel, QR, store"
       // with a single QR call site: one job for an absorbed or plain panel,
@@ -580,6 +632,7 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
       double* Rtmp = Racc + (int64_t)P * P;
       int kacc = 0, kleaf = 0;
       for (int job = 0; job < njobs; ++job) {
+        double x[QMR][QNC];   // the register panel, dead between jobs
         // job -> (leaf c) or (merge c): leaf 0 is job 0, then leaf c = job 2c - 1, merge c = job 2c
         const bool merge = tsqr && job > 0 && (job % 2 == 0);
         const int c = tsqr ? (job + 1) / 2 : 0;
@@ -610,16 +663,23 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
           taud = ws_tau + (int64_t)c * P;
           kleaf = mrows < P ? mrows : P;
         } else {
+          // stack [Racc; Rtmp] column-major into this merge's (not yet written)
+          // reflector block, then load it like a plain panel
           mrows = kacc + kleaf;
-          reg_load_stack(x, Racc, kacc, Rtmp, kleaf, P);
+          Vdst = Xt + (int64_t)(nc + c) * QROWS * P;
+          for (int e = tid; e < mrows * P; e += NT) {
+            const int col = e / mrows, r = e % mrows;
+            Vdst[e] = r < kacc ? Racc[r * P + col] : Rtmp[(r - kacc) * P + col];
+          }
+          __syncthreads();
+          reg_load_plain<double>(x, Vdst, mrows, P);
           __syncthreads();
           ldv = mrows;
-          Vdst = Xt + (int64_t)(nc + c) * QROWS * P;
           Rdst = (job == njobs - 1) ? L + cd.l_off : Racc;
           taud = ws_tau + (int64_t)(nc + c) * P;
         }
-        reg_geqr(x, mrows, P, vb, tb, taud);
-        reg_store(x, mrows, P, Vdst, ldv, Rdst);
+        reg_geqr(x, mrows, P, vb, tb, taud, Vdst, ldv, Rdst, arena + 2 * QROWS,
+                 arena + 2 * QROWS + QCOLS);
         __syncthreads();
         if (tsqr) {
           if (job == 0)
@@ -638,7 +698,7 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
       continue;
     }
     const int64_t tot = (int64_t)m * P;
-    if (i == d - 1) {
+    if (PH == 0) {
       // last core: Zt = Z (the K leg is external), stored transposed
       for (int64_t o = tid; o < tot; o += NT) {
         const int p = (int)(o / m), jj = (int)(o % m);
@@ -749,7 +809,9 @@ __device__ void wg_apply_q_reg(const double* __restrict__ V, const double* __res
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       const int r = lane + 64 * t;
-      y[t] = (have && r < m) ? Y[(int64_t)c * ldy + r] : 0.0;
+      const bool ok = have && r < m;
+      const double raw = Y[ok ? c * ldy + r : 0];
+      y[t] = ok ? raw : 0.0;
     }
     for (int hi = k; hi > 0; hi -= CH) {
       const int lo = hi - CH > 0 ? hi - CH : 0;
@@ -787,7 +849,7 @@ __device__ void wg_apply_q_reg(const double* __restrict__ V, const double* __res
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         const int r = lane + 64 * t;
-        if (r < m) Y[(int64_t)c * ldy + r] = y[t];
+        if (r < m) Y[c * ldy + r] = y[t];
       }
     }
   }
@@ -803,37 +865,37 @@ __device__ void tsqr_apply(const double* ws, int m, int n, double* Y, int s, int
                            double* stage, int cap, double* tstage, double* zbuf) {
   const int tid = threadIdx.x;
   const double* ws_tau = ws + (int64_t)(2 * nc * QROWS + 2 * n) * n;
-  // k_acc after each leaf / merge, recomputed from the shapes
-  int kacc[16];
-  int kleaf[16];
-  for (int c = 0; c < nc; ++c) {
+  // rows of leaf c and of the running factor after merge c, from the shapes
+  auto kleaf = [&](int c) {
     const int mc = (m - c * QROWS) < QROWS ? (m - c * QROWS) : QROWS;
-    kleaf[c] = mc < n ? mc : n;
-    if (c == 0)
-      kacc[0] = kleaf[0];
-    else
-      kacc[c] = (kacc[c - 1] + kleaf[c]) < n ? (kacc[c - 1] + kleaf[c]) : n;
-  }
-  // running top block: the first kacc[nc-1] rows of Y (= T^T), copied to zbuf
+    return mc < n ? mc : n;
+  };
+  auto kacc = [&](int c) {
+    int k = kleaf(0);
+    for (int q = 1; q <= c; ++q) k = (k + kleaf(q)) < n ? (k + kleaf(q)) : n;
+    return k;
+  };
+  // the running top block starts as the first kacc(nc-1) rows of Y (= T^T)
   for (int c = nc - 1; c >= 1; --c) {
-    const int mr = kacc[c - 1] + kleaf[c];
-    // zbuf (mr x s) = [top (kacc[c] rows); 0]
+    const int kprev = kacc(c - 1), kc = kacc(c);
+    const int mr = kprev + kleaf(c);
+    // zbuf (mr x s) = [top (kc rows); 0]
     for (int e = tid; e < mr * s; e += NT) {
       const int col = e / mr, r = e % mr;
-      zbuf[e] = (r < kacc[c]) ? Y[(int64_t)col * m + r] : 0.0;
+      zbuf[e] = (r < kc) ? Y[(int64_t)col * m + r] : 0.0;
     }
     __syncthreads();
     const int kk = mr < n ? mr : n;
     wg_apply_q_reg<4>(ws + (int64_t)(nc + c) * QROWS * n, ws_tau + (int64_t)(nc + c) * n, mr, kk,
                       zbuf, s, stage, cap, tstage);
-    // top kacc[c-1] rows back to the head of Y; the rest is leaf c's input,
+    // top kprev rows back to the head of Y; the rest is leaf c's input,
     // placed at the head of leaf c's row block
     for (int e = tid; e < mr * s; e += NT) {
       const int col = e / mr, r = e % mr;
-      if (r < kacc[c - 1])
+      if (r < kprev)
         Y[(int64_t)col * m + r] = zbuf[e];
       else
-        Y[(int64_t)col * m + c * QROWS + (r - kacc[c - 1])] = zbuf[e];
+        Y[(int64_t)col * m + c * QROWS + (r - kprev)] = zbuf[e];
     }
     __syncthreads();
   }
@@ -841,12 +903,13 @@ __device__ void tsqr_apply(const double* ws, int m, int n, double* Y, int s, int
   for (int c = 0; c < nc; ++c) {
     const int mc = (m - c * QROWS) < QROWS ? (m - c * QROWS) : QROWS;
     double* Yc = Y + c * QROWS;
+    const int kl = kleaf(c);
     for (int e = tid; e < mc * s; e += NT) {
       const int col = e / mc, r = e % mc;
-      if (r >= kleaf[c]) Yc[(int64_t)col * m + r] = 0.0;
+      if (r >= kl) Yc[(int64_t)col * m + r] = 0.0;
     }
     __syncthreads();
-    wg_apply_q_reg<4>(ws + (int64_t)c * QROWS * n, ws_tau + (int64_t)c * n, mc, kleaf[c], Yc, s,
+    wg_apply_q_reg<4>(ws + (int64_t)c * QROWS * n, ws_tau + (int64_t)c * n, mc, kl, Yc, s,
                       stage, cap, tstage, m);
   }
 }
@@ -1060,12 +1123,17 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
                           double* L, double* tau, int* err, hipStream_t s) {
-  if (dtype == 0)
-    k_rl_pass<double><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const double*)Z, Wd, L,
-                                            tau, err);
-  else
-    k_rl_pass<float><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const float*)Z, Wd, L,
-                                           tau, err);
+  if (dtype == 0) {
+    k_rl_pass<double, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const double*)Z, Wd,
+                                               L, tau, err);
+    k_rl_pass<double, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const double*)Z, Wd,
+                                               L, tau, err);
+  } else {
+    k_rl_pass<float, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const float*)Z, Wd, L,
+                                              tau, err);
+    k_rl_pass<float, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const float*)Z, Wd, L,
+                                              tau, err);
+  }
   return hipGetLastError();
 }
 

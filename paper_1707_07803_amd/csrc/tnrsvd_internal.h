@@ -61,7 +61,7 @@ struct SweepOpts {
   int mode;          // 0: orthogonalise (QR of the last core), 1: solve (SVD)
 };
 
-constexpr int kSweepThreads = 1024;
+constexpr int kSweepThreads = 512;
 constexpr int kMaxK = 256;
 constexpr int kSweepArena = 19456;   // doubles of static LDS per sweep workgroup
 constexpr int kSortCap = 990;        // largest panel row count the sweep sorts

@@ -122,8 +122,12 @@ def spectrum(d_inner: int = 15, last: int = 32, r: int = 5, n_sig: int = 50,
     V = orthonormal_mps(ranks, dims, n_sig, 4)
     sig = 10.0 ** (-np.arange(n_sig) / 4.0)
     cores = known_spectrum_mpo(U, V, sig)
+    # FP32 product cores carry a relative error of a few 1e-7, so the FP32
+    # rounding tolerance sits above that floor (the tail test compares squared
+    # singular values against (eps |Y|)^2 / (d - 1)); with 1e-6 some draws of
+    # Omega keep noise directions through the power step and inflate ranks.
     return Workload("spectrum", cores, k=k, p=p, q=q, eps=1e-12, rmax=32,
-                    eps_by_precision={"f64": 1e-12, "f32": 1e-6, "bf16": 1e-2},
+                    eps_by_precision={"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2},
                     omega_seed=5, sigma_exact=sig)
 
 
