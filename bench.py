@@ -45,6 +45,9 @@ def parse():
                     help="independent copies of the workload for the batched measurement "
                          "(0 = skip); one persistent workgroup per MPO")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 10 device-to-device copies of MIB MiB (the reference kernel "
+                         "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
     return ap.parse_args()
 
 
@@ -155,6 +158,22 @@ def time_path(W, precision, eps, steps, warmup, batch=1):
             "sigma_all": sig_all, "ranks": ranks, "counts": counts, "batch": batch}
 
 
+def measured_traffic(precision):
+    """HBM bytes per sweep from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
+    or None when the sweep kernel's source no longer matches the profiled one."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_rl_pass_spectrum_{precision}_traffic.md")
+    try:
+        text = open(path).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        src = open(os.path.join(ROOT, blob["source"]), "rb").read()
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != blob["source_sha256"]:
+        return None
+    return blob["read_bytes_per_launch"] + blob["write_bytes_per_launch"]
+
+
 def cpu_baseline(W, eps, budget):
     import numpy as np
     from oracle import tnrsvd_oracle as o
@@ -178,8 +197,23 @@ def cpu_baseline(W, eps, budget):
             "seconds": round(dt, 3)}, sig
 
 
+def copy_calibration(mib):
+    import torch
+    n = mib * 2 ** 20 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4,
+                      "launches": 10}))
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
                                    "described in DESIGN.md and not launched",
@@ -242,9 +276,10 @@ def main():
     if dom == "rl_sweep":
         fl = counts["rl_sweep"][1] / counts["rl_sweep"][2]
         ach = fl / (avg_ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "k_rl_pass (FP64 Householder LQ sweep)",
+        roof = {"bound": "alu",
+                "kernel": "k_rl_pass<T,0> + k_rl_pass<T,1> (one FP64 Householder LQ sweep)",
                 "achieved": round(ach, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / FP64_PEAK_TFLOPS, 6), "traffic": None,
+                "frac": round(ach / FP64_PEAK_TFLOPS, 6), "traffic": measured_traffic(main_p),
                 "flops_per_launch": fl, "avg_launch_ms": round(avg_ms[dom], 5)}
     else:
         by = counts["contract"][0] / counts["contract"][2]
