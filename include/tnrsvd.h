@@ -158,6 +158,23 @@ tnrsvd_status tnrsvd_solve(tnrsvd_t h, double* sigma);
 tnrsvd_status tnrsvd_run(tnrsvd_t h, double* sigma);
 
 /*
+ * tnrsvd_run_graph -- the same sequence as tnrsvd_run, captured once into a
+ * HIP graph and replayed on every later call (batched solves as one graph
+ * launch; not part of the paper).  The first call synchronises the handle's
+ * stream and records the launch sequence on a private stream of default
+ * priority; every call (the first included) replays the graph there, ordered
+ * after the work already queued on the handle's stream and before any work
+ * queued on it afterwards.  The graph reads Omega from the handle, so
+ * tnrsvd_set_omega between calls takes effect.  No call allocates after the
+ * first.  Kernel arguments are fixed at capture (device slab pointers, op,
+ * tolerance, rank cap), which never change for a handle.
+ * sigma as in tnrsvd_solve.  Results (factors, ranks) are those of tnrsvd_run.
+ * Errors: E_STATE while profiling is on (event records cannot be captured);
+ * E_DEVICE if capture or instantiation fails.
+ */
+tnrsvd_status tnrsvd_run_graph(tnrsvd_t h, double* sigma);
+
+/*
  * tnrsvd_get_factor -- borrow a device pointer to one core of a result.
  *   which 0: U (row space, last core (r, I, k)), available after solve;
  *   which 1: V (column space, last core (s, J, k)), after solve;

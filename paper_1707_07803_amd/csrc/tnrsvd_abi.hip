@@ -83,6 +83,12 @@ struct tnrsvd_s {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[kKinds];
+  // captured whole-solve graph (tnrsvd_run_graph): a private default-priority
+  // stream that owns the capture and the replays, joined to `stream` by events
+  hipStream_t gstream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t gev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -160,6 +166,12 @@ const char* tnrsvd_version(void) { return "tnrsvd-gfx950 0.1"; }
 tnrsvd_status tnrsvd_destroy(tnrsvd_t h) {
   if (!h) return TNRSVD_OK;
   (void)hipStreamSynchronize(h->stream);
+  if (h->gstream) (void)hipStreamSynchronize(h->gstream);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (hipEvent_t e : h->gev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->gstream) (void)hipStreamDestroy(h->gstream);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   release(h);
   delete h;
@@ -686,6 +698,53 @@ tnrsvd_status tnrsvd_run(tnrsvd_t h, double* sigma) {
   }
   TRY(tnrsvd_project(h));
   return tnrsvd_solve(h, sigma);
+}
+
+tnrsvd_status tnrsvd_run_graph(tnrsvd_t h, double* sigma) {
+  TRY(check_handle(h));
+  if (h->profiling)
+    return fail(TNRSVD_E_STATE, "profiling events cannot be captured; disable profiling first");
+  if (!h->gexec) {
+    if (!h->gstream) {
+      TRY(dev_check(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking),
+                    "create capture stream"));
+      for (hipEvent_t& e : h->gev)
+        TRY(dev_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "create event"));
+    }
+    // work already queued on the caller's stream (create, set_omega) must not
+    // be reordered behind the capture
+    TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+    hipStream_t user = h->stream;
+    h->stream = h->gstream;
+    hipError_t e = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal);
+    tnrsvd_status st = e == hipSuccess ? tnrsvd_run(h, nullptr) : dev_check(e, "begin capture");
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(h->gstream, &g);
+    h->stream = user;
+    if (st == TNRSVD_OK) st = dev_check(e2, "end capture");
+    if (st == TNRSVD_OK)
+      st = dev_check(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0), "instantiate graph");
+    if (st != TNRSVD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      h->gexec = nullptr;
+      return st;
+    }
+    h->graph = g;
+  }
+  // caller's stream -> replay on the capture stream -> caller's stream
+  TRY(dev_check(hipEventRecord(h->gev[0], h->stream), "record event"));
+  TRY(dev_check(hipStreamWaitEvent(h->gstream, h->gev[0], 0), "wait event"));
+  TRY(dev_check(hipGraphLaunch(h->gexec, h->gstream), "launch graph"));
+  TRY(dev_check(hipEventRecord(h->gev[1], h->gstream), "record event"));
+  TRY(dev_check(hipStreamWaitEvent(h->stream, h->gev[1], 0), "wait event"));
+  h->pending = -1;
+  h->projected = false;
+  h->solved = true;
+  h->space = kRow;
+  h->first_product = false;
+  h->y0_valid = true;
+  if (sigma) TRY(read_sigma(h, sigma));
+  return TNRSVD_OK;
 }
 
 tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merged) {

@@ -23,7 +23,7 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16}
 # the C function names exported by the library, in header order
 EXPORTS = [
     "tnrsvd_create", "tnrsvd_mult", "tnrsvd_orthogonalize", "tnrsvd_project",
-    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_get_factor", "tnrsvd_copy_factor",
+    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
     "tnrsvd_last_error", "tnrsvd_version",
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_project.argtypes = [H]
     L.tnrsvd_solve.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_run.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
+    L.tnrsvd_run_graph.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_get_factor.argtypes = [H, I, I, I, ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I)]
     L.tnrsvd_copy_factor.argtypes = [H, I, I, I, ctypes.c_void_p]
@@ -195,6 +196,15 @@ class TNrSVD:
             return None
         out = np.zeros(self.batch * self.k, dtype=np.float64)
         _check(self._lib.tnrsvd_run(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(self.batch, self.k)
+
+    def run_graph(self, want_sigma: bool = True) -> Optional[np.ndarray]:
+        """tnrsvd_run captured once into a HIP graph, replayed on later calls."""
+        if not want_sigma:
+            _check(self._lib.tnrsvd_run_graph(self._h, None))
+            return None
+        out = np.zeros(self.batch * self.k, dtype=np.float64)
+        _check(self._lib.tnrsvd_run_graph(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out.reshape(self.batch, self.k)
 
     # -- getters --------------------------------------------------------------
