@@ -4,13 +4,16 @@
 Workload: the known-spectrum MPO (2^20 x 2^20 matrix U diag(sigma) V^T built from
 left-orthonormal rank-5 MPOs in merged layout: 15 cores of 2 x 2 and one core of
 32 x 32; sigma_j = 10^(-j/4), j < 50), k = 20, p = 10 (K = 30), q = 1, rank cap
-32, rounding tolerance 1e-5 (mixed path) / 1e-12 (FP64 path).  A step is one
+32, rounding tolerance 1e-5 (FP32 path) / 1e-12 (FP64 path) / 1e-2 (BF16 path,
+whose FP32 refinement step rounds at 1e-5).  A step is one
 whole solve: Omega load, Y = A Omega, ROUND+QR, one power iteration (A^T Q and
 A Q, each rounded and orthogonalised), projection B^T = A^T Q, ROUND + sweep +
 SVD of the last core, U = Q W.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line.  `value` is solves/s of the mixed path (FP32
-contractions, FP64 sweeps); the FP64 path is reported beside it.
+contractions, FP64 sweeps); the FP64 path, the BF16 path and the BF16 path
+followed by one FP32 refinement step are reported beside it under `paths`,
+with their sigma errors under `sigma_err`.
 """
 
 from __future__ import annotations
@@ -40,7 +43,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="time budget of the oracle sample (cpu_baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precisions", default="f32,f64")
+    ap.add_argument("--precisions", default="f32,f64,bf16",
+                    help="contraction paths to time; the first one gives `value`; bf16 is "
+                         "also timed with its FP32 refinement step")
     ap.add_argument("--batch", type=int, default=256,
                     help="independent copies of the workload for the batched measurement "
                          "(0 = skip); one persistent workgroup per MPO")
@@ -121,7 +126,7 @@ def instrumented_counts(h, R, I, J, K, q, esz):
 
 # ---------------------------------------------------------------------------
 
-def time_path(W, precision, eps, steps, warmup, batch=1, graph=False):
+def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol=None):
     import numpy as np
     import torch
     from paper_1707_07803_amd import TNrSVD
@@ -132,7 +137,12 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False):
     h = TNrSVD(mpos, W.k, W.p, W.q, seed=W.omega_seed, precision=precision, round_tol=eps,
                max_rank=W.rmax)
     del cores
-    step = h.run_graph if graph else h.run
+    if refine_tol is None:
+        step = h.run_graph if graph else h.run
+    else:
+        def step(want_sigma=False):
+            (h.run_graph if graph else h.run)(want_sigma=False)
+            h.refine(refine_tol, want_sigma=False)
     for _ in range(warmup):
         step(want_sigma=False)
     torch.cuda.synchronize()
@@ -153,6 +163,7 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False):
     h.profile(False)
     sig_all = h.run()
     sigma = sig_all[0]
+    sigma_refined = h.refine(refine_tol)[0] if refine_tol is not None else None
     ranks = h.ranks()
     R = [W.cores[0].shape[0]] + [c.shape[3] for c in W.cores]
     I = [c.shape[1] for c in W.cores]
@@ -161,6 +172,7 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False):
     counts = instrumented_counts(h, R, I, J, W.K, W.q, esz)
     h.close()
     return {"seconds": t1 - t0, "steps": steps, "kernels": kern, "sigma": sigma,
+            "sigma_refined": sigma_refined,
             "sigma_all": sig_all, "ranks": ranks, "counts": counts, "batch": batch}
 
 
@@ -244,6 +256,14 @@ def main():
         res[p] = time_path(W, p, eps, args.steps, args.warmup)
         print(f"[bench] {p}: {res[p]['steps'] / res[p]['seconds']:.1f} solves/s", file=sys.stderr,
               flush=True)
+        if p == "bf16":
+            # BF16 solve followed by one FP32 power step + projection + solve
+            res["bf16+refine"] = time_path(W, p, eps, args.steps, args.warmup,
+                                           refine_tol=W.eps_by_precision["f32"])
+            print(f"[bench] bf16+refine: "
+                  f"{res['bf16+refine']['steps'] / res['bf16+refine']['seconds']:.1f} solves/s",
+                  file=sys.stderr, flush=True)
+    paths = precs + (["bf16+refine"] if "bf16" in precs else [])
 
     batched = None
     if args.batch > 0:
@@ -302,14 +322,18 @@ def main():
 
     exact = W.sigma_exact[: W.k]
     sig_err = {}
-    for p in precs:
-        s = res[p]["sigma"]
+
+    def final_sigma(p):
+        return res[p]["sigma_refined"] if res[p]["sigma_refined"] is not None else res[p]["sigma"]
+
+    for p in paths:
+        s = final_sigma(p)
         sig_err[p] = {"vs_prescribed": float(np.linalg.norm(s - exact) / np.linalg.norm(exact))}
     cpu = None
     if not args.no_cpu_baseline:
         cpu, osig = cpu_baseline(W, W.eps_by_precision["f64"], args.cpu_seconds)
-        for p in precs:
-            s = res[p]["sigma"]
+        for p in paths:
+            s = final_sigma(p)
             sig_err[p]["vs_oracle"] = float(np.linalg.norm(s - osig) / np.linalg.norm(osig))
     out = {
         "metric": METRIC,
@@ -337,7 +361,7 @@ def main():
         "sigma_err": sig_err,
         "paths": {p: {"solves_per_s": round(res[p]["steps"] / res[p]["seconds"], 3),
                       "ms_per_step": round(1e3 * res[p]["seconds"] / res[p]["steps"], 4),
-                      "basis_ranks": res[p]["ranks"]} for p in precs},
+                      "basis_ranks": res[p]["ranks"]} for p in paths},
         "device": device,
         "paper_context": "MATLAB on an i7-6700: 2.13 s per TNrSVD solve of a 2^15 x 2^15 "
                          "prescribed-spectrum MPO, rank-50, K=100, q=1 (a different size)",

@@ -22,8 +22,10 @@
  *   product rank   p = a * r + c  (a: A rank index, c: basis rank index)
  *
  * Precision.  Contractions run in the precision chosen in tnrsvd_opts
- * (FP64, FP32, or BF16 inputs with FP32 accumulation); every QR, SVD and
- * rank decision of the sweeps runs in FP64.
+ * (FP64; FP32 with FP32 accumulation; or BF16 storage of A, the basis and
+ * the products with FP32 accumulation); every QR, SVD and rank decision of
+ * the sweeps runs in FP64.  A BF16 solve can be refined by one FP32 power
+ * step (tnrsvd_refine).
  *
  * Threading.  A handle is bound to one HIP device and one stream (borrowed,
  * never synchronised except where noted).  Calls on one handle must not
@@ -56,7 +58,7 @@ typedef enum {
 typedef enum {
   TNRSVD_F64 = 0,          /* FP64 contractions                              */
   TNRSVD_F32 = 1,          /* FP32 contractions, FP32 accumulation           */
-  TNRSVD_BF16 = 2          /* BF16 operands on MFMA, FP32 accumulation       */
+  TNRSVD_BF16 = 2          /* BF16 storage (round to nearest even), FP32 acc */
 } tnrsvd_precision;
 
 /* One MPO matrix A of size (prod I) x (prod J) (Sec. 3). */
@@ -175,15 +177,33 @@ tnrsvd_status tnrsvd_run(tnrsvd_t h, double* sigma);
 tnrsvd_status tnrsvd_run_graph(tnrsvd_t h, double* sigma);
 
 /*
+ * tnrsvd_refine -- after a BF16 solve (tnrsvd_run, tnrsvd_run_graph or
+ * tnrsvd_solve on a handle created with TNRSVD_BF16): one FP32 power step
+ * from the BF16 basis Q -- Z = A^T Q, orthogonalize, Y = A Q_Z,
+ * orthogonalize -- then an FP32 projection and solve (the randomized
+ * subspace iteration of Algorithm 5.4 continued in FP32; refining a BF16
+ * result is not part of the paper).  A is used in FP32, as staged by
+ * tnrsvd_create before narrowing it to BF16.  Results (sigma, U, V, ranks,
+ * the basis, now FP32) replace those of the BF16 solve; the next
+ * tnrsvd_run or tnrsvd_run_graph starts again in BF16.
+ * round_tol: the rounding tolerance of the FP32 step (the handle's own
+ * tolerance, chosen above BF16 noise, is restored afterwards); the rank cap
+ * is the handle's.  sigma as in tnrsvd_solve.
+ * Errors: E_INVALID (round_tol negative or not finite); E_STATE (not a BF16
+ * handle, no BF16 solve, or already refined).
+ */
+tnrsvd_status tnrsvd_refine(tnrsvd_t h, double round_tol, double* sigma);
+
+/*
  * tnrsvd_get_factor -- borrow a device pointer to one core of a result.
  *   which 0: U (row space, last core (r, I, k)), available after solve;
  *   which 1: V (column space, last core (s, J, k)), after solve;
  *   which 2: the current basis (Q after an orthogonalize; last core (r,n,K));
  *   which 3: the first product Y = A Omega of the last run (last (R,I,K)),
  *            valid until the next tnrsvd_mult.
- * shape receives (r, n, r', 1) and *dtype TNRSVD_F64 or TNRSVD_F32: U and V
- * are FP64, the basis and Y are stored in the contraction type (FP32 for
- * the FP32 and BF16 modes).  The pointer stays valid until the next call
+ * shape receives (r, n, r', 1) and *dtype (a tnrsvd_precision code): U and
+ * V are FP64, the basis and Y are stored in the contraction type (BF16 in
+ * the BF16 mode; the basis is FP32 after tnrsvd_refine).  The pointer stays valid until the next call
  * on the handle other than a getter.  The call synchronises the stream
  * (ranks are read from the device).
  * Errors: E_INVALID (b, which or core out of range), E_STATE (not available).

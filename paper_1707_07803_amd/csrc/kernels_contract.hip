@@ -92,8 +92,11 @@ __global__ void k_omega(const MpoDesc* mpos, const CoreDesc* cores, uint64_t see
 
 template <typename T>
 __global__ void k_load_omega(const MpoDesc* mpos, const CoreDesc* cores, const double* om,
-                             int* xr, T* X) {
-  // Basis := Omega as rank-1 cores (1, J_i, 1) and (1, J_{d-1}, K).
+                             int* xr, T* X, int* err) {
+  // Basis := Omega as rank-1 cores (1, J_i, 1) and (1, J_{d-1}, K).  A new
+  // solve starts here, so the first block also clears the capacity flags
+  // (a kernel store, so the whole solve stays capturable in a graph).
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) err[0] = 0;
   const MpoDesc md = mpos[blockIdx.y];
   const int i = blockIdx.x;
   if (i >= md.d) return;
@@ -225,15 +228,21 @@ hipError_t launch_merge_pair(const double* Tin, const double* C, double* out, in
 
 hipError_t launch_convert_core(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
                                hipStream_t s) {
-  const int g = grid_for(n, 256, 65535);
-  if (in_dtype == 0 && out_dtype == 0)
-    k_convert<double, double><<<g, 256, 0, s>>>((const double*)in, (double*)out, n);
-  else if (in_dtype == 0 && out_dtype == 1)
-    k_convert<double, float><<<g, 256, 0, s>>>((const double*)in, (float*)out, n);
-  else if (in_dtype == 1 && out_dtype == 0)
-    k_convert<float, double><<<g, 256, 0, s>>>((const float*)in, (double*)out, n);
-  else
-    k_convert<float, float><<<g, 256, 0, s>>>((const float*)in, (float*)out, n);
+  if (n <= 0) return hipSuccess;
+  const int g = grid_for(n, 256, 4096);
+  auto go = [&](auto* ti, auto* to) {
+    using TI = std::remove_pointer_t<decltype(ti)>;
+    using TO = std::remove_pointer_t<decltype(to)>;
+    k_convert<TI, TO><<<g, 256, 0, s>>>((const TI*)in, (TO*)out, n);
+  };
+  auto out_as = [&](auto* ti) {
+    if (out_dtype == kF64) go(ti, (double*)nullptr);
+    else if (out_dtype == kF32) go(ti, (float*)nullptr);
+    else go(ti, (bf16*)nullptr);
+  };
+  if (in_dtype == kF64) out_as((double*)nullptr);
+  else if (in_dtype == kF32) out_as((float*)nullptr);
+  else out_as((bf16*)nullptr);
   return hipGetLastError();
 }
 
@@ -255,13 +264,12 @@ hipError_t launch_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch, u
 
 hipError_t launch_load_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch,
                              const double* om, int* xr, void* X, int dtype, int max_d,
-                             int64_t max_len, hipStream_t s) {
-  (void)max_len;
+                             int64_t max_len, int* err, hipStream_t s) {
   dim3 grid(max_d, batch);
-  if (dtype == 0)
-    k_load_omega<double><<<grid, 256, 0, s>>>(mpos, cores, om, xr, (double*)X);
-  else
-    k_load_omega<float><<<grid, 256, 0, s>>>(mpos, cores, om, xr, (float*)X);
+  by_dtype(dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
+    k_load_omega<T><<<grid, 256, 0, s>>>(mpos, cores, om, xr, (T*)X, err);
+  });
   return hipGetLastError();
 }
 
@@ -269,21 +277,15 @@ hipError_t launch_contract(const MpoDesc* mpos, const CoreDesc* cores, const int
                            int ncores, const int* xr, int* pr, const void* A, const void* X,
                            void* Z, int dtype, int op, int64_t max_out, int* err, hipStream_t s) {
   dim3 grid(grid_for(max_out, 256, 256), ncores);
-  if (dtype == 0) {
+  by_dtype(dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
     if (op == 0)
-      k_contract<double, 0><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const double*)A,
-                                                  (const double*)X, (double*)Z, err);
+      k_contract<T, 0><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const T*)A,
+                                             (const T*)X, (T*)Z, err);
     else
-      k_contract<double, 1><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const double*)A,
-                                                  (const double*)X, (double*)Z, err);
-  } else {
-    if (op == 0)
-      k_contract<float, 0><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const float*)A,
-                                                 (const float*)X, (float*)Z, err);
-    else
-      k_contract<float, 1><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const float*)A,
-                                                 (const float*)X, (float*)Z, err);
-  }
+      k_contract<T, 1><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const T*)A,
+                                             (const T*)X, (T*)Z, err);
+  });
   return hipGetLastError();
 }
 
@@ -291,12 +293,10 @@ hipError_t launch_copy_y0(const MpoDesc* mpos, const CoreDesc* cores, const int*
                           int ncores, const int* pr, const void* Z, void* Y0, int dtype,
                           int64_t max_out, hipStream_t s) {
   dim3 grid(grid_for(max_out, 256, 256), ncores);
-  if (dtype == 0)
-    k_copy_y0<double><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, pr, (const double*)Z,
-                                           (double*)Y0);
-  else
-    k_copy_y0<float><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, pr, (const float*)Z,
-                                          (float*)Y0);
+  by_dtype(dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
+    k_copy_y0<T><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, pr, (const T*)Z, (T*)Y0);
+  });
   return hipGetLastError();
 }
 
@@ -304,12 +304,10 @@ hipError_t launch_form_u(const MpoDesc* mpos, const CoreDesc* cores, const int* 
                          int ncores, const int* xr, const void* X, int dtype, const double* outs,
                          double* U, int64_t max_out, int* err, hipStream_t s) {
   dim3 grid(grid_for(max_out, 256, 256), ncores);
-  if (dtype == 0)
-    k_form_u<double><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, (const double*)X, outs, U,
-                                          err);
-  else
-    k_form_u<float><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, (const float*)X, outs, U,
-                                         err);
+  by_dtype(dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
+    k_form_u<T><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, (const T*)X, outs, U, err);
+  });
   return hipGetLastError();
 }
 

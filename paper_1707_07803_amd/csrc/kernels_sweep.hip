@@ -1123,17 +1123,13 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
                           double* L, double* tau, int* err, hipStream_t s) {
-  if (dtype == 0) {
-    k_rl_pass<double, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const double*)Z, Wd,
-                                               L, tau, err);
-    k_rl_pass<double, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const double*)Z, Wd,
-                                               L, tau, err);
-  } else {
-    k_rl_pass<float, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const float*)Z, Wd, L,
-                                              tau, err);
-    k_rl_pass<float, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const float*)Z, Wd, L,
-                                              tau, err);
-  }
+  by_dtype(dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
+    k_rl_pass<T, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,
+                                         err);
+    k_rl_pass<T, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,
+                                         err);
+  });
   return hipGetLastError();
 }
 
@@ -1142,12 +1138,11 @@ hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
                           const double* tau, double* scratch, void* Xout, int out_dtype,
                           double* outs, SweepOpts o, int64_t tcap, int64_t mcap_s, int64_t ucap,
                           int* err, hipStream_t s) {
-  if (out_dtype == 0)
-    k_lr_pass<double><<<batch, NT, 0, s>>>(mpos, cores, op, rho, ldm, xr, Wd, tau, scratch,
-                                            (double*)Xout, outs, o, tcap, mcap_s, ucap, err);
-  else
-    k_lr_pass<float><<<batch, NT, 0, s>>>(mpos, cores, op, rho, ldm, xr, Wd, tau, scratch,
-                                           (float*)Xout, outs, o, tcap, mcap_s, ucap, err);
+  by_dtype(out_dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
+    k_lr_pass<T><<<batch, NT, 0, s>>>(mpos, cores, op, rho, ldm, xr, Wd, tau, scratch, (T*)Xout,
+                                      outs, o, tcap, mcap_s, ucap, err);
+  });
   return hipGetLastError();
 }
 

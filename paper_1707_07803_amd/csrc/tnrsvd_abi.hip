@@ -52,7 +52,13 @@ struct tnrsvd_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int batch = 0;
-  int dtype = 0;         // contraction storage: 0 double, 1 float
+  int dtype = 0;         // contraction storage of A, X, Z: kF64, kF32 or kBF16
+  int y0_dtype = 0;      // storage of the Y0 slab (the creation precision)
+  // BF16 handles keep FP32 copies of A, X and Z for tnrsvd_refine; `refined`
+  // says the FP32 set is the active one (swapped into A, X, Z)
+  void *A32 = nullptr, *X32 = nullptr, *Z32 = nullptr;
+  bool refined = false;
+  int64_t x_elems = 0;
   tnrsvd_opts opts{};
   std::vector<MpoDesc> mh;
   std::vector<CoreDesc> ch;
@@ -110,6 +116,10 @@ tnrsvd_status dalloc(tnrsvd_s* h, P** out, size_t bytes) {
 void release(tnrsvd_s* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
+}
+
+size_t elem_size(int dt) {
+  return dt == kF64 ? sizeof(double) : (dt == kF32 ? sizeof(float) : sizeof(bf16));
 }
 
 tnrsvd_status dev_check(hipError_t e, const char* what) {
@@ -193,8 +203,6 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   if (!(o->round_tol >= 0.0) || !std::isfinite(o->round_tol))
     return fail(TNRSVD_E_INVALID, "round_tol must be finite and >= 0");
   if (o->max_rank < 0) return fail(TNRSVD_E_INVALID, "max_rank must be >= 0");
-  if (o->precision == TNRSVD_BF16)
-    return fail(TNRSVD_E_INVALID, "BF16 contractions are not available in this build");
 
   std::vector<int> merge(batch);
   for (int b = 0; b < batch; ++b) TRY(plan_mpo(mpos[b], K, &merge[b]));
@@ -204,7 +212,8 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   h->batch = batch;
   h->opts = *o;
   h->stream = (hipStream_t)o->stream;
-  h->dtype = (o->precision == TNRSVD_F64) ? 0 : 1;
+  h->dtype = o->precision == TNRSVD_F64 ? kF64 : (o->precision == TNRSVD_F32 ? kF32 : kBF16);
+  h->y0_dtype = h->dtype;
   (void)hipGetDevice(&h->device);
   const int64_t rmax = o->max_rank;
 
@@ -255,7 +264,9 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
       if (rmax > 0) cap = std::min<int64_t>(cap, rmax);
       // without a cap, ranks of the rounded products are bounded by R^(2q+2)
       int64_t g = 1;
-      for (int t = 0; t < 2 * o->q + 2; ++t) g = sat_mul(g, R[i]);
+      // (a BF16 handle plans one more power step for tnrsvd_refine)
+      const int qp = o->q + (o->precision == TNRSVD_BF16 ? 1 : 0);
+      for (int t = 0; t < 2 * qp + 2; ++t) g = sat_mul(g, R[i]);
       cap = std::min(cap, std::max<int64_t>(g, 1));
       if (cap > kHardCap) {
         delete h;
@@ -363,7 +374,8 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
                 "panels too large for one workgroup (rows %d, sorted vectors %d); lower max_rank",
                 vcap, scap);
   }
-  const size_t esz = h->dtype == 0 ? sizeof(double) : sizeof(float);
+  const size_t esz = elem_size(h->dtype);
+  h->x_elems = x_tot;
 
   // ---- allocation ---------------------------------------------------------
   tnrsvd_status st = TNRSVD_OK;
@@ -389,6 +401,11 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   ALLOC(h->X, esz * x_tot);
   ALLOC(h->Z, esz * z_tot);
   ALLOC(h->Y0, esz * y_tot);
+  if (h->dtype == kBF16) {
+    ALLOC(h->A32, sizeof(float) * a_tot);
+    ALLOC(h->X32, sizeof(float) * x_tot);
+    ALLOC(h->Z32, sizeof(float) * z_tot);
+  }
   ALLOC(h->W, sizeof(double) * w_tot);
   ALLOC(h->L, sizeof(double) * l_tot);
   ALLOC(h->tau, sizeof(double) * t_tot);
@@ -451,7 +468,10 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
     const MpoDesc& md = h->mh[b];
     const int m = merge[b];
     const int dm = md.d;
-    char* Abase = (char*)h->A;
+    // BF16 handles stage A in FP32 (kept for tnrsvd_refine) and narrow it below
+    const int sdt = h->dtype == kBF16 ? kF32 : h->dtype;
+    const size_t sesz = elem_size(sdt);
+    char* Abase = (char*)(h->dtype == kBF16 ? h->A32 : h->A);
     if (o->check_finite) {
       for (int i = 0; i < a.d && e == hipSuccess; ++i)
         e = launch_check_finite(a.core[i], a.dtype,
@@ -459,14 +479,14 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
     }
     for (int i = 0; i < dm - 1 && e == hipSuccess; ++i) {
       const CoreDesc& cd = h->ch[md.c0 + i];
-      e = launch_convert_core(a.core[i], a.dtype, Abase + esz * cd.a_off, h->dtype,
+      e = launch_convert_core(a.core[i], a.dtype, Abase + sesz * cd.a_off, sdt,
                               a.rank[i] * a.rows[i] * a.cols[i] * a.rank[i + 1], s);
     }
     const CoreDesc& cl = h->ch[md.c0 + dm - 1];
     const int f = a.d - m;
     if (m == 1) {
       if (e == hipSuccess)
-        e = launch_convert_core(a.core[f], a.dtype, Abase + esz * cl.a_off, h->dtype,
+        e = launch_convert_core(a.core[f], a.dtype, Abase + sesz * cl.a_off, sdt,
                                 a.rank[f] * a.rows[f] * a.cols[f] * a.rank[f + 1], s);
     } else {
       // T <- core f (FP64); repeatedly T <- merge(T, core j)
@@ -486,9 +506,11 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
         std::swap(cur, nxt);
       }
       if (e == hipSuccess)
-        e = launch_convert_core(cur, 0, Abase + esz * cl.a_off, h->dtype, ra * ti * tj * tb, s);
+        e = launch_convert_core(cur, 0, Abase + sesz * cl.a_off, sdt, ra * ti * tj * tb, s);
     }
   }
+  if (e == hipSuccess && h->dtype == kBF16)
+    e = launch_convert_core(h->A32, kF32, h->A, kBF16, a_tot, s);
   if (e == hipSuccess) e = launch_omega(h->mpos_d, h->cores_d, batch, o->seed, h->om, h->max_om, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(t0);
@@ -553,10 +575,20 @@ tnrsvd_status check_handle(tnrsvd_t h) {
   return TNRSVD_OK;
 }
 
+void restore_precision(tnrsvd_t h) {
+  if (!h->refined) return;
+  std::swap(h->A, h->A32);
+  std::swap(h->X, h->X32);
+  std::swap(h->Z, h->Z32);
+  h->dtype = kBF16;
+  h->refined = false;
+}
+
 tnrsvd_status load_omega(tnrsvd_t h) {
+  restore_precision(h);
   Timed tm(h, 4);
   hipError_t e = launch_load_omega(h->mpos_d, h->cores_d, h->batch, h->om, h->xr, h->X, h->dtype,
-                                   h->max_d, h->max_om, h->stream);
+                                   h->max_d, h->max_om, h->err, h->stream);
   TRY(dev_check(e, "load Omega"));
   h->space = kCol;
   h->first_product = true;
@@ -599,7 +631,7 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   so.rmax = (int)h->opts.max_rank;
   so.mode = mode;
   void* out = mode == 0 ? h->X : (void*)h->V;
-  const int odt = mode == 0 ? h->dtype : 0;
+  const int odt = mode == 0 ? h->dtype : kF64;
   int* rout = mode == 0 ? h->xr : h->vr;
   e = launch_lr_pass(h->mpos_d, h->cores_d, h->batch, op, h->rho, h->ldm, rout, h->W, h->tau,
                      h->scratch, out, odt, h->outs, so, h->tcap, h->mcap_s, h->ucap, h->err,
@@ -731,6 +763,7 @@ tnrsvd_status tnrsvd_run_graph(tnrsvd_t h, double* sigma) {
     }
     h->graph = g;
   }
+  restore_precision(h);
   // caller's stream -> replay on the capture stream -> caller's stream
   TRY(dev_check(hipEventRecord(h->gev[0], h->stream), "record event"));
   TRY(dev_check(hipStreamWaitEvent(h->gstream, h->gev[0], 0), "wait event"));
@@ -745,6 +778,38 @@ tnrsvd_status tnrsvd_run_graph(tnrsvd_t h, double* sigma) {
   h->y0_valid = true;
   if (sigma) TRY(read_sigma(h, sigma));
   return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_refine(tnrsvd_t h, double round_tol, double* sigma) {
+  TRY(check_handle(h));
+  if (!(round_tol >= 0.0) || !std::isfinite(round_tol))
+    return fail(TNRSVD_E_INVALID, "round_tol must be finite and >= 0");
+  if (h->dtype != kBF16 || h->refined)
+    return fail(TNRSVD_E_STATE, "refinement follows a BF16 solve on a BF16 handle");
+  if (!h->solved) return fail(TNRSVD_E_STATE, "no BF16 solve to refine");
+  // the basis Q of the BF16 solve, widened to FP32, becomes the starting basis
+  TRY(dev_check(launch_convert_core(h->X, kBF16, h->X32, kF32, h->x_elems, h->stream),
+                "widen the basis"));
+  std::swap(h->A, h->A32);
+  std::swap(h->X, h->X32);
+  std::swap(h->Z, h->Z32);
+  h->dtype = kF32;
+  h->refined = true;
+  h->space = kRow;
+  h->pending = -1;
+  h->projected = false;
+  h->solved = false;
+  h->first_product = false;
+  const double tol = h->opts.round_tol;
+  h->opts.round_tol = round_tol;
+  tnrsvd_status st = tnrsvd_mult(h, 1);
+  if (st == TNRSVD_OK) st = tnrsvd_orthogonalize(h);
+  if (st == TNRSVD_OK) st = tnrsvd_mult(h, 0);
+  if (st == TNRSVD_OK) st = tnrsvd_orthogonalize(h);
+  if (st == TNRSVD_OK) st = tnrsvd_project(h);
+  if (st == TNRSVD_OK) st = tnrsvd_solve(h, sigma);
+  h->opts.round_tol = tol;
+  return st;
 }
 
 tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merged) {
@@ -781,7 +846,7 @@ tnrsvd_status tnrsvd_get_factor(tnrsvd_t h, int b, int which, int core, const vo
     TRY(dev_check(hipMemcpy(r.data(), src + md.r0, sizeof(int) * (md.d + 1),
                             hipMemcpyDeviceToHost),
                   "copy ranks"));
-  const size_t esz = h->dtype == 0 ? sizeof(double) : sizeof(float);
+  const size_t esz = elem_size(h->dtype);
   int64_t n;
   if (which == 0) {
     n = cd.I;
@@ -797,8 +862,8 @@ tnrsvd_status tnrsvd_get_factor(tnrsvd_t h, int b, int which, int core, const vo
     shape[1] = cd.I;
     shape[2] = core == md.d - 1 ? md.K : cd.RA2;
     shape[3] = 1;
-    *dev_ptr = (const char*)h->Y0 + esz * cd.y0_off;
-    *dtype = h->dtype == 0 ? TNRSVD_F64 : TNRSVD_F32;
+    *dev_ptr = (const char*)h->Y0 + elem_size(h->y0_dtype) * cd.y0_off;
+    *dtype = h->y0_dtype;
     return TNRSVD_OK;
   }
   shape[0] = r[core];
@@ -813,7 +878,7 @@ tnrsvd_status tnrsvd_get_factor(tnrsvd_t h, int b, int which, int core, const vo
     *dtype = TNRSVD_F64;
   } else {
     *dev_ptr = (const char*)h->X + esz * cd.x_off;
-    *dtype = h->dtype == 0 ? TNRSVD_F64 : TNRSVD_F32;
+    *dtype = h->dtype;
   }
   return TNRSVD_OK;
 }
@@ -824,8 +889,7 @@ tnrsvd_status tnrsvd_copy_factor(tnrsvd_t h, int b, int which, int core, void* d
   int dt = 0;
   TRY(tnrsvd_get_factor(h, b, which, core, &src, shape, &dt));
   if (!dst) return fail(TNRSVD_E_INVALID, "null destination");
-  const size_t bytes = (size_t)(shape[0] * shape[1] * shape[2]) *
-                       (dt == TNRSVD_F64 ? sizeof(double) : sizeof(float));
+  const size_t bytes = (size_t)(shape[0] * shape[1] * shape[2]) * elem_size(dt);
   TRY(dev_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream),
                 "copy factor"));
   return dev_check(hipStreamSynchronize(h->stream), "synchronise");

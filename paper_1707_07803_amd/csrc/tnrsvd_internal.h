@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace tnr {
 
 // Per (MPO, merged core) static plan.
@@ -61,6 +63,40 @@ struct SweepOpts {
   int mode;          // 0: orthogonalise (QR of the last core), 1: solve (SVD)
 };
 
+// BF16 storage: the upper 16 bits of an FP32 (1 sign, 8 exponent, 7 fraction
+// bits).  FP32 -> BF16 rounds to nearest, ties to even; NaN stays a quiet NaN.
+// FP64 values are narrowed through FP32.  Arithmetic on it is always done in
+// FP32 or wider after an explicit conversion.
+struct bf16 {
+  unsigned short u;
+  bf16() = default;
+  __host__ __device__ explicit bf16(float f) : u(from_f32(f)) {}
+  __host__ __device__ explicit bf16(double d) : u(from_f32((float)d)) {}
+  __host__ __device__ explicit operator float() const {
+    return __builtin_bit_cast(float, (unsigned)u << 16);
+  }
+  __host__ __device__ explicit operator double() const { return (double)(float)(*this); }
+  __host__ __device__ static unsigned short from_f32(float f) {
+    unsigned x = __builtin_bit_cast(unsigned, f);
+    if ((x & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((x >> 16) | 0x40u);
+    x += 0x7fffu + ((x >> 16) & 1u);
+    return (unsigned short)(x >> 16);
+  }
+};
+
+// Storage codes of the contraction slabs (A, X, Z, Y0).
+constexpr int kF64 = 0, kF32 = 1, kBF16 = 2;
+
+// Host-side dispatch on a storage code: f receives a null pointer of the type.
+template <typename F>
+inline void by_dtype(int dt, F&& f) {
+  if (dt == kF64) f((double*)nullptr);
+  else if (dt == kF32) f((float*)nullptr);
+  else f((bf16*)nullptr);
+}
+template <typename P>
+using elem_t = std::remove_const_t<std::remove_pointer_t<P>>;
+
 constexpr int kSweepThreads = 512;
 constexpr int kMaxK = 256;
 constexpr int kSweepArena = 19456;   // doubles of static LDS per sweep workgroup
@@ -79,7 +115,7 @@ hipError_t launch_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch, u
                         double* om, int64_t max_len, hipStream_t s);
 hipError_t launch_load_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch,
                              const double* om, int* xr, void* X, int dtype, int max_d,
-                             int64_t max_len, hipStream_t s);
+                             int64_t max_len, int* err, hipStream_t s);
 hipError_t launch_contract(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
                            int ncores, const int* xr, int* pr, const void* A, const void* X,
                            void* Z, int dtype, int op, int64_t max_out, int* err, hipStream_t s);

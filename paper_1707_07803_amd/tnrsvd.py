@@ -23,7 +23,7 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16}
 # the C function names exported by the library, in header order
 EXPORTS = [
     "tnrsvd_create", "tnrsvd_mult", "tnrsvd_orthogonalize", "tnrsvd_project",
-    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_get_factor", "tnrsvd_copy_factor",
+    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_refine", "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
     "tnrsvd_last_error", "tnrsvd_version",
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_solve.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_run.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_run_graph.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
+    L.tnrsvd_refine.argtypes = [H, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_get_factor.argtypes = [H, I, I, I, ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I)]
     L.tnrsvd_copy_factor.argtypes = [H, I, I, I, ctypes.c_void_p]
@@ -198,6 +199,16 @@ class TNrSVD:
         _check(self._lib.tnrsvd_run(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out.reshape(self.batch, self.k)
 
+    def refine(self, round_tol: float = 0.0, want_sigma: bool = True) -> Optional[np.ndarray]:
+        """One FP32 power step + projection + solve from the basis of a BF16 solve."""
+        if not want_sigma:
+            _check(self._lib.tnrsvd_refine(self._h, float(round_tol), None))
+            return None
+        out = np.zeros(self.batch * self.k, dtype=np.float64)
+        _check(self._lib.tnrsvd_refine(self._h, float(round_tol),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(self.batch, self.k)
+
     def run_graph(self, want_sigma: bool = True) -> Optional[np.ndarray]:
         """tnrsvd_run captured once into a HIP graph, replayed on later calls."""
         if not want_sigma:
@@ -230,9 +241,8 @@ class TNrSVD:
             dt = ctypes.c_int()
             _check(self._lib.tnrsvd_get_factor(self._h, b, which, core, ctypes.byref(ptr), shape,
                                                ctypes.byref(dt)))
-            t = torch.empty((shape[0], shape[1], shape[2]),
-                            dtype=torch.float64 if dt.value == F64 else torch.float32,
-                            device="cuda")
+            tdt = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[dt.value]
+            t = torch.empty((shape[0], shape[1], shape[2]), dtype=tdt, device="cuda")
             _check(self._lib.tnrsvd_copy_factor(self._h, b, which, core, ctypes.c_void_p(t.data_ptr())))
             out.append(t)
         return out
