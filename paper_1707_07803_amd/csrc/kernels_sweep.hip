@@ -71,16 +71,19 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-// Householder QR with nonnegative diagonal of the m x n column-major X (ld m),
+// Householder QR with nonnegative diagonal of the m x n column-major X (ld m
+// unless given),
 // in place: R on and above the diagonal of the first min(m,n) rows, the
 // Householder vectors (unit leading entry implicit) below it, scalars in tau.
 // Each reflector maps its column x to +||x|| e_1, using Parlett's form of the
 // leading entry when x_1 > 0 so that no cancellation occurs.
-__device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double* red) {
+__device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double* red,
+                         int64_t ld = -1) {
   const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   const int kmax = m < n ? m : n;
+  if (ld < 0) ld = m;
   for (int j = 0; j < kmax; ++j) {
-    double* col = X + (int64_t)j * m;
+    double* col = X + (int64_t)j * ld;
     const double alpha = col[j];
     double s2 = 0.0;
     for (int r = j + 1 + tid; r < m; r += NT) {
@@ -119,7 +122,7 @@ __device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double
     if (tj != 0.0) {
       const int r0 = j & ~63;
       for (int c = j + 1 + w; c < n; c += NW) {
-        double* xc = X + (int64_t)c * m;
+        double* xc = X + (int64_t)c * ld;
         double part = 0.0;
         for (int r = r0 + lane; r < m; r += 64)
           if (r >= j) part += v[r] * xc[r];
@@ -131,6 +134,162 @@ __device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double
     }
     __syncthreads();
   }
+}
+
+// C (M x N) = beta C + alpha A (M x K) B (K x N) with FP64 accumulation, by
+// the whole workgroup.  Element (i, k) of A is A[i sai + k sak], (k, j) of B
+// is B[k sbk + j sbj] (type TB, widened to FP64) and (i, j) of C is
+// C[i sci + j scj]; C may be in global memory or LDS.  64 x 64 output tiles;
+// K goes through LDS 32 at a time, the next chunk's loads (clamped in-bounds
+// addresses, mapped so the unit-stride index runs across lanes) in flight
+// while the current one is multiplied; each thread owns a 4 x 2 block of a
+// tile.  beta == 0 never reads C.  `lds` holds 2 x 32 x 65 doubles.  Ends
+// with a barrier.
+constexpr int GK = 32, GLD = 65, GEMM_LDS = 2 * GK * GLD;
+template <typename TB>
+__device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int64_t sai,
+                        int64_t sak, const TB* B, int64_t sbk, int64_t sbj, double beta, double* C,
+                        int64_t sci, int64_t scj, double* lds) {
+  constexpr int NL = 64 * GK / NT;   // elements of each operand per thread and chunk
+  const int tid = threadIdx.x;
+  double* As = lds;             // As[k * GLD + i]
+  double* Bs = lds + GK * GLD;  // Bs[k * GLD + j]
+  const int ty = tid >> 5, tx = tid & 31;
+  const bool a_ifast = sai == 1, b_jfast = sbj == 1;
+  int ai[NL], ak[NL], bk[NL], bj[NL];
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    const int e = tid + t * NT;
+    ai[t] = a_ifast ? (e & 63) : (e / GK);
+    ak[t] = a_ifast ? (e >> 6) : (e % GK);
+    bj[t] = b_jfast ? (e & 63) : (e / GK);
+    bk[t] = b_jfast ? (e >> 6) : (e % GK);
+  }
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      double acc[4][2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = 0.0;
+      double av[NL], bv[NL];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+          const bool oka = i0 + ai[t] < M && k0 + ak[t] < K;
+          const double va = A[oka ? (int64_t)(i0 + ai[t]) * sai + (int64_t)(k0 + ak[t]) * sak : 0];
+          av[t] = oka ? va : 0.0;
+          const bool okb = j0 + bj[t] < N && k0 + bk[t] < K;
+          const double vb =
+              (double)B[okb ? (int64_t)(k0 + bk[t]) * sbk + (int64_t)(j0 + bj[t]) * sbj : 0];
+          bv[t] = okb ? vb : 0.0;
+        }
+      };
+      fetch(0);
+      for (int k0 = 0; k0 < K; k0 += GK) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+          As[ak[t] * GLD + ai[t]] = av[t];
+          Bs[bk[t] * GLD + bj[t]] = bv[t];
+        }
+        __syncthreads();
+        if (k0 + GK < K) fetch(k0 + GK);
+#pragma unroll 8
+        for (int k = 0; k < GK; ++k) {
+          const double b0 = Bs[k * GLD + tx], b1 = Bs[k * GLD + tx + 32];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double a = As[k * GLD + ty * 4 + r];
+            acc[r][0] += a * b0;
+            acc[r][1] += a * b1;
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int i = i0 + ty * 4 + r, j = j0 + tx + 32 * c;
+          if (i < M && j < N) {
+            double* cp = C + (int64_t)i * sci + (int64_t)j * scj;
+            *cp = beta == 0.0 ? alpha * acc[r][c] : beta * *cp + alpha * acc[r][c];
+          }
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// Blocked Householder QR (same output as wg_geqr2: R on and above the
+// diagonal, reflectors below it, tau) of the m x n column-major X (ld m), for
+// panels too large for registers.  Each block of QB columns is factorised by
+// wg_geqr2; its reflectors are applied to the trailing columns at once in the
+// compact WY form H_0 ... H_{b-1} = I - V T V^T (T upper triangular):
+//   C <- C - V T^T (V^T C),  two GEMMs.
+// A panel that fits in lds (lds_cap doubles, at least GEMM_LDS) is factorised
+// there; otherwise in place in global memory with v as the LDS vector.
+// ws: m QB + 2 QB n doubles of global workspace; Ts, Gs: QB x QB doubles each
+// in LDS outside lds.
+constexpr int QB = 16;
+__device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double* red, double* ws,
+                         double* lds, int64_t lds_cap, double* Ts, double* Gs) {
+  const int tid = threadIdx.x;
+  const int kmax = m < n ? m : n;
+  for (int j0 = 0; j0 < kmax; j0 += QB) {
+    const int jb = (kmax - j0) < QB ? (kmax - j0) : QB;
+    const int mp = m - j0;
+    double* P0 = X + (int64_t)j0 * m + j0;   // panel (mp x jb), ld m
+    const int nc = n - j0 - jb;
+    double* Vp = ws;                          // explicit V (mp x jb, column-major)
+    if ((int64_t)mp * (jb + 1) <= lds_cap) {
+      // factorise the panel in LDS (v in lds[0, mp), panel after it, ld mp)
+      double* PL = lds + mp;
+      for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
+        const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
+        PL[e] = P0[(int64_t)c * m + r];
+      }
+      __syncthreads();
+      wg_geqr2(PL, mp, jb, tau + j0, lds, red, mp);
+      for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
+        const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
+        P0[(int64_t)c * m + r] = PL[e];
+        if (nc > 0) Vp[e] = r > c ? PL[e] : (r == c ? 1.0 : 0.0);
+      }
+      __syncthreads();
+      if (nc <= 0) continue;
+    } else {
+      wg_geqr2(P0, mp, jb, tau + j0, v, red, m);
+      if (nc <= 0) continue;
+      for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
+        const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
+        Vp[e] = r > c ? P0[(int64_t)c * m + r] : (r == c ? 1.0 : 0.0);
+      }
+      __syncthreads();
+    }
+    // G = V^T V (jb x jb, row-major in LDS), then T by the forward recurrence
+    //   T_ii = tau_i,  T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
+    wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QB, 1, lds);
+    if (tid < 64) {
+      for (int i = 0; i < jb; ++i) {
+        const double ti = tau[j0 + i];
+        if (tid < i) {
+          double acc = 0.0;
+          for (int c = tid; c < i; ++c) acc += Ts[tid * QB + c] * Gs[c * QB + i];
+          Ts[tid * QB + i] = -ti * acc;
+        } else if (tid < QB) {
+          Ts[tid * QB + i] = tid == i ? ti : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    double* C = X + (int64_t)(j0 + jb) * m + j0;   // trailing block (mp x nc), ld m
+    double* Wm = ws + (int64_t)mp * QB;             // jb x nc, row-major
+    double* Wm2 = Wm + (int64_t)QB * n;             // jb x nc, row-major
+    wg_gemm<double>(jb, nc, mp, 1.0, Vp, mp, 1, C, 1, m, 0.0, Wm, nc, 1, lds);      // V^T C
+    wg_gemm<double>(jb, nc, jb, 1.0, Ts, 1, QB, Wm, nc, 1, 0.0, Wm2, nc, 1, lds);   // T^T W
+    wg_gemm<double>(mp, nc, jb, -1.0, Vp, 1, mp, Wm2, nc, 1, 1.0, C, 1, m, lds);    // C -= V W
+  }
+  __syncthreads();
 }
 
 // Y <- H_0 H_1 ... H_{k-1} Y for the m x s column-major Y (ld m), with the
@@ -166,11 +325,21 @@ __device__ void wg_apply_q(const double* V, const double* tau, int m, int k, dou
 // accumulate the rotations in U (nv x nv, column-major).  Pairs follow the
 // round-robin (circle) ordering so a round's pairs are disjoint and each is
 // handled by one wave.  Returns the number of sweeps.
-__device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* flag) {
+__device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* flag, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   for (int t = tid; t < nv * nv; t += NT) U[t] = ((t % nv) == (t / nv)) ? 1.0 : 0.0;
   __syncthreads();
   if (nv < 2) return 0;
+  // Vectors whose norm is below 16 eps |B|_F (rotations keep |B|_F) are
+  // rounding noise, e.g. the null space when nv > len; rotating them cannot
+  // change any singular value above that level, and their relative
+  // orthogonality would never converge, so pairs with one are left alone.
+  double part = 0.0;
+  for (int e = tid; e < nv * len; e += NT) {
+    const double x = B[(int64_t)(e / len) * ldb + e % len];
+    part += x * x;
+  }
+  const double tiny = 256.0 * 4.930380657631324e-32 * block_sum(part, red);
   // Convergence threshold len * eps on |<b_p,b_q>| / (|b_p| |b_q|): above the
   // rounding level of the computed inner products, so a converged pair is
   // never rotated again and the sweep count stays small.
@@ -208,7 +377,7 @@ __device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* fl
         a = wave_sum(a);
         b = wave_sum(b);
         c = wave_sum(c);
-        if (a == 0.0 || b == 0.0 || fabs(c) <= tol * sqrt(a) * sqrt(b)) continue;
+        if (a <= tiny || b <= tiny || fabs(c) <= tol * sqrt(a) * sqrt(b)) continue;
         const double zeta = (b - a) / (2.0 * c);
         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -607,7 +776,7 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
     const int Pn = pr[md.r0 + i + 1];
     const int m = n * rnext;
     if (P < 1 || P > cd.RA * cd.xcap || Pn < 1 || Pn > cd.RA2 * cd.xcap2 || rnext > Pn ||
-        m > ARENA - 64) {
+        m > ARENA - 64 - 2 * QB * QB) {
       if (tid == 0) atomicOr(err, 4);
       return;
     }
@@ -705,21 +874,17 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
         Xt[o] = (double)Zc[(int64_t)p * m + jj];
       }
     } else {
-      // Zt^T[(y, f), p] = sum_{q >= f} Z[p, y, q] R_{i+1}[f, q]   (L_{i+1} = R_{i+1}^T)
-      for (int64_t o = tid; o < tot; o += NT) {
-        const int p = (int)(o / m), jj = (int)(o % m);
-        const int y = jj / rnext, f = jj % rnext;
-        const T* zr = Zc + ((int64_t)p * n + y) * Pn;
-        const double* rr = Rn + (int64_t)f * Pn;
-        double acc = 0.0;
-        for (int qq = f; qq < Pn; ++qq) acc += (double)zr[qq] * rr[qq];
-        Xt[o] = acc;
-      }
+      // Zt^T[(y, f), p] = sum_q R_{i+1}[f, q] Z[p, y, q]   (L_{i+1} = R_{i+1}^T; R is
+      // stored upper triangular with zeros below), one GEMM per y
+      for (int y = 0; y < n; ++y)
+        wg_gemm<T>(rnext, P, Pn, 1.0, Rn, Pn, 1, Zc + (int64_t)y * Pn, 1, (int64_t)n * Pn, 0.0,
+                   Xt + (int64_t)y * rnext, 1, m, arena);
     }
     if (tid == 0) ldm[md.r0 + i] = rnext;
     __syncthreads();
     if (i == 0) break;
-    wg_geqr2(Xt, m, P, tau + cd.tau_off, vb, red);
+    wg_geqrf(Xt, m, P, tau + cd.tau_off, vb, red, Xt + tot, arena, ARENA - 64 - 2 * QB * QB,
+             arena + ARENA - 32 - 2 * QB * QB, arena + ARENA - 32 - QB * QB);
     const int k = m < P ? m : P;
     double* Ro = L + cd.l_off;
     for (int64_t o = tid; o < (int64_t)k * P; o += NT) {
@@ -1022,7 +1187,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
     const int nv = s * n;
     if (i < d - 1) {
       double* U = (nvg * nvg <= LR_UB) ? Ub : SL.U;
-      wg_jacobi(M, nv, rn, ld, U, ibuf);
+      wg_jacobi(M, nv, rn, ld, U, ibuf, red);
       wg_norms_sorted(M, nv, rn, ld, sig, perm, nrmb);
       if (tid == 0) {
         const int kk = nv < rn ? nv : rn;
@@ -1097,7 +1262,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       } else {
         // economical SVD (Algorithm 5.3, mirrored): C W = X diag(sigma)
         double* Wr = ((int64_t)K * K <= LR_VB) ? Vb : SL.U + ck;
-        wg_jacobi(C, K, nv, nv, Wr, ibuf);
+        wg_jacobi(C, K, nv, nv, Wr, ibuf, red);
         wg_norms_sorted(C, K, nv, nv, sig, perm, nrmb);
         for (int k = tid; k < K; k += NT) sgn[k] = sign_of_max(C + (int64_t)perm[k] * nv, nv, 1);
         __syncthreads();
