@@ -48,6 +48,7 @@ __all__ = [
     "lq_nonneg", "qr_nonneg", "svd_signfix", "choose_rank",
     "round_sweep", "tnrsvd", "TNrSVDResult", "dense_rsvd",
     "tnrsvd_paper_orientation", "reverse_mpo",
+    "merge_tail_adjoint", "sigma_sum_grad",
 ]
 
 # --------------------------------------------------------------------------
@@ -635,3 +636,65 @@ def tnrsvd_paper_orientation(A_cores: Sequence[np.ndarray], k: int, p: int,
         Q, _ = _paper_round_orth(times(Qz, False), eps, rmax, "qr")
     _, S = _paper_round_orth(times(Q, True), eps, rmax, "svd")
     return S[:k]
+
+
+# --------------------------------------------------------------------------
+# Gradient of the sum of the computed singular values (not in the paper)
+# --------------------------------------------------------------------------
+
+def merge_tail_adjoint(tail: Sequence[np.ndarray], dM: np.ndarray) -> List[np.ndarray]:
+    """Adjoint of ``merge_tail`` over the cores ``tail``: given dL/dM for the
+    merged core M, return dL/d(each core of ``tail``) by the chain rule through
+    the pairwise merges (the forward chain is recomputed)."""
+    tail = [np.asarray(c, dtype=np.float64) for c in tail]
+    chain = [tail[0]]
+    for c in tail[1:]:
+        T = chain[-1]
+        a, I1, J1, _ = T.shape
+        _, I2, J2, b = c.shape
+        chain.append(np.einsum("axyr,rXYb->aXxYyb", T, c).reshape(a, I2 * I1, J2 * J1, b))
+    grads = [None] * len(tail)
+    dT = np.asarray(dM, dtype=np.float64)
+    for j in range(len(tail) - 1, 0, -1):
+        T, c = chain[j - 1], tail[j]
+        a, I1, J1, _ = T.shape
+        _, I2, J2, b = c.shape
+        dN = dT.reshape(a, I2, I1, J2, J1, b)
+        grads[j] = np.einsum("aXxYyb,axyr->rXYb", dN, T)
+        dT = np.einsum("aXxYyb,rXYb->axyr", dN, c)
+    grads[0] = dT
+    return grads
+
+
+def sigma_sum_grad(A_cores: Sequence[np.ndarray], res: "TNrSVDResult",
+                   dsigma: Optional[np.ndarray] = None) -> List[np.ndarray]:
+    """Gradient of L = sum_j dsigma_j sigma_j (dsigma = 1 by default) with
+    respect to the original cores of A, with the computed singular subspaces
+    held fixed: dL/dA = sum_j dsigma_j u_j v_j^T, written into each core by
+    contracting U and V with A's other cores (left environments E_i and right
+    environments F_i), then through the merge of the trailing cores.
+
+    This is the derivative of sum_j dsigma_j u_j^T A v_j at fixed (u_j, v_j);
+    it equals the derivative of the pipeline's output (and of the exact
+    singular values) when the subspace is exact, e.g. rank(A) <= K with no
+    truncation.  Parity: pinned by the dense bilinear form and, in the exact
+    case, by finite differences of the whole pipeline and by LAPACK's
+    singular vectors.
+    """
+    A = [np.asarray(c, dtype=np.float64) for c in A_cores]
+    M = res.merged
+    dm = len(M)
+    U, V = res.U, res.V
+    k = U[-1].shape[2]
+    w = np.ones(k) if dsigma is None else np.asarray(dsigma, dtype=np.float64)
+    E = [np.ones((1, 1, 1))]
+    for i in range(dm - 1):
+        E.append(np.einsum("ras,rxR,axyb,syS->RbS", E[i], U[i], M[i], V[i], optimize=True))
+    F = np.zeros((k, 1, k))
+    F[np.arange(k), 0, np.arange(k)] = w
+    gm = [None] * dm
+    for i in range(dm - 1, -1, -1):
+        gm[i] = np.einsum("ras,rxR,syS,RbS->axyb", E[i], U[i], V[i], F, optimize=True)
+        F = np.einsum("rxR,axyb,syS,RbS->ras", U[i], M[i], V[i], F, optimize=True)
+    m = len(A) - dm + 1
+    return gm[:-1] + merge_tail_adjoint(A[dm - 1:], gm[-1]) if m > 1 else gm
