@@ -195,6 +195,26 @@ tnrsvd_status tnrsvd_run_graph(tnrsvd_t h, double* sigma);
 tnrsvd_status tnrsvd_refine(tnrsvd_t h, double round_tol, double* sigma);
 
 /*
+ * tnrsvd_backward -- gradient of L = sum_{j<k} dsigma_j sigma_j with respect
+ * to the ORIGINAL (unmerged) cores of every MPO, with the singular vectors of
+ * the last solve held fixed: dL/dA = sum_j dsigma_j u_j v_j^T, written into
+ * each core by left and right environments of U, A and V (formed here, not
+ * kept from the solve) and, for the trailing cores that tnrsvd_create merged,
+ * by the adjoint of the merge.  Differentiation is not part of the paper; this
+ * is the derivative of sum_j dsigma_j u_j^T A v_j at fixed (u_j, v_j), which
+ * equals the derivative of the solve's output when the computed subspace is
+ * exact (rank(A) <= K and nothing truncated).
+ * dsigma: HOST array of batch*k doubles, or NULL for all ones.
+ * dcores: DEVICE pointers, one per original core (MPO 0's cores in order,
+ *   then MPO 1's, ...); each receives the R x I x J x R' gradient, C order,
+ *   in the dtype that MPO's cores had in tnrsvd_create.
+ * The first call allocates the workspace; the call synchronises the stream.
+ * Errors: E_INVALID (dcores NULL); E_STATE (no solve yet); E_NOMEM; E_SHAPE
+ * (a rank beyond its planned capacity).
+ */
+tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores);
+
+/*
  * tnrsvd_get_factor -- borrow a device pointer to one core of a result.
  *   which 0: U (row space, last core (r, I, k)), available after solve;
  *   which 1: V (column space, last core (s, J, k)), after solve;

@@ -687,14 +687,20 @@ def sigma_sum_grad(A_cores: Sequence[np.ndarray], res: "TNrSVDResult",
     U, V = res.U, res.V
     k = U[-1].shape[2]
     w = np.ones(k) if dsigma is None else np.asarray(dsigma, dtype=np.float64)
+    # every environment update is three two-operand contractions
     E = [np.ones((1, 1, 1))]
     for i in range(dm - 1):
-        E.append(np.einsum("ras,rxR,axyb,syS->RbS", E[i], U[i], M[i], V[i], optimize=True))
+        t1 = np.einsum("ras,rxR->axsR", E[i], U[i])
+        t2 = np.einsum("axsR,axyb->ysRb", t1, M[i])
+        E.append(np.einsum("ysRb,syS->RbS", t2, V[i]))
     F = np.zeros((k, 1, k))
     F[np.arange(k), 0, np.arange(k)] = w
     gm = [None] * dm
     for i in range(dm - 1, -1, -1):
-        gm[i] = np.einsum("ras,rxR,syS,RbS->axyb", E[i], U[i], V[i], F, optimize=True)
-        F = np.einsum("rxR,axyb,syS,RbS->ras", U[i], M[i], V[i], F, optimize=True)
+        s1 = np.einsum("syS,RbS->Rbsy", V[i], F)
+        t1 = np.einsum("ras,rxR->axsR", E[i], U[i])
+        gm[i] = np.einsum("axsR,Rbsy->axyb", t1, s1)
+        s2 = np.einsum("axyb,Rbsy->Raxs", M[i], s1)
+        F = np.einsum("rxR,Raxs->ras", U[i], s2)
     m = len(A) - dm + 1
     return gm[:-1] + merge_tail_adjoint(A[dm - 1:], gm[-1]) if m > 1 else gm

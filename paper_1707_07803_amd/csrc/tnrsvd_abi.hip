@@ -14,6 +14,8 @@
 #include <vector>
 
 #include "../../include/tnrsvd.h"
+#include <array>
+
 #include "tnrsvd_internal.h"
 
 
@@ -95,6 +97,18 @@ struct tnrsvd_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipEvent_t gev[2] = {nullptr, nullptr};
+  // backward: input dtype, original core count and merge count per MPO; the
+  // original trailing cores that were merged (FP64, kept for the merge
+  // adjoint); gradient buffers planned at the first tnrsvd_backward
+  std::vector<int> in_dtype, d_orig, mcount;
+  std::vector<std::vector<int64_t>> tail_off;
+  std::vector<std::vector<std::array<int, 4>>> tail_shape;
+  double* tail = nullptr;
+  bool grad_ready = false;
+  GradMpo* gm_d = nullptr;
+  int64_t* eoff_d = nullptr;
+  double *gws = nullptr, *gG = nullptr, *gw = nullptr, *gchain = nullptr;
+  int64_t a_elems = 0, chain_cap = 0;
 };
 
 namespace {
@@ -206,6 +220,19 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
 
   std::vector<int> merge(batch);
   for (int b = 0; b < batch; ++b) TRY(plan_mpo(mpos[b], K, &merge[b]));
+  // original trailing cores kept in FP64 for the merge adjoint of tnrsvd_backward
+  std::vector<std::vector<int64_t>> tail_off(batch);
+  std::vector<std::vector<std::array<int, 4>>> tail_shape(batch);
+  int64_t tail_tot = 0;
+  for (int b = 0; b < batch; ++b) {
+    const tnrsvd_mpo& a = mpos[b];
+    if (merge[b] < 2) continue;
+    for (int j = a.d - merge[b]; j < a.d; ++j) {
+      tail_off[b].push_back(tail_tot);
+      tail_shape[b].push_back({(int)a.rank[j], (int)a.rows[j], (int)a.cols[j], (int)a.rank[j + 1]});
+      tail_tot += a.rank[j] * a.rows[j] * a.cols[j] * a.rank[j + 1];
+    }
+  }
 
   tnrsvd_s* h = new (std::nothrow) tnrsvd_s();
   if (!h) return fail(TNRSVD_E_NOMEM, "host allocation failed");
@@ -213,6 +240,13 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   h->opts = *o;
   h->stream = (hipStream_t)o->stream;
   h->dtype = o->precision == TNRSVD_F64 ? kF64 : (o->precision == TNRSVD_F32 ? kF32 : kBF16);
+  for (int b = 0; b < batch; ++b) {
+    h->in_dtype.push_back(mpos[b].dtype == TNRSVD_F64 ? kF64 : kF32);
+    h->d_orig.push_back(mpos[b].d);
+    h->mcount.push_back(merge[b]);
+  }
+  h->tail_off = tail_off;
+  h->tail_shape = tail_shape;
   h->y0_dtype = h->dtype;
   (void)hipGetDevice(&h->device);
   const int64_t rmax = o->max_rank;
@@ -416,6 +450,8 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   ALLOC(h->om, sizeof(double) * om_tot);
   ALLOC(h->U, sizeof(double) * x_tot);
   ALLOC(h->V, sizeof(double) * x_tot);
+  ALLOC(h->tail, sizeof(double) * tail_tot);
+  h->a_elems = a_tot;
 #undef ALLOC
   hipStream_t s = h->stream;
   auto fail_dev = [&](hipError_t e, const char* what) {
@@ -491,6 +527,9 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
         e = launch_convert_core(a.core[f], a.dtype, Abase + sesz * cl.a_off, sdt,
                                 a.rank[f] * a.rows[f] * a.cols[f] * a.rank[f + 1], s);
     } else {
+      for (int j = f; j < a.d && e == hipSuccess; ++j)
+        e = launch_convert_core(a.core[j], a.dtype, h->tail + h->tail_off[b][j - f], kF64,
+                                a.rank[j] * a.rows[j] * a.cols[j] * a.rank[j + 1], s);
       // T <- core f (FP64); repeatedly T <- merge(T, core j)
       int64_t ra = a.rank[f], ti = a.rows[f], tj = a.cols[f], tb = a.rank[f + 1];
       if (e == hipSuccess) e = launch_convert_core(a.core[f], a.dtype, t0, 0, ra * ti * tj * tb, s);
@@ -812,6 +851,149 @@ tnrsvd_status tnrsvd_refine(tnrsvd_t h, double round_tol, double* sigma) {
   if (st == TNRSVD_OK) st = tnrsvd_solve(h, sigma);
   h->opts.round_tol = tol;
   return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of the backward pass, planned from the rank capacities at its first
+// call: per MPO the left environments E_0 .. E_{d'-1} and five temporaries;
+// the merged-core gradient slab; the weights; the merge-adjoint chain.
+tnrsvd_status plan_grad(tnrsvd_t h) {
+  if (h->grad_ready) return TNRSVD_OK;
+  std::vector<GradMpo> gm(h->batch);
+  std::vector<int64_t> eoff(h->ncores);
+  int64_t tot = 0;
+  h->chain_cap = 1;
+  for (int b = 0; b < h->batch; ++b) {
+    const MpoDesc& md = h->mh[b];
+    int64_t tmp = 1;
+    for (int i = 0; i < md.d; ++i) {
+      const CoreDesc& cd = h->ch[md.c0 + i];
+      const int64_t l = cd.xcap, r = cd.xcap2, n = std::max(cd.I, cd.J);
+      eoff[md.c0 + i] = tot;
+      tot += l * cd.RA * l;
+      tmp = std::max({tmp, (int64_t)cd.RA * n * l * r, (int64_t)cd.RA2 * n * l * r,
+                      l * cd.RA * l, r * cd.RA2 * r});
+    }
+    gm[b].tmp0 = tot;
+    gm[b].tmpcap = tmp;
+    tot += 5 * tmp;
+    if (h->mcount[b] >= 2) {
+      // chain T_1 .. T_{m-2}, two ping-pong gradients and one core gradient
+      const auto& sh = h->tail_shape[b];
+      int64_t chain = 0, big = 0, cmax = 0, I1 = sh[0][1], J1 = sh[0][2];
+      big = (int64_t)sh[0][0] * I1 * J1 * sh[0][3];
+      for (size_t j = 1; j < sh.size(); ++j) {
+        I1 *= sh[j][1];
+        J1 *= sh[j][2];
+        const int64_t tj = (int64_t)sh[0][0] * I1 * J1 * sh[j][3];
+        if (j + 1 < sh.size()) chain += tj;
+        big = std::max(big, tj);
+      }
+      for (const auto& c : sh) cmax = std::max<int64_t>(cmax, (int64_t)c[0] * c[1] * c[2] * c[3]);
+      h->chain_cap = std::max(h->chain_cap, chain + 2 * big + cmax);
+    }
+  }
+  tnrsvd_status st = TNRSVD_OK;
+  if ((st = dalloc(h, &h->gm_d, sizeof(GradMpo) * h->batch)) != TNRSVD_OK) return st;
+  if ((st = dalloc(h, &h->eoff_d, sizeof(int64_t) * h->ncores)) != TNRSVD_OK) return st;
+  if ((st = dalloc(h, &h->gws, sizeof(double) * tot)) != TNRSVD_OK) return st;
+  if ((st = dalloc(h, &h->gG, sizeof(double) * h->a_elems)) != TNRSVD_OK) return st;
+  if ((st = dalloc(h, &h->gw, sizeof(double) * h->batch * h->opts.k)) != TNRSVD_OK) return st;
+  if ((st = dalloc(h, &h->gchain, sizeof(double) * h->chain_cap)) != TNRSVD_OK) return st;
+  TRY(dev_check(hipMemcpyAsync(h->gm_d, gm.data(), sizeof(GradMpo) * h->batch,
+                               hipMemcpyHostToDevice, h->stream), "copy gradient plan"));
+  TRY(dev_check(hipMemcpyAsync(h->eoff_d, eoff.data(), sizeof(int64_t) * h->ncores,
+                               hipMemcpyHostToDevice, h->stream), "copy gradient plan"));
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  h->grad_ready = true;
+  return TNRSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores) {
+  TRY(check_handle(h));
+  if (!dcores) return fail(TNRSVD_E_INVALID, "null gradient pointer array");
+  if (!h->solved) return fail(TNRSVD_E_STATE, "no solve to differentiate");
+  TRY(plan_grad(h));
+  const int k = h->opts.k;
+  std::vector<double> w((size_t)h->batch * k, 1.0);
+  if (dsigma) std::copy(dsigma, dsigma + w.size(), w.begin());
+  TRY(dev_check(hipMemcpyAsync(h->gw, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice,
+                               h->stream), "copy weights"));
+  TRY(dev_check(launch_grad_env(h->mpos_d, h->cores_d, h->gm_d, h->eoff_d, h->batch, h->xr, h->vr,
+                                h->A, h->dtype, h->U, h->V, h->gw, k, h->gws, h->gG, h->err,
+                                h->stream), "environment gradient"));
+  int base = 0;
+  for (int b = 0; b < h->batch; ++b) {
+    const MpoDesc& md = h->mh[b];
+    const int odt = h->in_dtype[b];
+    for (int i = 0; i + 1 < md.d; ++i) {
+      const CoreDesc& cd = h->ch[md.c0 + i];
+      TRY(dev_check(launch_convert_core(h->gG + cd.a_off, kF64, dcores[base + i], odt,
+                                        (int64_t)cd.RA * cd.I * cd.J * cd.RA2, h->stream),
+                    "write gradient"));
+    }
+    const CoreDesc& cl = h->ch[md.c0 + md.d - 1];
+    const int m = h->mcount[b];
+    const int f = h->d_orig[b] - m;   // first merged original core
+    if (m < 2) {
+      TRY(dev_check(launch_convert_core(h->gG + cl.a_off, kF64, dcores[base + f], odt,
+                                        (int64_t)cl.RA * cl.I * cl.J * cl.RA2, h->stream),
+                    "write gradient"));
+    } else {
+      // recompute the merge chain T_0 = P_0, T_j = merge(T_{j-1}, P_j), then run it backwards
+      const auto& sh = h->tail_shape[b];
+      const auto& off = h->tail_off[b];
+      std::vector<const double*> T(m);
+      std::vector<int64_t> TI(m), TJ(m);
+      T[0] = h->tail + off[0];
+      TI[0] = sh[0][1];
+      TJ[0] = sh[0][2];
+      double* cur = h->gchain;
+      for (int j = 1; j < m; ++j) {
+        TI[j] = TI[j - 1] * sh[j][1];
+        TJ[j] = TJ[j - 1] * sh[j][2];
+        if (j + 1 < m) {
+          TRY(dev_check(launch_merge_pair(T[j - 1], h->tail + off[j], cur, sh[0][0], (int)TI[j - 1],
+                                          (int)TJ[j - 1], sh[j][0], sh[j][1], sh[j][2], sh[j][3],
+                                          h->stream), "recompute merge"));
+          T[j] = cur;
+          cur += (int64_t)sh[0][0] * TI[j] * TJ[j] * sh[j][3];
+        }
+      }
+      int64_t big = 0;
+      for (int j = 0; j < m; ++j) big = std::max(big, (int64_t)sh[0][0] * TI[j] * TJ[j] * sh[j][3]);
+      double* pp[2] = {cur, cur + big};
+      double* dC = cur + 2 * big;
+      const double* dT = h->gG + cl.a_off;
+      for (int j = m - 1; j >= 1; --j) {
+        double* out = pp[j & 1];
+        TRY(dev_check(launch_merge_pair_bwd(T[j - 1], h->tail + off[j], dT, out, dC, sh[0][0],
+                                            (int)TI[j - 1], (int)TJ[j - 1], sh[j][0], sh[j][1],
+                                            sh[j][2], sh[j][3], h->stream), "merge adjoint"));
+        TRY(dev_check(launch_convert_core(dC, kF64, dcores[base + f + j], odt,
+                                          (int64_t)sh[j][0] * sh[j][1] * sh[j][2] * sh[j][3],
+                                          h->stream), "write gradient"));
+        dT = out;
+      }
+      TRY(dev_check(launch_convert_core(dT, kF64, dcores[base + f], odt,
+                                        (int64_t)sh[0][0] * sh[0][1] * sh[0][2] * sh[0][3],
+                                        h->stream), "write gradient"));
+    }
+    base += h->d_orig[b];
+  }
+  int flags[4] = {0, 0, 0, 0};
+  TRY(dev_check(hipMemcpyAsync(flags, h->err, sizeof(flags), hipMemcpyDeviceToHost, h->stream),
+                "copy error flags"));
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  if (flags[0] & 4) return fail(TNRSVD_E_SHAPE, "a kernel met shapes beyond its planned capacity");
+  return TNRSVD_OK;
 }
 
 tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merged) {

@@ -104,6 +104,12 @@ constexpr int kSortCap = 990;        // largest panel row count the sweep sorts
 
 }  // namespace tnr
 
+// Gradient workspace of one MPO: five temporaries of tmpcap doubles from tmp0.
+struct GradMpo {
+  int64_t tmp0;
+  int64_t tmpcap;
+};
+
 // Launchers implemented in the .hip sources, called from the ABI layer.
 namespace tnr {
 hipError_t launch_merge_pair(const double* Tin, const double* C, double* out, int a, int I1, int J1,
@@ -133,4 +139,12 @@ hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
 hipError_t launch_form_u(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
                          int ncores, const int* xr, const void* X, int dtype, const double* outs,
                          double* U, int64_t max_out, int* err, hipStream_t s);
+hipError_t launch_grad_env(const MpoDesc* mpos, const CoreDesc* cores, const GradMpo* gm,
+                           const int64_t* eoff, int batch, const int* xr, const int* vr,
+                           const void* A, int dtype, const double* U, const double* V,
+                           const double* w, int k, double* ws, double* G, int* err,
+                           hipStream_t s);
+hipError_t launch_merge_pair_bwd(const double* T, const double* C, const double* dN, double* dT,
+                                 double* dC, int a, int I1, int J1, int r, int I2, int J2, int b,
+                                 hipStream_t s);
 }  // namespace tnr

@@ -23,7 +23,8 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16}
 # the C function names exported by the library, in header order
 EXPORTS = [
     "tnrsvd_create", "tnrsvd_mult", "tnrsvd_orthogonalize", "tnrsvd_project",
-    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_refine", "tnrsvd_get_factor", "tnrsvd_copy_factor",
+    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_refine", "tnrsvd_backward",
+    "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
     "tnrsvd_last_error", "tnrsvd_version",
@@ -81,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_run.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_run_graph.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_refine.argtypes = [H, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    L.tnrsvd_backward.argtypes = [H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p)]
     L.tnrsvd_get_factor.argtypes = [H, I, I, I, ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I)]
     L.tnrsvd_copy_factor.argtypes = [H, I, I, I, ctypes.c_void_p]
@@ -209,6 +211,21 @@ class TNrSVD:
                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out.reshape(self.batch, self.k)
 
+    def backward(self, dsigma, grads) -> None:
+        """tnrsvd_backward: write d(sum_j dsigma_j sigma_j)/d(core) into the device
+        tensors ``grads`` (one per original core of every MPO, in order)."""
+        w = None
+        if dsigma is not None:
+            w = np.ascontiguousarray(np.asarray(dsigma, dtype=np.float64).reshape(-1))
+            if w.size != self.batch * self.k:
+                raise TNrSVDError(-1, "dsigma must hold batch * k values")
+        for g in grads:
+            if not g.is_cuda or not g.is_contiguous():
+                raise TNrSVDError(-1, "gradients must be contiguous device tensors")
+        ptrs = (ctypes.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
+        _check(self._lib.tnrsvd_backward(
+            self._h, None if w is None else w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs))
+
     def run_graph(self, want_sigma: bool = True) -> Optional[np.ndarray]:
         """tnrsvd_run captured once into a HIP graph, replayed on later calls."""
         if not want_sigma:
@@ -317,3 +334,48 @@ def solve(cores, k: int, p: int = 0, q: int = 0, seed: int = 0, precision: str =
     U[-1] = U[-1][:, :, :k].contiguous()
     V[-1] = V[-1][:, :, :k].contiguous()
     return sig, U, V
+
+
+def _autograd_function():
+    import torch
+
+    class TNrSVDFunction(torch.autograd.Function):
+        """sigma_top_k = TNrSVDFunction.apply(options, *cores) for one MPO.
+
+        Forward: one solve in the library (contractions, FP64 sweeps, final SVD).
+        Backward: tnrsvd_backward with the incoming gradient of sigma -- the
+        derivative at fixed computed singular vectors (see include/tnrsvd.h).
+        ``options`` is a dict of TNrSVD keyword arguments (k, p, q, seed,
+        precision, round_tol, max_rank).
+        """
+
+        @staticmethod
+        def forward(ctx, options, *cores):
+            h = TNrSVD([c.detach().contiguous() for c in cores], **options)
+            sig = h.run()[0]
+            ctx.h = h
+            ctx.like = [(c.shape, c.dtype) for c in cores]
+            return torch.as_tensor(sig, dtype=torch.float64, device=cores[0].device)
+
+        @staticmethod
+        def backward(ctx, gsig):
+            h = ctx.h
+            grads = [torch.empty(sh, dtype=dt, device="cuda") for sh, dt in ctx.like]
+            h.backward(gsig.detach().to("cpu", torch.float64).numpy(), grads)
+            h.close()
+            return (None, *grads)
+
+    return TNrSVDFunction
+
+
+class _Lazy:
+    def __init__(self):
+        self._f = None
+
+    def apply(self, *args):
+        if self._f is None:
+            self._f = _autograd_function()
+        return self._f.apply(*args)
+
+
+TNrSVDFunction = _Lazy()
