@@ -3,8 +3,10 @@ against the oracle's sigma_sum_grad on the same Omega.
 
 Both sides differentiate sum_j dsigma_j u_j^T A v_j at the computed singular
 vectors; the FP64 factors of the two sides agree to ~1e-12, so FP64
-gradients must agree to 1e-8 relative (norm-wise over all cores), FP32 ones
-to 1e-4.  Finite differences of the whole GPU pipeline are checked in the
+gradients must agree to 1e-8 relative (norm-wise over all cores); FP32 ones
+to 1e-4 when the singular values are well separated relative to sigma_0 and
+to 1e-3 on the known spectrum, whose small singular vectors FP32 rounding
+moves by eps32 sigma_0 / gap.  Finite differences of the whole GPU pipeline are checked in the
 exact case (rank(A) <= K, no truncation), where the two derivatives coincide.
 """
 
@@ -110,7 +112,11 @@ def test_autograd_function_spectrum_f32():
     assert all(c.grad.dtype == torch.float32 for c in cores)
     err = rel(G, G_ref)
     print(f"spectrum f32 autograd gradient: rel err {err:.3e}")
-    assert err <= 1e-4
+    # the top-20 values span sigma_19 / sigma_0 = 10^(-19/4); FP32 products
+    # move the j-th singular vectors by about eps32 sigma_0 / gap_j (gaps
+    # 0.44 sigma_j), i.e. up to ~1e-2 for the last of them and ~1e-3 norm-wise
+    # over the sum of the 20 rank-one terms
+    assert err <= 1e-3
 
 
 def test_grad_workload_f32_against_oracle():
