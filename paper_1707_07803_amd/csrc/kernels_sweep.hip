@@ -220,7 +220,8 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
 }
 
 // Blocked Householder QR (same output as wg_geqr2: R on and above the
-// diagonal, reflectors below it, tau) of the m x n column-major X (ld m), for
+// diagonal, reflectors below it, tau) of the m x n column-major X (ld ld,
+// default m), for
 // panels too large for registers.  Each block of QB columns is factorised by
 // wg_geqr2; its reflectors are applied to the trailing columns at once in the
 // compact WY form H_0 ... H_{b-1} = I - V T V^T (T upper triangular):
@@ -231,13 +232,14 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
 // in LDS outside lds.
 constexpr int QB = 16;
 __device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double* red, double* ws,
-                         double* lds, int64_t lds_cap, double* Ts, double* Gs) {
+                         double* lds, int64_t lds_cap, double* Ts, double* Gs, int64_t ld = -1) {
   const int tid = threadIdx.x;
+  if (ld < 0) ld = m;
   const int kmax = m < n ? m : n;
   for (int j0 = 0; j0 < kmax; j0 += QB) {
     const int jb = (kmax - j0) < QB ? (kmax - j0) : QB;
     const int mp = m - j0;
-    double* P0 = X + (int64_t)j0 * m + j0;   // panel (mp x jb), ld m
+    double* P0 = X + (int64_t)j0 * ld + j0;  // panel (mp x jb), ld ld
     const int nc = n - j0 - jb;
     double* Vp = ws;                          // explicit V (mp x jb, column-major)
     if ((int64_t)mp * (jb + 1) <= lds_cap) {
@@ -245,23 +247,23 @@ __device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double
       double* PL = lds + mp;
       for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
         const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
-        PL[e] = P0[(int64_t)c * m + r];
+        PL[e] = P0[(int64_t)c * ld + r];
       }
       __syncthreads();
       wg_geqr2(PL, mp, jb, tau + j0, lds, red, mp);
       for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
         const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
-        P0[(int64_t)c * m + r] = PL[e];
+        P0[(int64_t)c * ld + r] = PL[e];
         if (nc > 0) Vp[e] = r > c ? PL[e] : (r == c ? 1.0 : 0.0);
       }
       __syncthreads();
       if (nc <= 0) continue;
     } else {
-      wg_geqr2(P0, mp, jb, tau + j0, v, red, m);
+      wg_geqr2(P0, mp, jb, tau + j0, v, red, ld);
       if (nc <= 0) continue;
       for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
         const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
-        Vp[e] = r > c ? P0[(int64_t)c * m + r] : (r == c ? 1.0 : 0.0);
+        Vp[e] = r > c ? P0[(int64_t)c * ld + r] : (r == c ? 1.0 : 0.0);
       }
       __syncthreads();
     }
@@ -282,27 +284,29 @@ __device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double
       }
     }
     __syncthreads();
-    double* C = X + (int64_t)(j0 + jb) * m + j0;   // trailing block (mp x nc), ld m
+    double* C = X + (int64_t)(j0 + jb) * ld + j0;  // trailing block (mp x nc), ld ld
     double* Wm = ws + (int64_t)mp * QB;             // jb x nc, row-major
     double* Wm2 = Wm + (int64_t)QB * n;             // jb x nc, row-major
-    wg_gemm<double>(jb, nc, mp, 1.0, Vp, mp, 1, C, 1, m, 0.0, Wm, nc, 1, lds);      // V^T C
+    wg_gemm<double>(jb, nc, mp, 1.0, Vp, mp, 1, C, 1, ld, 0.0, Wm, nc, 1, lds);     // V^T C
     wg_gemm<double>(jb, nc, jb, 1.0, Ts, 1, QB, Wm, nc, 1, 0.0, Wm2, nc, 1, lds);   // T^T W
-    wg_gemm<double>(mp, nc, jb, -1.0, Vp, 1, mp, Wm2, nc, 1, 1.0, C, 1, m, lds);    // C -= V W
+    wg_gemm<double>(mp, nc, jb, -1.0, Vp, 1, mp, Wm2, nc, 1, 1.0, C, 1, ld, lds);   // C -= V W
   }
   __syncthreads();
 }
 
 // Y <- H_0 H_1 ... H_{k-1} Y for the m x s column-major Y (ld m), with the
-// reflectors stored as by wg_geqr2 in V (ld m).  One wave per column of Y;
+// reflectors stored as by wg_geqr2 in V (ld ldv, default m).  One wave per column of Y;
 // columns are independent, so no barrier is needed between reflectors.
-__device__ void wg_apply_q(const double* V, const double* tau, int m, int k, double* Y, int s) {
+__device__ void wg_apply_q(const double* V, const double* tau, int m, int k, double* Y, int s,
+                           int64_t ldv = -1) {
   const int lane = threadIdx.x & 63, w = wave_id();
+  if (ldv < 0) ldv = m;
   for (int c = w; c < s; c += NW) {
     double* yc = Y + (int64_t)c * m;
     for (int j = k - 1; j >= 0; --j) {
       const double tj = tau[j];
       if (tj == 0.0) continue;
-      const double* vj = V + (int64_t)j * m;
+      const double* vj = V + (int64_t)j * ldv;
       const int r0 = j & ~63;
       double part = 0.0;
       for (int r = r0 + lane; r < m; r += 64) {
@@ -1095,6 +1099,7 @@ struct ScratchLayout {
   double* T;
   double* M;
   double* U;
+  double* Q;   // QR-preconditioned Jacobi: blocked-QR workspace, then the scalars
 };
 
 template <typename TO>
@@ -1123,6 +1128,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
   SL.T = scratch + md.s_off;
   SL.M = SL.T + tcap;
   SL.U = SL.M + mcap_s;
+  SL.Q = SL.U + ucap;
   const CoreDesc c0 = cores[md.c0];
   const int n0 = op == 0 ? c0.I : c0.J;
   const int m0 = n0 * (d > 1 ? rho[md.r0 + 1] : K);
@@ -1187,8 +1193,30 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
     const int nv = s * n;
     if (i < d - 1) {
       double* U = (nvg * nvg <= LR_UB) ? Ub : SL.U;
-      wg_jacobi(M, nv, rn, ld, U, ibuf, red);
-      wg_norms_sorted(M, nv, rn, ld, sig, perm, nrmb);
+      // A panel in global memory with fewer rows than columns is first reduced
+      // by a QR of its transpose, M^T = Q R (blocked Householder, in place):
+      // the rows of M and of R^T have the same inner products, so the one-sided
+      // Jacobi runs on the nv x nv R^T in LDS with the same rotations, and the
+      // carried factor U^T M = (U^T R^T) Q^T is recovered by applying Q.
+      const bool pre = !m_in_lds && nv < rn && nv * nv <= LR_MB && nvg * nvg <= LR_UB &&
+                       (int64_t)rn * (QB + 1) <= LR_VB && 2 * QB * QB <= LR_UB &&
+                       (int64_t)rn * QB + 2 * QB * nv + nv <= so.qcap;
+      double* B = M;
+      int blen = rn, bld = ld;
+      double* tauP = SL.Q + (int64_t)rn * QB + 2 * QB * nv;
+      if (pre) {
+        wg_geqrf(M, rn, nv, tauP, Vb, red, SL.Q, Vb, LR_VB, Ub, Ub + QB * QB, ld);
+        for (int e = tid; e < nv * nv; e += NT) {
+          const int p = e / nv, c = e - p * nv;
+          Mb[e] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T
+        }
+        __syncthreads();
+        B = Mb;
+        blen = nv;
+        bld = nv;
+      }
+      wg_jacobi(B, nv, blen, bld, U, ibuf, red);
+      wg_norms_sorted(B, nv, blen, bld, sig, perm, nrmb);
       if (tid == 0) {
         const int kk = nv < rn ? nv : rn;
         const double d2 = delta * delta;
@@ -1219,9 +1247,19 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         const int row = (int)(o / rnew), k = (int)(o % rnew);
         xo[o] = (TO)(U[(int64_t)perm[k] * nv + row] * sgn[k]);
       }
-      for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
-        const int k = (int)(o / rn), f = (int)(o % rn);
-        SL.T[o] = M[(int64_t)perm[k] * ld + f] * sgn[k];
+      if (pre) {
+        // T^T (rn x rnew, column-major = T row-major) = Q [B_sel^T; 0]
+        for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
+          const int k = (int)(o / rn), f = (int)(o % rn);
+          SL.T[o] = f < nv ? B[(int64_t)perm[k] * nv + f] * sgn[k] : 0.0;
+        }
+        __syncthreads();
+        wg_apply_q(M, tauP, rn, nv, SL.T, rnew, ld);
+      } else {
+        for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
+          const int k = (int)(o / rn), f = (int)(o % rn);
+          SL.T[o] = M[(int64_t)perm[k] * ld + f] * sgn[k];
+        }
       }
       if (tid == 0) xr[md.r0 + i + 1] = rnew;
       s = rnew;

@@ -68,7 +68,7 @@ struct tnrsvd_s {
   int ncores = 0, max_d = 0;
   int64_t max_core_out = 1, max_om = 1, max_y0 = 1;
   int vcap = 64, scap = 64;
-  int64_t tcap = 1, mcap_s = 1, ucap = 1;
+  int64_t tcap = 1, mcap_s = 1, ucap = 1, qcap = 1;
   // device buffers
   MpoDesc* mpos_d = nullptr;
   CoreDesc* cores_d = nullptr;
@@ -255,7 +255,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   int64_t a_tot = 0, x_tot = 0, z_tot = 0, w_tot = 0, l_tot = 0, t_tot = 0, y_tot = 0,
           u_tot = 0, om_tot = 0, s_tot = 0, out_tot = 0;
   int r_tot = 0;
-  int64_t tcap = 1, mcap_s = 1, ucap = 1;
+  int64_t tcap = 1, mcap_s = 1, ucap = 1, qcap = 1;
   int vcap = 64, scap = K;
   for (int b = 0; b < batch; ++b) {
     const tnrsvd_mpo& a = mpos[b];
@@ -322,7 +322,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
     omn += J[dm - 1] * K;
     om_tot += omn;
     h->max_om = std::max(h->max_om, omn);
-    int64_t mpo_t = 1, mpo_m = 1, mpo_u = 1;
+    int64_t mpo_t = 1, mpo_m = 1, mpo_u = 1, mpo_q = 1;
     int mpo_v = 64;
     for (int i = 0; i < dm; ++i) {
       CoreDesc cd{};
@@ -367,6 +367,9 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
       mpo_m = std::max(mpo_m, xc[i] * nmax * P2pad);
       mpo_v = (int)std::max<int64_t>(mpo_v, nmax * P2);
       const int64_t nv = xc[i] * nmax;
+      // QR-preconditioned Jacobi of the left-to-right pass: blocked QR of the
+      // transposed panel (P2 rows, nv columns) and its scalars
+      mpo_q = std::max(mpo_q, P2 * 16 + 2 * 16 * nv + nv);
       if (i < dm - 1) {
         scap = (int)std::max<int64_t>(scap, nv);
         mpo_u = std::max(mpo_u, nv * nv);
@@ -378,7 +381,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
       h->core_mpo.push_back(b);
     }
     md.s_off = s_tot;
-    md.s_len = mpo_t + mpo_m + mpo_u;
+    md.s_len = mpo_t + mpo_m + mpo_u + mpo_q;
     s_tot += md.s_len;
     md.out_off = out_tot;
     out_tot += K + 2 * (int64_t)K * K;
@@ -387,6 +390,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
     tcap = std::max(tcap, mpo_t);
     mcap_s = std::max(mcap_s, mpo_m);
     ucap = std::max(ucap, mpo_u);
+    qcap = std::max(qcap, mpo_q);
     vcap = std::max(vcap, mpo_v);
     h->max_d = std::max(h->max_d, dm);
     h->mh.push_back(md);
@@ -395,7 +399,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   s_tot = 0;
   for (auto& md : h->mh) {
     md.s_off = s_tot;
-    md.s_len = tcap + mcap_s + ucap;
+    md.s_len = tcap + mcap_s + ucap + qcap;
     s_tot += md.s_len;
   }
   h->ncores = (int)h->ch.size();
@@ -404,6 +408,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   h->tcap = tcap;
   h->mcap_s = mcap_s;
   h->ucap = ucap;
+  h->qcap = qcap;
   if (vcap > kSweepArena - 64 - 2 * 16 * 16 || scap > kSortCap) {
     delete h;
     return fail(TNRSVD_E_SHAPE,
@@ -671,6 +676,7 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   so.eps = h->opts.round_tol;
   so.rmax = (int)h->opts.max_rank;
   so.mode = mode;
+  so.qcap = h->qcap;
   void* out = mode == 0 ? h->X : (void*)h->V;
   const int odt = mode == 0 ? h->dtype : kF64;
   int* rout = mode == 0 ? h->xr : h->vr;

@@ -61,6 +61,7 @@ struct SweepOpts {
   double eps;        // rounding tolerance
   int rmax;          // rank cap (0 = none)
   int mode;          // 0: orthogonalise (QR of the last core), 1: solve (SVD)
+  int64_t qcap;      // scratch doubles per MPO for the QR-preconditioned Jacobi
 };
 
 // BF16 storage: the upper 16 bits of an FP32 (1 sign, 8 exponent, 7 fraction
