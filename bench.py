@@ -50,6 +50,9 @@ def parse():
                     help="independent copies of the workload for the batched measurement "
                          "(0 = skip); one persistent workgroup per MPO")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the timings of the other workloads (plain FP64, large, "
+                         "batched uneven subset, gradient)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (the reference kernel "
                          "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
@@ -176,6 +179,71 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol
             "sigma_all": sig_all, "ranks": ranks, "counts": counts, "batch": batch}
 
 
+def other_configs():
+    """Timings of the other workloads on the GPU (their parity with the oracle is
+    checked by the GPU tests, not here)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1707_07803_amd import TNrSVD
+
+    def dev(cores, dt):
+        td = torch.float64 if dt == "f64" else torch.float32
+        return [torch.as_tensor(c, dtype=td).cuda() for c in cores]
+
+    def timed(h, fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    out = {}
+    W = wl.small()
+    h = TNrSVD(dev(W.cores, "f64"), W.k, W.p, W.q, seed=W.omega_seed)
+    dt = timed(h, lambda: h.run(False), 50)
+    out["plain_fp64"] = {"workload": "d=8, 2x2 cores, ranks 3, k=10 p=6 q=0 (256 x 256)",
+                         "solves_per_s": round(1.0 / dt, 2)}
+    h.close()
+    W = wl.large()
+    res = {}
+    for p in ("f32", "f64"):
+        h = TNrSVD(dev(W.cores, p), W.k, W.p, W.q, seed=W.omega_seed, precision=p,
+                   round_tol=W.eps, max_rank=W.rmax)
+        dt = timed(h, lambda: h.run(False), 1)
+        res[p] = (dt, h.run()[0])
+        h.close()
+    out["large"] = {"workload": "d=50, 2x2 cores, ranks 10, k=10 p=10 q=2, r_max=32 (2^50 x 2^50)",
+                    "solves_per_s": {p: round(1.0 / res[p][0], 4) for p in res},
+                    "sigma_rel_diff_f32_vs_f64": float(np.linalg.norm(res["f32"][1] - res["f64"][1])
+                                                       / np.linalg.norm(res["f64"][1]))}
+    Ws = wl.batched(512)
+    cost = [len(w.cores) * w.cores[0].shape[1] ** 2 * w.cores[1].shape[0] ** 3 for w in Ws]
+    sel = sorted(range(len(Ws)), key=lambda b: cost[b])[:128]
+    h = TNrSVD([dev(Ws[b].cores, "f32") for b in sel], 8, 8, 1, seed=9, precision="f32",
+               max_rank=32)
+    dt = timed(h, lambda: h.run_graph(False), 1)
+    out["batched_uneven_subset"] = {
+        "workload": "the 128 cheapest of the 512 uneven MPOs (d in [10,40], I=J in {2,4}, "
+                    "ranks in [4,32]), k=8 p=8 q=1, FP32, one persistent launch per pass, "
+                    "hipGraph replay",
+        "solves_per_s": round(128 / dt, 2), "ms_per_batch": round(1e3 * dt, 2)}
+    h.close()
+    W = wl.grad()
+    cores = dev(W.cores, "f32")
+    h = TNrSVD(cores, W.k, W.p, W.q, seed=W.omega_seed, precision="f32", max_rank=W.rmax)
+    tf = timed(h, lambda: h.run(False), 1)
+    grads = [torch.empty_like(c) for c in cores]
+    tb = timed(h, lambda: h.backward(None, grads), 1)
+    out["grad"] = {"workload": "d=30, 4x4 cores, ranks 16, k=16 p=8 q=1, FP32; gradient of the "
+                               "sum of the top 16 sigma at fixed singular vectors",
+                   "forward_s": round(tf, 4), "backward_s": round(tb, 4)}
+    h.close()
+    return out
+
+
 def measured_traffic(precision):
     """HBM bytes per sweep from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
     or None when the sweep kernel's source no longer matches the profiled one."""
@@ -290,6 +358,11 @@ def main():
         print(f"[bench] batched {args.batch}: {batched['solves_per_s']} solves/s", file=sys.stderr,
               flush=True)
 
+    configs = None
+    if not args.no_configs:
+        configs = other_configs()
+        print(f"[bench] other configs: {configs}", file=sys.stderr, flush=True)
+
     main_p = precs[0]
     r = res[main_p]
     ms_per_step = 1e3 * r["seconds"] / r["steps"]
@@ -356,6 +429,7 @@ def main():
         "cpu_baseline": cpu,
         "contraction": contraction,
         "batched": batched,
+        "other_configs": configs,
         "kernel_avg_ms": {k: round(v, 5) for k, v in avg_ms.items()},
         "launches_per_solve": launches_per_solve,
         "sigma_err": sig_err,

@@ -329,7 +329,8 @@ __device__ void wg_apply_q(const double* V, const double* tau, int m, int k, dou
 // accumulate the rotations in U (nv x nv, column-major).  Pairs follow the
 // round-robin (circle) ordering so a round's pairs are disjoint and each is
 // handled by one wave.  Returns the number of sweeps.
-__device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* flag, double* red) {
+__device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* flag, double* red,
+                          double skip2 = 0.0) {
   const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   for (int t = tid; t < nv * nv; t += NT) U[t] = ((t % nv) == (t / nv)) ? 1.0 : 0.0;
   __syncthreads();
@@ -344,6 +345,11 @@ __device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* fl
     part += x * x;
   }
   const double tiny = 256.0 * 4.930380657631324e-32 * block_sum(part, red);
+  // A pair whose squared norms sum to at most skip2 (the caller passes
+  // delta^2 / nv when the rank will be cut at tail delta^2) needs no rotation:
+  // every vector that small ends in the discarded tail (nv of them sum to at
+  // most delta^2), and the tail's Frobenius norm does not depend on rotations
+  // among its vectors.
   // Convergence threshold len * eps on |<b_p,b_q>| / (|b_p| |b_q|): above the
   // rounding level of the computed inner products, so a converged pair is
   // never rotated again and the sweep count stays small.
@@ -381,7 +387,8 @@ __device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* fl
         a = wave_sum(a);
         b = wave_sum(b);
         c = wave_sum(c);
-        if (a <= tiny || b <= tiny || fabs(c) <= tol * sqrt(a) * sqrt(b)) continue;
+        if (a <= tiny || b <= tiny || a + b <= skip2 || fabs(c) <= tol * sqrt(a) * sqrt(b))
+          continue;
         const double zeta = (b - a) / (2.0 * c);
         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -1215,7 +1222,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         blen = nv;
         bld = nv;
       }
-      wg_jacobi(B, nv, blen, bld, U, ibuf, red);
+      wg_jacobi(B, nv, blen, bld, U, ibuf, red, delta * delta / (double)nv);
       wg_norms_sorted(B, nv, blen, bld, sig, perm, nrmb);
       if (tid == 0) {
         const int kk = nv < rn ? nv : rn;
