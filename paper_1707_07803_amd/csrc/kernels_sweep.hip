@@ -139,44 +139,64 @@ __device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double
 // C (M x N) = beta C + alpha A (M x K) B (K x N) with FP64 accumulation, by
 // the whole workgroup.  Element (i, k) of A is A[i sai + k sak], (k, j) of B
 // is B[k sbk + j sbj] (type TB, widened to FP64) and (i, j) of C is
-// C[i sci + j scj]; C may be in global memory or LDS.  64 x 64 output tiles;
-// K goes through LDS 32 at a time, the next chunk's loads (clamped in-bounds
-// addresses, mapped so the unit-stride index runs across lanes) in flight
-// while the current one is multiplied; each thread owns a 4 x 2 block of a
-// tile.  beta == 0 never reads C.  `lds` holds 2 x 32 x 65 doubles.  Ends
-// with a barrier.
-constexpr int GK = 32, GLD = 65, GEMM_LDS = 2 * GK * GLD;
-template <typename TB>
-__device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int64_t sai,
-                        int64_t sak, const TB* B, int64_t sbk, int64_t sbj, double beta, double* C,
-                        int64_t sci, int64_t scj, double* lds) {
-  constexpr int NL = 64 * GK / NT;   // elements of each operand per thread and chunk
+// C[i sci + j scj]; C may be in global memory or LDS.  TM x TN output tiles
+// (64 x 64, or 128 x 32 for products only a few columns wide); K goes through
+// LDS GK at a time, the next chunk's loads (clamped in-bounds addresses,
+// mapped so the unit-stride index runs across lanes) in flight while the
+// current one is multiplied; each thread owns a 4 x 2 block of a tile, and
+// when beta != 0 its C values are loaded before the K loop.  beta == 0 never
+// reads C.  `lds` holds GEMM_LDS doubles.  Ends with a barrier.
+constexpr int GK = 32;
+constexpr int GEMM_LDS = GK * (128 + 1) + GK * (64 + 1);
+template <int TM, int TN, typename TB>
+__device__ void wg_gemm_t(int M, int N, int K, double alpha, const double* A, int64_t sai,
+                          int64_t sak, const TB* B, int64_t sbk, int64_t sbj, double beta,
+                          double* C, int64_t sci, int64_t scj, double* lds) {
+  constexpr int TX = TN / 2, TY = NT / TX;           // threads across columns / rows
+  static_assert(TY * 4 == TM, "4 rows per thread");
+  constexpr int ALD = TM + 1, BLD = TN + 1;
+  constexpr int NA = TM * GK / NT, NB = TN * GK / NT;  // loads per thread and chunk
   const int tid = threadIdx.x;
-  double* As = lds;             // As[k * GLD + i]
-  double* Bs = lds + GK * GLD;  // Bs[k * GLD + j]
-  const int ty = tid >> 5, tx = tid & 31;
+  double* As = lds;             // As[k * ALD + i]
+  double* Bs = lds + GK * ALD;  // Bs[k * BLD + j]
+  const int ty = tid / TX, tx = tid % TX;
   const bool a_ifast = sai == 1, b_jfast = sbj == 1;
-  int ai[NL], ak[NL], bk[NL], bj[NL];
+  int ai[NA], ak[NA], bk[NB], bj[NB];
 #pragma unroll
-  for (int t = 0; t < NL; ++t) {
+  for (int t = 0; t < NA; ++t) {
     const int e = tid + t * NT;
-    ai[t] = a_ifast ? (e & 63) : (e / GK);
-    ak[t] = a_ifast ? (e >> 6) : (e % GK);
-    bj[t] = b_jfast ? (e & 63) : (e / GK);
-    bk[t] = b_jfast ? (e >> 6) : (e % GK);
+    ai[t] = a_ifast ? (e % TM) : (e / GK);
+    ak[t] = a_ifast ? (e / TM) : (e % GK);
   }
-  for (int i0 = 0; i0 < M; i0 += 64) {
-    for (int j0 = 0; j0 < N; j0 += 64) {
-      double acc[4][2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = 0.0;
-      double av[NL], bv[NL];
+  for (int t = 0; t < NB; ++t) {
+    const int e = tid + t * NT;
+    bj[t] = b_jfast ? (e % TN) : (e / GK);
+    bk[t] = b_jfast ? (e / TN) : (e % GK);
+  }
+  for (int i0 = 0; i0 < M; i0 += TM) {
+    for (int j0 = 0; j0 < N; j0 += TN) {
+      double acc[4][2], cold[4][2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          acc[r][c] = 0.0;
+          const int i = i0 + ty * 4 + r, j = j0 + tx + TX * c;
+          const bool ok = beta != 0.0 && i < M && j < N;
+          const double v = C[ok ? (int64_t)i * sci + (int64_t)j * scj : 0];
+          cold[r][c] = ok ? v : 0.0;
+        }
+      double av[NA], bv[NB];
       auto fetch = [&](int k0) {
 #pragma unroll
-        for (int t = 0; t < NL; ++t) {
+        for (int t = 0; t < NA; ++t) {
           const bool oka = i0 + ai[t] < M && k0 + ak[t] < K;
           const double va = A[oka ? (int64_t)(i0 + ai[t]) * sai + (int64_t)(k0 + ak[t]) * sak : 0];
           av[t] = oka ? va : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
           const bool okb = j0 + bj[t] < N && k0 + bk[t] < K;
           const double vb =
               (double)B[okb ? (int64_t)(k0 + bk[t]) * sbk + (int64_t)(j0 + bj[t]) * sbj : 0];
@@ -186,18 +206,17 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
       fetch(0);
       for (int k0 = 0; k0 < K; k0 += GK) {
 #pragma unroll
-        for (int t = 0; t < NL; ++t) {
-          As[ak[t] * GLD + ai[t]] = av[t];
-          Bs[bk[t] * GLD + bj[t]] = bv[t];
-        }
+        for (int t = 0; t < NA; ++t) As[ak[t] * ALD + ai[t]] = av[t];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) Bs[bk[t] * BLD + bj[t]] = bv[t];
         __syncthreads();
         if (k0 + GK < K) fetch(k0 + GK);
 #pragma unroll 8
         for (int k = 0; k < GK; ++k) {
-          const double b0 = Bs[k * GLD + tx], b1 = Bs[k * GLD + tx + 32];
+          const double b0 = Bs[k * BLD + tx], b1 = Bs[k * BLD + tx + TX];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const double a = As[k * GLD + ty * 4 + r];
+            const double a = As[k * ALD + ty * 4 + r];
             acc[r][0] += a * b0;
             acc[r][1] += a * b1;
           }
@@ -208,15 +227,20 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          const int i = i0 + ty * 4 + r, j = j0 + tx + 32 * c;
-          if (i < M && j < N) {
-            double* cp = C + (int64_t)i * sci + (int64_t)j * scj;
-            *cp = beta == 0.0 ? alpha * acc[r][c] : beta * *cp + alpha * acc[r][c];
-          }
+          const int i = i0 + ty * 4 + r, j = j0 + tx + TX * c;
+          if (i < M && j < N)
+            C[(int64_t)i * sci + (int64_t)j * scj] = beta * cold[r][c] + alpha * acc[r][c];
         }
     }
   }
   __syncthreads();
+}
+
+template <typename TB>
+__device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int64_t sai,
+                        int64_t sak, const TB* B, int64_t sbk, int64_t sbj, double beta, double* C,
+                        int64_t sci, int64_t scj, double* lds) {
+  wg_gemm_t<64, 64, TB>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, sci, scj, lds);
 }
 
 // Blocked Householder QR (same output as wg_geqr2: R on and above the
@@ -225,19 +249,21 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
 // panels too large for registers.  Each block of QB columns is factorised by
 // wg_geqr2; its reflectors are applied to the trailing columns at once in the
 // compact WY form H_0 ... H_{b-1} = I - V T V^T (T upper triangular):
-//   C <- C - V T^T (V^T C),  two GEMMs.
+//   C <- C - V (C^T V T)^T,  three GEMMs (the two skinny ones in 128 x 32 tiles).
 // A panel that fits in lds (lds_cap doubles, at least GEMM_LDS) is factorised
 // there; otherwise in place in global memory with v as the LDS vector.
-// ws: m QB + 2 QB n doubles of global workspace; Ts, Gs: QB x QB doubles each
-// in LDS outside lds.
-constexpr int QB = 16;
+// qb: block width (<= QBMAX).  ws: m qb + 2 qb n doubles of global workspace;
+// Ts, Gs: QBMAX x QBMAX doubles each in LDS outside lds.
+constexpr int QB = 16;      // block width of the left-to-right pass
+constexpr int QBMAX = 32;   // widest block; Ts and Gs are QBMAX x QBMAX
 __device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double* red, double* ws,
-                         double* lds, int64_t lds_cap, double* Ts, double* Gs, int64_t ld = -1) {
+                         double* lds, int64_t lds_cap, double* Ts, double* Gs, int64_t ld = -1,
+                         int qb = QB) {
   const int tid = threadIdx.x;
   if (ld < 0) ld = m;
   const int kmax = m < n ? m : n;
-  for (int j0 = 0; j0 < kmax; j0 += QB) {
-    const int jb = (kmax - j0) < QB ? (kmax - j0) : QB;
+  for (int j0 = 0; j0 < kmax; j0 += qb) {
+    const int jb = (kmax - j0) < qb ? (kmax - j0) : qb;
     const int mp = m - j0;
     double* P0 = X + (int64_t)j0 * ld + j0;  // panel (mp x jb), ld ld
     const int nc = n - j0 - jb;
@@ -269,27 +295,28 @@ __device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double
     }
     // G = V^T V (jb x jb, row-major in LDS), then T by the forward recurrence
     //   T_ii = tau_i,  T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-    wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QB, 1, lds);
+    wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QBMAX, 1, lds);
     if (tid < 64) {
       for (int i = 0; i < jb; ++i) {
         const double ti = tau[j0 + i];
         if (tid < i) {
           double acc = 0.0;
-          for (int c = tid; c < i; ++c) acc += Ts[tid * QB + c] * Gs[c * QB + i];
-          Ts[tid * QB + i] = -ti * acc;
-        } else if (tid < QB) {
-          Ts[tid * QB + i] = tid == i ? ti : 0.0;
+          for (int c = tid; c < i; ++c) acc += Ts[tid * QBMAX + c] * Gs[c * QBMAX + i];
+          Ts[tid * QBMAX + i] = -ti * acc;
+        } else if (tid < QBMAX) {
+          Ts[tid * QBMAX + i] = tid == i ? ti : 0.0;
         }
         __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
     double* C = X + (int64_t)(j0 + jb) * ld + j0;  // trailing block (mp x nc), ld ld
-    double* Wm = ws + (int64_t)mp * QB;             // jb x nc, row-major
-    double* Wm2 = Wm + (int64_t)QB * n;             // jb x nc, row-major
-    wg_gemm<double>(jb, nc, mp, 1.0, Vp, mp, 1, C, 1, ld, 0.0, Wm, nc, 1, lds);     // V^T C
-    wg_gemm<double>(jb, nc, jb, 1.0, Ts, 1, QB, Wm, nc, 1, 0.0, Wm2, nc, 1, lds);   // T^T W
-    wg_gemm<double>(mp, nc, jb, -1.0, Vp, 1, mp, Wm2, nc, 1, 1.0, C, 1, ld, lds);   // C -= V W
+    double* Wt = ws + (int64_t)mp * qb;             // W^T = C^T V, nc x jb (ld qb)
+    double* Wt2 = Wt + (int64_t)qb * n;             // W^T T, nc x jb (ld qb)
+    wg_gemm_t<128, 32, double>(nc, jb, mp, 1.0, C, ld, 1, Vp, 1, mp, 0.0, Wt, qb, 1, lds);
+    wg_gemm_t<128, 32, double>(nc, jb, jb, 1.0, Wt, qb, 1, Ts, QBMAX, 1, 0.0, Wt2, qb, 1, lds);
+    // C -= V (W^T T)^T
+    wg_gemm<double>(mp, nc, jb, -1.0, Vp, 1, mp, Wt2, 1, qb, 1.0, C, 1, ld, lds);
   }
   __syncthreads();
 }
@@ -787,7 +814,7 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
     const int Pn = pr[md.r0 + i + 1];
     const int m = n * rnext;
     if (P < 1 || P > cd.RA * cd.xcap || Pn < 1 || Pn > cd.RA2 * cd.xcap2 || rnext > Pn ||
-        m > ARENA - 64 - 2 * QB * QB) {
+        m > ARENA - 64 - 2 * QBMAX * QBMAX) {
       if (tid == 0) atomicOr(err, 4);
       return;
     }
@@ -894,8 +921,12 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
     if (tid == 0) ldm[md.r0 + i] = rnext;
     __syncthreads();
     if (i == 0) break;
-    wg_geqrf(Xt, m, P, tau + cd.tau_off, vb, red, Xt + tot, arena, ARENA - 64 - 2 * QB * QB,
-             arena + ARENA - 32 - 2 * QB * QB, arena + ARENA - 32 - QB * QB);
+    {
+      constexpr int RCAP = ARENA - 64 - 2 * QBMAX * QBMAX;   // LDS left for panel and tiles
+      const int qb = (int64_t)m * (QBMAX + 1) <= RCAP ? QBMAX : QB;
+      wg_geqrf(Xt, m, P, tau + cd.tau_off, vb, red, Xt + tot, arena, RCAP,
+               arena + ARENA - 32 - 2 * QBMAX * QBMAX, arena + ARENA - 32 - QBMAX * QBMAX, m, qb);
+    }
     const int k = m < P ? m : P;
     double* Ro = L + cd.l_off;
     for (int64_t o = tid; o < (int64_t)k * P; o += NT) {
@@ -1206,13 +1237,13 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       // Jacobi runs on the nv x nv R^T in LDS with the same rotations, and the
       // carried factor U^T M = (U^T R^T) Q^T is recovered by applying Q.
       const bool pre = !m_in_lds && nv < rn && nv * nv <= LR_MB && nvg * nvg <= LR_UB &&
-                       (int64_t)rn * (QB + 1) <= LR_VB && 2 * QB * QB <= LR_UB &&
+                       (int64_t)rn * (QB + 1) <= LR_VB && 2 * QBMAX * QBMAX <= LR_UB &&
                        (int64_t)rn * QB + 2 * QB * nv + nv <= so.qcap;
       double* B = M;
       int blen = rn, bld = ld;
       double* tauP = SL.Q + (int64_t)rn * QB + 2 * QB * nv;
       if (pre) {
-        wg_geqrf(M, rn, nv, tauP, Vb, red, SL.Q, Vb, LR_VB, Ub, Ub + QB * QB, ld);
+        wg_geqrf(M, rn, nv, tauP, Vb, red, SL.Q, Vb, LR_VB, Ub, Ub + QBMAX * QBMAX, ld, QB);
         for (int e = tid; e < nv * nv; e += NT) {
           const int p = e / nv, c = e - p * nv;
           Mb[e] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T

@@ -352,8 +352,8 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
         const int64_t nc = (nmax * K + 255) / 256;
         wneed = std::max(wneed, (2 * nc * 256 + 2 * P) * P + 2 * nc * P);
       }
-      // the blocked QR of the global path needs m QB + 2 QB P more (QB = 16)
-      wneed += nmax * P2pad * 16 + 2 * 16 * P;
+      // the blocked QR of the global path needs m qb + 2 qb P more (qb <= 32)
+      wneed += nmax * P2pad * 32 + 2 * 32 * P;
       w_tot += wneed;
       cd.l_off = l_tot;
       l_tot += P * P;
@@ -409,7 +409,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
   h->mcap_s = mcap_s;
   h->ucap = ucap;
   h->qcap = qcap;
-  if (vcap > kSweepArena - 64 - 2 * 16 * 16 || scap > kSortCap) {
+  if (vcap > kSweepArena - 64 - 2 * 32 * 32 || scap > kSortCap) {
     delete h;
     return fail(TNRSVD_E_SHAPE,
                 "panels too large for one workgroup (rows %d, sorted vectors %d); lower max_rank",
