@@ -129,7 +129,8 @@ def instrumented_counts(h, R, I, J, K, q, esz):
 
 # ---------------------------------------------------------------------------
 
-def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol=None):
+def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol=None,
+              autotune=False):
     import numpy as np
     import torch
     from paper_1707_07803_amd import TNrSVD
@@ -140,6 +141,7 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol
     h = TNrSVD(mpos, W.k, W.p, W.q, seed=W.omega_seed, precision=precision, round_tol=eps,
                max_rank=W.rmax)
     del cores
+    tuned = h.autotune(3) if autotune else None
     if refine_tol is None:
         step = h.run_graph if graph else h.run
     else:
@@ -175,7 +177,7 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol
     counts = instrumented_counts(h, R, I, J, W.K, W.q, esz)
     h.close()
     return {"seconds": t1 - t0, "steps": steps, "kernels": kern, "sigma": sigma,
-            "sigma_refined": sigma_refined,
+            "sigma_refined": sigma_refined, "autotune": tuned,
             "sigma_all": sig_all, "ranks": ranks, "counts": counts, "batch": batch}
 
 
@@ -337,7 +339,7 @@ def main():
     if args.batch > 0:
         pb = precs[0]
         rb = time_path(W, pb, W.eps_by_precision[pb], args.batch_steps, 1, batch=args.batch,
-                       graph=True)
+                       graph=True, autotune=True)
         kb = {k: v for k, v in rb["kernels"].items() if v[1] > 0}
         domb = max(kb, key=lambda k: kb[k][0])
         avgb = kb[domb][0] / kb[domb][1]
@@ -347,6 +349,7 @@ def main():
         errs = [float(np.linalg.norm(sv - exact) / np.linalg.norm(exact)) for sv in rb["sigma_all"]]
         batched = {"batch": args.batch, "precision": pb, "steps": args.batch_steps,
                    "launch": "hipGraph replay of the whole solve (tnrsvd_run_graph)",
+                   "contraction_launch_autotuned": rb["autotune"],
                    "solves_per_s": round(args.batch * rb["steps"] / rb["seconds"], 2),
                    "ms_per_step": round(1e3 * rb["seconds"] / rb["steps"], 3),
                    "max_sigma_err_vs_prescribed": max(errs),

@@ -215,6 +215,22 @@ tnrsvd_status tnrsvd_refine(tnrsvd_t h, double round_tol, double* sigma);
 tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores);
 
 /*
+ * tnrsvd_autotune -- choose the launch shape of the MPO x MPS contraction
+ * (threads per block in {64, 128, 256, 512}, blocks per core capped at
+ * {64, 256, 1024, 4096}) for each product direction by timing `reps` launches
+ * of every shape on this handle's own shapes and planned ranks (batching
+ * support; not part of the paper).  Runs one solve first to obtain a basis of
+ * realistic ranks; afterwards every result of the handle is invalid (the
+ * next call must be tnrsvd_run, tnrsvd_run_graph or tnrsvd_mult(0)), and a
+ * captured graph is dropped and recaptured on the next tnrsvd_run_graph.
+ * choice: NULL or 4 ints receiving (threads, cap) for Y = A X, then for
+ * Z = A^T X.  Every shape computes each output with the same arithmetic, so
+ * results do not depend on the choice.
+ * Errors: E_INVALID (reps < 1); E_STATE (profiling on); E_DEVICE.
+ */
+tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice);
+
+/*
  * tnrsvd_get_factor -- borrow a device pointer to one core of a result.
  *   which 0: U (row space, last core (r, I, k)), available after solve;
  *   which 1: V (column space, last core (s, J, k)), after solve;

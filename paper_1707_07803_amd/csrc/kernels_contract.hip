@@ -275,16 +275,19 @@ hipError_t launch_load_omega(const MpoDesc* mpos, const CoreDesc* cores, int bat
 
 hipError_t launch_contract(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
                            int ncores, const int* xr, int* pr, const void* A, const void* X,
-                           void* Z, int dtype, int op, int64_t max_out, int* err, hipStream_t s) {
-  dim3 grid(grid_for(max_out, 256, 256), ncores);
+                           void* Z, int dtype, int op, int64_t max_out, int* err, int threads,
+                           int gcap, hipStream_t s) {
+  // threads per block and the cap on blocks per core come from the plan or the
+  // autotuner; the grid-stride loop makes every shape cover all outputs
+  dim3 grid(grid_for(max_out, threads, gcap), ncores);
   by_dtype(dtype, [&](auto* t) {
     using T = elem_t<decltype(t)>;
     if (op == 0)
-      k_contract<T, 0><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const T*)A,
-                                             (const T*)X, (T*)Z, err);
+      k_contract<T, 0><<<grid, threads, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const T*)A,
+                                                 (const T*)X, (T*)Z, err);
     else
-      k_contract<T, 1><<<grid, 256, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const T*)A,
-                                             (const T*)X, (T*)Z, err);
+      k_contract<T, 1><<<grid, threads, 0, s>>>(mpos, cores, core_mpo, xr, pr, (const T*)A,
+                                                 (const T*)X, (T*)Z, err);
   });
   return hipGetLastError();
 }

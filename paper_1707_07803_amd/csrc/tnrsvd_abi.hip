@@ -109,6 +109,9 @@ struct tnrsvd_s {
   int64_t* eoff_d = nullptr;
   double *gws = nullptr, *gG = nullptr, *gw = nullptr, *gchain = nullptr;
   int64_t a_elems = 0, chain_cap = 0;
+  // launch shape of the contraction per op (threads per block, blocks per core
+  // cap), from tnrsvd_autotune
+  int ct_threads[2] = {256, 256}, ct_cap[2] = {256, 256};
 };
 
 namespace {
@@ -649,7 +652,7 @@ tnrsvd_status do_mult(tnrsvd_t h, int op) {
     Timed tm(h, 0);
     e = launch_contract(h->mpos_d, h->cores_d, h->core_mpo_d, h->ncores, h->xr, h->pr,
                                  h->A, h->X, h->Z, h->dtype, op, h->max_core_out, h->err,
-                                 h->stream);
+                                 h->ct_threads[op], h->ct_cap[op], h->stream);
   }
   TRY(dev_check(e, "contract"));
   if (op == 0 && h->first_product) {
@@ -921,6 +924,80 @@ tnrsvd_status plan_grad(tnrsvd_t h) {
 }  // namespace
 
 extern "C" {
+
+tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice) {
+  TRY(check_handle(h));
+  if (reps < 1) return fail(TNRSVD_E_INVALID, "reps must be >= 1");
+  if (h->profiling) return fail(TNRSVD_E_STATE, "disable profiling before autotuning");
+  // one solve leaves a basis of the planned ranks in X; both products are then
+  // timed on it (for op 0 with I != J the values are meaningless but every
+  // access stays inside the slabs, and the products are recomputed by the next
+  // solve, which the state reset below requires)
+  TRY(tnrsvd_run(h, nullptr));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TRY(dev_check(hipEventCreate(&e0), "create event"));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(TNRSVD_E_DEVICE, "create event");
+  }
+  const int th[4] = {64, 128, 256, 512};
+  const int cp[4] = {64, 256, 1024, 4096};
+  tnrsvd_status st = TNRSVD_OK;
+  for (int op = 0; op < 2 && st == TNRSVD_OK; ++op) {
+    float best = 1e30f;
+    int bt = h->ct_threads[op], bc = h->ct_cap[op];
+    for (int a = 0; a < 4 && st == TNRSVD_OK; ++a)
+      for (int c = 0; c < 4 && st == TNRSVD_OK; ++c) {
+        auto go = [&]() {
+          return launch_contract(h->mpos_d, h->cores_d, h->core_mpo_d, h->ncores, h->xr, h->pr,
+                                 h->A, h->X, h->Z, h->dtype, op, h->max_core_out, h->err, th[a],
+                                 cp[c], h->stream);
+        };
+        hipError_t e = go();   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = go();
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          st = dev_check(e, "autotune contraction");
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          bt = th[a];
+          bc = cp[c];
+        }
+      }
+    h->ct_threads[op] = bt;
+    h->ct_cap[op] = bc;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  TRY(st);
+  if (choice) {
+    choice[0] = h->ct_threads[0];
+    choice[1] = h->ct_cap[0];
+    choice[2] = h->ct_threads[1];
+    choice[3] = h->ct_cap[1];
+  }
+  // a captured graph holds the old launch shapes: capture again on next use
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  h->space = kNone;
+  h->pending = -1;
+  h->projected = false;
+  h->solved = false;
+  h->y0_valid = false;
+  return TNRSVD_OK;
+}
 
 tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores) {
   TRY(check_handle(h));

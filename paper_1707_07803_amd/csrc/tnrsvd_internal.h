@@ -125,7 +125,8 @@ hipError_t launch_load_omega(const MpoDesc* mpos, const CoreDesc* cores, int bat
                              int64_t max_len, int* err, hipStream_t s);
 hipError_t launch_contract(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
                            int ncores, const int* xr, int* pr, const void* A, const void* X,
-                           void* Z, int dtype, int op, int64_t max_out, int* err, hipStream_t s);
+                           void* Z, int dtype, int op, int64_t max_out, int* err, int threads,
+                           int gcap, hipStream_t s);
 hipError_t launch_copy_y0(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
                           int ncores, const int* pr, const void* Z, void* Y0, int dtype,
                           int64_t max_out, hipStream_t s);

@@ -23,7 +23,7 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16}
 # the C function names exported by the library, in header order
 EXPORTS = [
     "tnrsvd_create", "tnrsvd_mult", "tnrsvd_orthogonalize", "tnrsvd_project",
-    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_refine", "tnrsvd_backward",
+    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_refine", "tnrsvd_backward", "tnrsvd_autotune",
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_run_graph.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_refine.argtypes = [H, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_backward.argtypes = [H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p)]
+    L.tnrsvd_autotune.argtypes = [H, I, ctypes.POINTER(I)]
     L.tnrsvd_get_factor.argtypes = [H, I, I, I, ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I)]
     L.tnrsvd_copy_factor.argtypes = [H, I, I, I, ctypes.c_void_p]
@@ -225,6 +226,13 @@ class TNrSVD:
         ptrs = (ctypes.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
         _check(self._lib.tnrsvd_backward(
             self._h, None if w is None else w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs))
+
+    def autotune(self, reps: int = 5) -> dict:
+        """tnrsvd_autotune: pick the contraction launch shapes for this handle."""
+        out = (ctypes.c_int * 4)()
+        _check(self._lib.tnrsvd_autotune(self._h, int(reps), out))
+        return {"A_X": {"threads": out[0], "blocks_per_core_cap": out[1]},
+                "At_X": {"threads": out[2], "blocks_per_core_cap": out[3]}}
 
     def run_graph(self, want_sigma: bool = True) -> Optional[np.ndarray]:
         """tnrsvd_run captured once into a HIP graph, replayed on later calls."""

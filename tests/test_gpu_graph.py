@@ -1,4 +1,5 @@
-"""Captured-graph solves (tnrsvd_run_graph) against eager solves (tnrsvd_run).
+"""Captured-graph solves (tnrsvd_run_graph) against eager solves (tnrsvd_run),
+and the contraction autotuner (tnrsvd_autotune).
 
 Every replay is checked against the eager result, with eager solves and
 stream synchronisations between the replays; the kernels are deterministic,
@@ -74,5 +75,26 @@ def test_graph_refuses_profiling():
     assert e.value.status == -3
     h.profile(False)
     ref = h.run()[0]
+    np.testing.assert_array_equal(h.run_graph()[0], ref)
+    h.close()
+
+
+def test_autotune_keeps_results_and_recaptures_the_graph():
+    from paper_1707_07803_amd import TNrSVD, TNrSVDError, omega_flat
+    W = wl.spectrum()
+    h = TNrSVD(to_device(W.cores, "f32"), W.k, W.p, W.q, precision="f32",
+               round_tol=W.eps_by_precision["f32"], max_rank=W.rmax)
+    h.set_omega(omega_flat(*omega_for(W.cores, W.K, W.omega_seed)))
+    ref = h.run()[0]
+    np.testing.assert_array_equal(h.run_graph()[0], ref)
+    choice = h.autotune(3)
+    for op in ("A_X", "At_X"):
+        assert choice[op]["threads"] in (64, 128, 256, 512)
+        assert choice[op]["blocks_per_core_cap"] in (64, 256, 1024, 4096)
+    with pytest.raises(TNrSVDError) as e:     # results were invalidated
+        h.solve()
+    assert e.value.status == -3
+    # every launch shape computes each output with the same arithmetic
+    np.testing.assert_array_equal(h.run()[0], ref)
     np.testing.assert_array_equal(h.run_graph()[0], ref)
     h.close()
