@@ -384,6 +384,8 @@ def main():
                 "kernel": "k_rl_pass<T,0> + k_rl_pass<T,1> (one FP64 Householder LQ sweep)",
                 "achieved": round(ach, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / FP64_PEAK_TFLOPS, 6), "traffic": measured_traffic(main_p),
+                # one MPO's sweep runs as one workgroup on one of the 256 CUs
+                "frac_of_one_cu": round(ach / (FP64_PEAK_TFLOPS / 256), 4),
                 "flops_per_launch": fl, "avg_launch_ms": round(avg_ms[dom], 5)}
     else:
         by = counts["contract"][0] / counts["contract"][2]
