@@ -152,3 +152,23 @@ def test_grad_workload_f32_against_oracle():
         fd = (sp.sum() - sm.sum()) / 2e-3
         print(f"  direction {t} (core {i}): frozen-subspace {np.sum(G[i] * D):.6e}, "
               f"pipeline FD {fd:.6e}")
+
+
+def test_backward_errors():
+    import torch
+    from paper_1707_07803_amd import TNrSVD, TNrSVDError
+    W = wl.small()
+    h = TNrSVD(to_device(W.cores), W.k, W.p, 0, seed=4)
+    grads = [torch.empty(c.shape, dtype=torch.float64, device="cuda") for c in W.cores]
+    with pytest.raises(TNrSVDError) as e:        # no solve yet
+        h.backward(None, grads)
+    assert e.value.status == -3
+    h.run()
+    with pytest.raises(TNrSVDError) as e:        # wrong number of weights
+        h.backward(np.ones(W.k + 1), grads)
+    assert e.value.status == -1
+    h.backward(None, grads)                      # all-ones weights
+    G = [g.cpu().numpy() for g in grads]
+    res = o.tnrsvd(W.cores, W.k, W.p, 0, seed=4)
+    assert rel(G, o.sigma_sum_grad(W.cores, res)) <= 1e-8
+    h.close()

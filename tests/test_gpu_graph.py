@@ -98,3 +98,18 @@ def test_autotune_keeps_results_and_recaptures_the_graph():
     np.testing.assert_array_equal(h.run()[0], ref)
     np.testing.assert_array_equal(h.run_graph()[0], ref)
     h.close()
+
+
+def test_graph_on_bf16_handle_then_refine():
+    from paper_1707_07803_amd import TNrSVD, omega_flat
+    W = wl.spectrum()
+    h = TNrSVD(to_device(W.cores, "f32"), W.k, W.p, W.q, precision="bf16",
+               round_tol=W.eps_by_precision["bf16"], max_rank=W.rmax)
+    h.set_omega(omega_flat(*omega_for(W.cores, W.K, W.omega_seed)))
+    ref = h.run()[0]
+    ref_refined = h.refine(W.eps_by_precision["f32"])[0]
+    # the graph restores BF16 after a refinement and replays the BF16 solve
+    for _ in range(2):
+        np.testing.assert_array_equal(h.run_graph()[0], ref)
+        np.testing.assert_array_equal(h.refine(W.eps_by_precision["f32"])[0], ref_refined)
+    h.close()
