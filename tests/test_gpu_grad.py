@@ -172,3 +172,32 @@ def test_backward_errors():
     res = o.tnrsvd(W.cores, W.k, W.p, 0, seed=4)
     assert rel(G, o.sigma_sum_grad(W.cores, res)) <= 1e-8
     h.close()
+
+
+def test_spectrum_gradient_matches_pipeline_finite_differences():
+    """On the known spectrum (sigma_j = 10^(-j/4), K = 30 > k = 20) the computed
+    subspace captures A v_j up to ~sigma_30 / sigma_j, so the derivative at fixed
+    singular vectors is the derivative of the FP64 pipeline to ~1e-6."""
+    W = wl.spectrum()
+    om = omega_for(W.cores, W.K, W.omega_seed)
+    eps = W.eps_by_precision["f64"]
+    sig, h = gpu_solve(W.cores, W.k, W.p, W.q, eps=eps, rmax=W.rmax, omega=om)
+    G = gpu_grad(h, W.cores)
+    h.close()
+    rng = np.random.default_rng(3)
+    step = 1e-5
+    for i in (0, 7, len(W.cores) - 1):
+        D = rng.standard_normal(W.cores[i].shape)
+        D /= np.linalg.norm(D)
+        Ap = [c.copy() for c in W.cores]
+        Ap[i] = Ap[i] + step * D
+        Am = [c.copy() for c in W.cores]
+        Am[i] = Am[i] - step * D
+        sp, hp = gpu_solve(Ap, W.k, W.p, W.q, eps=eps, rmax=W.rmax, omega=om)
+        sm, hm = gpu_solve(Am, W.k, W.p, W.q, eps=eps, rmax=W.rmax, omega=om)
+        hp.close()
+        hm.close()
+        fd = (sp.sum() - sm.sum()) / (2 * step)
+        got = float(np.sum(G[i] * D))
+        print(f"spectrum core {i}: gradient {got:.9e}, pipeline FD {fd:.9e}")
+        assert abs(got - fd) <= 1e-5 * (abs(fd) + np.linalg.norm(G[i]))
