@@ -49,6 +49,7 @@ __all__ = [
     "round_sweep", "tnrsvd", "TNrSVDResult", "dense_rsvd",
     "tnrsvd_paper_orientation", "reverse_mpo",
     "merge_tail_adjoint", "sigma_sum_grad",
+    "sparse_to_mpo",
 ]
 
 # --------------------------------------------------------------------------
@@ -704,3 +705,47 @@ def sigma_sum_grad(A_cores: Sequence[np.ndarray], res: "TNrSVDResult",
         F = np.einsum("rxR,Raxs->ras", U[i], s2)
     m = len(A) - dm + 1
     return gm[:-1] + merge_tail_adjoint(A[dm - 1:], gm[-1]) if m > 1 else gm
+
+
+# --------------------------------------------------------------------------
+# Sparse matrix to MPO (Algorithm 4.1, Sec. 4.1)
+# --------------------------------------------------------------------------
+
+def sparse_to_mpo(coo_row: np.ndarray, coo_col: np.ndarray, coo_val: np.ndarray,
+                  rows: Sequence[int], cols: Sequence[int]) -> List[np.ndarray]:
+    """Algorithm 4.1 on a matrix given by its nonzero entries (COO).
+
+    The partition into I_1 x J_1 blocks follows the Kronecker ordering
+    A^(d) x ... x A^(1) (eq. (1): the first core carries the fastest index), so
+    the block of entry (i, j) is (i // I_1, j // J_1) and its position at level
+    k >= 2 is the k-th mixed-radix digit of that block index.  Every nonzero
+    block X becomes the rank-1 MPO (X, E^(2), ..., E^(d)) with E^(k) the unit
+    matrix of that digit pair, and the terms are summed (MPO addition), so the
+    rank is the number of nonzero blocks (a lemma of Sec. 4.2).  Blocks are
+    taken in increasing order of block_row * (J / J_1) + block_col.
+    """
+    d = len(rows)
+    I1, J1 = rows[0], cols[0]
+    nbc = int(np.prod(cols[1:])) if d > 1 else 1
+    r = np.asarray(coo_row, dtype=np.int64)
+    c = np.asarray(coo_col, dtype=np.int64)
+    v = np.asarray(coo_val, dtype=np.float64)
+    keys = (r // I1) * nbc + (c // J1)
+    blocks = sorted(set(int(k) for k in keys[v != 0.0])) if len(v) else []
+    mpo = None
+    for key in blocks:
+        br, bc = divmod(key, nbc)
+        X = np.zeros((I1, J1))
+        sel = keys == key
+        np.add.at(X, (r[sel] % I1, c[sel] % J1), v[sel])
+        term = [X.reshape(1, I1, J1, 1)]
+        for k in range(1, d):
+            E = np.zeros((rows[k], cols[k]))
+            E[br % rows[k], bc % cols[k]] = 1.0
+            br //= rows[k]
+            bc //= cols[k]
+            term.append(E.reshape(1, rows[k], cols[k], 1))
+        mpo = term if mpo is None else mpo_add(mpo, term)
+    if mpo is None:   # the zero matrix: one zero rank-1 term
+        mpo = [np.zeros((1, rows[k], cols[k], 1)) for k in range(d)]
+    return mpo
