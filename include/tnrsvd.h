@@ -290,6 +290,42 @@ tnrsvd_status tnrsvd_profile(tnrsvd_t h, int enable);
 tnrsvd_status tnrsvd_profile_read(tnrsvd_t h, int kernel, double* total_ms, int64_t* launches);
 tnrsvd_status tnrsvd_get_product_ranks(tnrsvd_t h, int b, int64_t* P_out, int64_t* rho_out);
 
+/*
+ * tnrsvd_sparse_to_mpo -- Algorithm 4.1 (Sec. 4.1): the MPO of a sparse
+ * matrix A (M x N, M = prod rows[k], N = prod cols[k]) given by nnz entries
+ * in COO form, with the mode sizes rows[0..d-1], cols[0..d-1] (HOST arrays)
+ * and the little-endian index ordering of eq. (1): row i = i_1 + I_1 (i_2 +
+ * I_2 (...)), so the first core carries the fastest index.  A is split into
+ * I_1 x J_1 blocks; every block with a nonzero entry becomes one rank-1 term
+ * (X, E^(2), ..., E^(d)), E^(k) being the unit matrix of the block's k-th
+ * row and column digits, and the terms are added, so the MPO rank is the
+ * number of nonzero blocks (the rank lemma of Sec. 4.2):
+ *   core 0 (1, I_1, J_1, R):  [0, x, y, t] = X_t[x, y]
+ *   core k (R, I_k, J_k, R):  [t, i_k(t), j_k(t), t] = 1   (0 < k < d-1)
+ *   core d-1 (R, I_d, J_d, 1): [t, i_d(t), j_d(t), 0] = 1
+ * (a single core, d = 1, is A itself).  Blocks t are numbered in increasing
+ * order of (i / I_1) * (N / J_1) + (j / J_1).  Explicit zeros form no block;
+ * duplicate entries add (atomically: their summation order is not fixed);
+ * the zero matrix gives one all-zero rank-1 term (R = 1).
+ * coo_row, coo_col (int64), coo_val (double): DEVICE arrays of nnz entries,
+ *   in any order; each index must lie in [0, M) resp. [0, N).
+ * Two calls.  With cores == NULL, *nblocks receives R.  With cores != NULL,
+ *   *nblocks must hold that R on input, cores holds d DEVICE pointers to
+ *   caller-allocated FP64 buffers of the shapes above in C order, which are
+ *   overwritten in full; the count is recomputed and nothing is written if it
+ *   differs from *nblocks.
+ * stream: the hipStream_t to run on (NULL: the null stream); the call
+ *   allocates and frees its own scratch and synchronises the stream.
+ * Errors: E_INVALID (null array, *nblocks < 1 with cores); E_SHAPE (d < 1,
+ * a mode size < 1, nnz outside [0, 2^31), dimensions or block positions
+ * beyond 2^62, an index outside the matrix, a block count that differs
+ * from *nblocks: no core written); E_DEVICE.
+ */
+tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* cols, int64_t nnz,
+                                   const int64_t* coo_row, const int64_t* coo_col,
+                                   const double* coo_val, int64_t* nblocks, double* const* cores,
+                                   void* stream);
+
 /* tnrsvd_destroy -- free every device buffer of the handle (NULL is a no-op). */
 tnrsvd_status tnrsvd_destroy(tnrsvd_t h);
 

@@ -1241,4 +1241,44 @@ tnrsvd_status tnrsvd_get_product_ranks(tnrsvd_t h, int b, int64_t* P_out, int64_
   return TNRSVD_OK;
 }
 
+tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* cols, int64_t nnz,
+                                   const int64_t* coo_row, const int64_t* coo_col,
+                                   const double* coo_val, int64_t* nblocks, double* const* cores,
+                                   void* stream) {
+  if (d < 1) return fail(TNRSVD_E_SHAPE, "d must be >= 1");
+  if (!rows || !cols || !nblocks) return fail(TNRSVD_E_INVALID, "null rows/cols/nblocks");
+  if (nnz < 0 || nnz > INT32_MAX) return fail(TNRSVD_E_SHAPE, "nnz must be in [0, 2^31)");
+  if (nnz > 0 && (!coo_row || !coo_col || !coo_val))
+    return fail(TNRSVD_E_INVALID, "null COO array");
+  constexpr int64_t kIdxCap = int64_t(1) << 62;
+  int64_t M = 1, Nc = 1;
+  for (int k = 0; k < d; ++k) {
+    if (rows[k] < 1 || cols[k] < 1) return fail(TNRSVD_E_SHAPE, "mode %d size < 1", k);
+    if (M > kIdxCap / rows[k] || Nc > kIdxCap / cols[k])
+      return fail(TNRSVD_E_SHAPE, "matrix dimensions exceed 2^62");
+    M *= rows[k];
+    Nc *= cols[k];
+  }
+  if ((M / rows[0]) > kIdxCap / (Nc / cols[0]))
+    return fail(TNRSVD_E_SHAPE, "number of block positions exceeds 2^62");
+  const int64_t expect = cores ? *nblocks : -1;
+  if (cores) {
+    if (expect < 1) return fail(TNRSVD_E_INVALID, "*nblocks must hold the rank of the cores");
+    for (int k = 0; k < d; ++k)
+      if (!cores[k]) return fail(TNRSVD_E_INVALID, "null core %d", k);
+  }
+  int bad = 0;
+  int64_t nb = 0;
+  TRY(dev_check(sparse_to_mpo(d, rows, cols, nnz, coo_row, coo_col, coo_val, expect, &nb, cores,
+                              &bad, (hipStream_t)stream),
+                "sparse to MPO"));
+  if (bad) return fail(TNRSVD_E_SHAPE, "COO index outside the %lld x %lld matrix", (long long)M,
+                       (long long)Nc);
+  *nblocks = nb;
+  if (cores && nb != expect)
+    return fail(TNRSVD_E_SHAPE, "the matrix has %lld nonzero blocks, cores sized for %lld",
+                (long long)nb, (long long)expect);
+  return TNRSVD_OK;
+}
+
 }  // extern "C"

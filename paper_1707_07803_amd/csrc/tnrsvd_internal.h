@@ -146,6 +146,10 @@ hipError_t launch_grad_env(const MpoDesc* mpos, const CoreDesc* cores, const Gra
                            const void* A, int dtype, const double* U, const double* V,
                            const double* w, int k, double* ws, double* G, int* err,
                            hipStream_t s);
+hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
+                         const int64_t* row, const int64_t* col, const double* val,
+                         int64_t expect, int64_t* nblocks, double* const* cores, int* bad_index,
+                         hipStream_t s);
 hipError_t launch_merge_pair_bwd(const double* T, const double* C, const double* dN, double* dT,
                                  double* dC, int a, int I1, int J1, int r, int I2, int J2, int b,
                                  hipStream_t s);

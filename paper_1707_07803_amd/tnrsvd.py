@@ -27,7 +27,7 @@ EXPORTS = [
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
-    "tnrsvd_last_error", "tnrsvd_version",
+    "tnrsvd_sparse_to_mpo", "tnrsvd_last_error", "tnrsvd_version",
 ]
 
 # kernel kinds reported by tnrsvd_profile_read
@@ -97,6 +97,10 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.POINTER(ctypes.c_int64)]
     L.tnrsvd_get_product_ranks.argtypes = [H, I, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int64)]
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    L.tnrsvd_sparse_to_mpo.argtypes = [I, P64, P64, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, P64,
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
     L.tnrsvd_last_error.restype = ctypes.c_char_p
     L.tnrsvd_last_error.argtypes = []
     L.tnrsvd_version.restype = ctypes.c_char_p
@@ -342,6 +346,42 @@ def solve(cores, k: int, p: int = 0, q: int = 0, seed: int = 0, precision: str =
     U[-1] = U[-1][:, :, :k].contiguous()
     V[-1] = V[-1][:, :, :k].contiguous()
     return sig, U, V
+
+
+def sparse_to_mpo(rows, cols, coo_row, coo_col, coo_val):
+    """Algorithm 4.1: the MPO cores of a sparse matrix given in COO form.
+
+    rows, cols: mode sizes I_1..I_d, J_1..J_d (eq. (1) ordering, first core
+    fastest).  coo_row, coo_col: int64 device tensors; coo_val: float64 device
+    tensor (same length).  Returns d float64 device tensors (R, I_k, J_k, R')
+    of rank R = number of nonzero I_1 x J_1 blocks, computed by
+    tnrsvd_sparse_to_mpo on the current stream.
+    """
+    import torch
+
+    L = load_library()
+    d = len(rows)
+    if len(cols) != d:
+        raise ValueError("rows and cols differ in length")
+    rr = _dptr([int(x) for x in rows], ntype=ctypes.c_int64)
+    cc = _dptr([int(x) for x in cols], ntype=ctypes.c_int64)
+    nnz = int(coo_val.numel())
+    for t, dt in ((coo_row, torch.int64), (coo_col, torch.int64), (coo_val, torch.float64)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != nnz:
+            raise ValueError("COO arrays must be contiguous device tensors of equal length "
+                             "(int64 indices, float64 values)")
+    dev = coo_val.device
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    args = (ctypes.c_void_p(coo_row.data_ptr()), ctypes.c_void_p(coo_col.data_ptr()),
+            ctypes.c_void_p(coo_val.data_ptr()))
+    nb = ctypes.c_int64(0)
+    _check(L.tnrsvd_sparse_to_mpo(d, rr, cc, nnz, *args, ctypes.byref(nb), None, stream))
+    R = nb.value
+    shapes = [(1 if k == 0 else R, rows[k], cols[k], 1 if k == d - 1 else R) for k in range(d)]
+    cores = [torch.empty(s, dtype=torch.float64, device=dev) for s in shapes]
+    ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+    _check(L.tnrsvd_sparse_to_mpo(d, rr, cc, nnz, *args, ctypes.byref(nb), ptrs, stream))
+    return cores
 
 
 def _autograd_function():

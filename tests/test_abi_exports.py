@@ -51,3 +51,30 @@ def test_version_and_error_string_without_gpu(lib):
     lib.tnrsvd_last_error.restype = ctypes.c_char_p
     assert lib.tnrsvd_version().decode().startswith("tnrsvd")
     assert isinstance(lib.tnrsvd_last_error(), bytes)
+
+
+def test_sparse_to_mpo_rejects_bad_arguments_on_the_host(lib):
+    """Argument checks of tnrsvd_sparse_to_mpo run before any device call."""
+    f = lib.tnrsvd_sparse_to_mpo
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    f.argtypes = [ctypes.c_int, P64, P64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p, P64, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    A2 = ctypes.c_int64 * 2
+    nb = ctypes.c_int64(0)
+    one = ctypes.c_void_p(8)      # never dereferenced: every case fails first
+    cases = [
+        ((0, A2(2, 2), A2(2, 2), 0, None, None, None, ctypes.byref(nb), None, None), -2),
+        ((2, None, A2(2, 2), 0, None, None, None, ctypes.byref(nb), None, None), -1),
+        ((2, A2(2, 2), A2(2, 2), -1, None, None, None, ctypes.byref(nb), None, None), -2),
+        ((2, A2(2, 2), A2(2, 2), 1 << 31, one, one, one, ctypes.byref(nb), None, None), -2),
+        ((2, A2(2, 2), A2(2, 2), 3, None, one, one, ctypes.byref(nb), None, None), -1),
+        ((2, A2(2, 0), A2(2, 2), 0, None, None, None, ctypes.byref(nb), None, None), -2),
+        ((2, A2(1 << 40, 1 << 30), A2(2, 2), 0, None, None, None, ctypes.byref(nb), None, None),
+         -2),
+        ((2, A2(2, 2), A2(2, 2), 0, None, None, None, None, None, None), -1),
+        ((2, A2(2, 2), A2(2, 2), 0, None, None, None, ctypes.byref(nb),
+          (ctypes.c_void_p * 2)(8, 8), None), -1),                   # *nblocks = 0 with cores
+    ]
+    for args, want in cases:
+        assert f(*args) == want, args

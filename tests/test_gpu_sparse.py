@@ -1,0 +1,205 @@
+"""GPU parity of the sparse-to-MPO conversion (Algorithm 4.1) with the oracle.
+
+Both sides receive the same seeded COO arrays.  Without duplicate positions
+every core entry is either a copied input value, 0 or 1, so the cores must be
+bit-identical to the oracle's; with duplicates the GPU adds them with atomics
+in no fixed order, so those sums are compared within a few ulps.  At the full
+sizes the oracle converts a sampled subset of blocks, and the GPU cores
+restricted to those block indices must equal it exactly; counts and sums over
+the whole cores check the rest.
+"""
+
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import tnrsvd_oracle as o
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1707_07803_amd import load_library
+    load_library()
+    yield
+
+
+def gpu_convert(r, c, v, rows, cols):
+    import torch
+    from paper_1707_07803_amd import sparse_to_mpo
+    dev = torch.device("cuda:0")
+    R = torch.as_tensor(np.ascontiguousarray(r, dtype=np.int64), device=dev)
+    C = torch.as_tensor(np.ascontiguousarray(c, dtype=np.int64), device=dev)
+    V = torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64), device=dev)
+    return sparse_to_mpo(rows, cols, R, C, V)
+
+
+def assert_same_cores(gpu, ref):
+    assert [tuple(g.shape) for g in gpu] == [r.shape for r in ref]
+    for g, r in zip(gpu, ref):
+        np.testing.assert_array_equal(g.cpu().numpy(), r)
+
+
+def coo(A):
+    r, c = np.nonzero(A)
+    return r, c, A[r, c]
+
+
+def test_paper_2x6_example():
+    g = json.load(open(os.path.join(GOLD, "sparse_2x6_example.json")))
+    A = np.array(g["matrix"], dtype=float)
+    r, c, v = coo(A)
+    gpu = gpu_convert(r, c, v, g["dims_I"], g["dims_J"])
+    assert_same_cores(gpu, o.sparse_to_mpo(r, c, v, g["dims_I"], g["dims_J"]))
+    np.testing.assert_array_equal(o.mpo_to_dense([x.cpu().numpy() for x in gpu]), A)
+
+
+@pytest.mark.parametrize("rows,cols,seed", [
+    ([16, 2, 2, 2, 2], [16, 2, 2, 2, 2], 1),          # 256 x 256, d = 5
+    ([5, 3, 2], [4, 3, 3], 2),                        # 30 x 36, mixed radix, rectangular
+    ([3, 4], [7, 2], 3),                              # d = 2
+    ([64, 2, 2, 2, 2, 2, 2], [64, 2, 2, 2, 2, 2, 2], 4),   # 4096 x 4096, d = 7
+    ([40, 5, 3], [24, 4, 4], 5),                       # ragged blocks, d = 3
+])
+def test_random_patterns_bit_exact(rows, cols, seed):
+    M, N = int(np.prod(rows)), int(np.prod(cols))
+    rng = np.random.default_rng(seed)
+    nnz = max(1, min((M * N) // 40, 400))
+    pos = rng.choice(M * N, size=min(nnz, M * N), replace=False)
+    r, c = pos // N, pos % N
+    v = rng.standard_normal(r.size)
+    perm = rng.permutation(r.size)                    # input order is irrelevant
+    gpu = gpu_convert(r[perm], c[perm], v[perm], rows, cols)
+    ref = o.sparse_to_mpo(r, c, v, rows, cols)
+    print(f"rows={rows} cols={cols}: nnz {r.size}, rank {ref[0].shape[-1]}")
+    assert_same_cores(gpu, ref)
+
+
+def test_banded_medium_against_full_oracle():
+    r, c, v = wl.banded_sparse(4096, 4000, 150, 40.0, 4, 30, 7)
+    rows = cols = [64, 2, 2, 2, 2, 2, 2]
+    gpu = gpu_convert(r, c, v, rows, cols)
+    ref = o.sparse_to_mpo(r, c, v, rows, cols)
+    print(f"banded 4096: nnz {r.size}, rank {ref[0].shape[-1]}")
+    assert_same_cores(gpu, ref)
+
+
+def test_explicit_zeros_form_no_block():
+    rows, cols = [4, 2, 2], [4, 2, 2]
+    r = np.array([0, 5, 9, 15, 2])
+    c = np.array([0, 12, 3, 15, 1])
+    v = np.array([1.0, 0.0, -2.0, 0.0, 3.0])           # two explicit zeros
+    gpu = gpu_convert(r, c, v, rows, cols)
+    ref = o.sparse_to_mpo(r, c, v, rows, cols)
+    assert ref[0].shape[-1] == 2
+    assert_same_cores(gpu, ref)
+
+
+def test_duplicates_add():
+    rng = np.random.default_rng(9)
+    rows, cols = [8, 2, 2], [8, 2, 2]
+    r = rng.integers(0, 32, 600)
+    c = np.clip(r + rng.integers(-6, 7, 600), 0, 31)
+    v = rng.standard_normal(600)
+    gpu = [x.cpu().numpy() for x in gpu_convert(r, c, v, rows, cols)]
+    ref = o.sparse_to_mpo(r, c, v, rows, cols)
+    assert [g.shape for g in gpu] == [x.shape for x in ref]
+    # sums of up to ~20 terms in another order: a few ulps of the absolute sum
+    absum = o.sparse_to_mpo(r, c, np.abs(v), rows, cols)[0]
+    assert np.all(np.abs(gpu[0] - ref[0]) <= 32 * np.finfo(float).eps * absum)
+    for g, x in zip(gpu[1:], ref[1:]):
+        np.testing.assert_array_equal(g, x)
+
+
+def test_zero_matrix_and_single_core():
+    rows, cols = [4, 2, 2], [2, 2, 2]
+    e = np.zeros(0)
+    for r, c, v in [(e, e, e), (np.array([3]), np.array([1]), np.array([0.0]))]:
+        gpu = gpu_convert(r, c, v, rows, cols)
+        assert [tuple(g.shape) for g in gpu] == [(1, 4, 2, 1), (1, 2, 2, 1), (1, 2, 2, 1)]
+        assert all(float(g.abs().sum()) == 0.0 for g in gpu)
+    # d = 1: the single core is the matrix
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((6, 5)) * (rng.random((6, 5)) < 0.4)
+    r, c, v = coo(A)
+    gpu = gpu_convert(r, c, v, [6], [5])
+    assert_same_cores(gpu, o.sparse_to_mpo(r, c, v, [6], [5]))
+
+
+def test_index_errors_and_rank_mismatch():
+    import torch
+    from paper_1707_07803_amd import TNrSVDError, load_library
+    rows, cols = [4, 2], [4, 2]
+    for r, c in [([0, 8], [1, 1]), ([0, 1], [1, -1])]:
+        with pytest.raises(TNrSVDError) as ei:
+            gpu_convert(np.array(r), np.array(c), np.array([1.0, 2.0]), rows, cols)
+        assert ei.value.status == -2
+    # cores sized for another rank: E_SHAPE and no core written
+    L = load_library()
+    dev = torch.device("cuda:0")
+    R = torch.tensor([0, 5], dtype=torch.int64, device=dev)     # blocks (0,0) and (1,0)
+    C = torch.tensor([1, 2], dtype=torch.int64, device=dev)
+    V = torch.tensor([1.0, 2.0], dtype=torch.float64, device=dev)
+    cores = [torch.full((1, 4, 4, 3), float("nan"), dtype=torch.float64, device=dev),
+             torch.full((3, 2, 2, 1), float("nan"), dtype=torch.float64, device=dev)]
+    ptrs = (ctypes.c_void_p * 2)(*[x.data_ptr() for x in cores])
+    nb = ctypes.c_int64(3)
+    I64 = ctypes.c_int64 * 2
+    st = L.tnrsvd_sparse_to_mpo(2, I64(*rows), I64(*cols), 2, ctypes.c_void_p(R.data_ptr()),
+                                ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                                ctypes.byref(nb), ptrs, None)
+    assert st == -2 and nb.value == 2
+    assert all(bool(torch.isnan(x).all()) for x in cores)
+
+
+def sampled_block_parity(w, n_sample, seed):
+    """Full-size conversion; the oracle converts the entries of a sample of
+    blocks, and the GPU cores restricted to those block indices must match."""
+    import torch
+    gpu = gpu_convert(w.coo_row, w.coo_col, w.coo_val, w.rows, w.cols)
+    d = len(w.rows)
+    I1, J1 = w.rows[0], w.cols[0]
+    nbc = int(np.prod(w.cols[1:])) if d > 1 else 1
+    nz = w.coo_val != 0.0
+    key = (w.coo_row // I1) * nbc + w.coo_col // J1
+    keys = np.unique(key[nz])
+    R = keys.size
+    assert tuple(gpu[0].shape) == (1, I1, J1, R)
+    rng = np.random.default_rng(seed)
+    pick = np.unique(np.concatenate([[0, R - 1], rng.choice(R, min(n_sample, R), replace=False)]))
+    sel = np.isin(key, keys[pick])
+    ref = o.sparse_to_mpo(w.coo_row[sel], w.coo_col[sel], w.coo_val[sel], w.rows, w.cols)
+    t = torch.as_tensor(pick, device=gpu[0].device)
+    np.testing.assert_array_equal(gpu[0].index_select(3, t).cpu().numpy(), ref[0])
+    for k in range(1, d):
+        g = gpu[k].index_select(0, t)
+        if k < d - 1:
+            g = g.index_select(3, t)
+        np.testing.assert_array_equal(g.cpu().numpy(), ref[k])
+    # whole cores: one unit per block in every core k >= 2, the values in core 1
+    for k in range(1, d):
+        assert int(torch.count_nonzero(gpu[k])) == R and float(gpu[k].sum()) == R
+    assert int(torch.count_nonzero(gpu[0])) == int(nz.sum())
+    np.testing.assert_allclose(float(gpu[0].sum()), w.coo_val.sum(), rtol=1e-12)
+    print(f"{w.name}: nnz {w.coo_val.size}, rank {R}, sampled {pick.size} blocks")
+    return gpu
+
+
+def test_power16k_sampled_blocks():
+    sampled_block_parity(wl.power16k(), 24, 11)
+
+
+def test_circuit150k_sampled_blocks():
+    import torch
+    gpu = sampled_block_parity(wl.circuit150k(), 12, 12)
+    del gpu
+    torch.cuda.empty_cache()

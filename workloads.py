@@ -17,6 +17,18 @@ are 2^N x 2^N MPOs with 2 x 2 cores; no dataset is involved):
 * ``batched``    512 MPOs, d in [10,40], I=J in {2,4}, ranks in [4,32],
                  N(0,1/R), K = 8+8, q = 1
 * ``grad``       d=30, 4x4 cores, ranks 16, N(0,1/16), K = 16+8, q = 1
+
+Sparse matrices for the conversion of Algorithm 4.1 (stand-ins for the
+matrices of the collection used in Sec. 6.1 and 6.2, which are not shipped):
+banded patterns with a full diagonal, band offsets ~ round(N(0, s^2)) clipped
+to the bandwidth, a few far symmetric pairs, N(0,1) values (diagonal 4 + |N|),
+duplicates merged (one entry per position, as a stored sparse matrix has):
+
+* ``power16k``   16384 x 16384 (nonzeros in the leading 15838 x 15838, the
+                 rest zero padding), I_1 = J_1 = 256 then six 2 x 2 modes
+                 (d = 7), bandwidth 200, ~4 entries per row, 115 far pairs
+* ``circuit150k`` 150102 x 150102, I = J = (1614, 31, 3) (d = 3), bandwidth
+                 1962, s = 400, ~5 entries per row
 """
 
 from __future__ import annotations
@@ -28,7 +40,8 @@ import numpy as np
 
 __all__ = ["Workload", "random_mpo", "gaussian_omega", "orthonormal_mps",
            "known_spectrum_mpo", "small", "spectrum", "large", "batched",
-           "grad", "get", "WORKLOADS"]
+           "grad", "get", "WORKLOADS", "SparseWorkload", "banded_sparse", "power16k",
+           "circuit150k", "SPARSE_WORKLOADS"]
 
 
 @dataclass
@@ -162,3 +175,54 @@ WORKLOADS = {"small": small, "spectrum": spectrum, "large": large, "grad": grad}
 
 def get(name: str) -> Workload:
     return WORKLOADS[name]()
+
+
+@dataclass
+class SparseWorkload:
+    name: str
+    rows: List[int]                   # I_1..I_d (eq. (1) ordering, first fastest)
+    cols: List[int]                   # J_1..J_d
+    coo_row: np.ndarray               # int64
+    coo_col: np.ndarray               # int64
+    coo_val: np.ndarray               # float64
+
+
+def banded_sparse(n: int, n_used: int, half_bw: int, spread: float, per_row: int,
+                  n_far: int, seed) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """COO of an n x n banded sparse matrix whose nonzeros lie in the leading
+    n_used x n_used part: the full diagonal, per_row - 1 band entries per row at
+    offsets round(N(0, spread^2)) clipped to [-half_bw, half_bw], and n_far
+    symmetric pairs at uniform positions; entries on one position are merged
+    (the last drawn value is kept).  Sorted by (row, col)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    i = np.repeat(np.arange(n_used, dtype=np.int64), per_row - 1)
+    off = np.clip(np.rint(rng.standard_normal(i.size) * spread), -half_bw, half_bw).astype(np.int64)
+    j = i + off
+    ok = (j >= 0) & (j < n_used)
+    fi = rng.integers(0, n_used, n_far)
+    fj = rng.integers(0, n_used, n_far)
+    diag = np.arange(n_used, dtype=np.int64)
+    r = np.concatenate([diag, i[ok], fi, fj])
+    c = np.concatenate([diag, j[ok], fj, fi])
+    fv = rng.standard_normal(n_far)
+    v = np.concatenate([4.0 + np.abs(rng.standard_normal(n_used)),
+                        rng.standard_normal(int(ok.sum())), fv, fv])
+    key = r * n + c
+    _, last = np.unique(key[::-1], return_index=True)
+    keep = key.size - 1 - last                       # last occurrence of every position
+    order = np.argsort(key[keep], kind="stable")
+    keep = keep[order]
+    return r[keep], c[keep], v[keep]
+
+
+def power16k() -> SparseWorkload:
+    r, c, v = banded_sparse(16384, 15838, 200, 80.0, 4, 115, 21)
+    return SparseWorkload("power16k", [256] + [2] * 6, [256] + [2] * 6, r, c, v)
+
+
+def circuit150k() -> SparseWorkload:
+    r, c, v = banded_sparse(150102, 150102, 1962, 400.0, 5, 0, 22)
+    return SparseWorkload("circuit150k", [1614, 31, 3], [1614, 31, 3], r, c, v)
+
+
+SPARSE_WORKLOADS = {"power16k": power16k, "circuit150k": circuit150k}
