@@ -10,11 +10,22 @@
 //   core k   (N, I_k, J_k, N):   [t, i_k(t), j_k(t), t] = 1       (1 < k < d)
 //   core d   (N, I_d, J_d, 1):   [t, i_d(t), j_d(t), 0] = 1
 // Blocks are numbered in increasing order of key = block_row * (J / J_1) +
-// block_col: keys are radix-sorted, block heads flagged and numbered by a
-// prefix sum, and every entry and every unit entry is then scattered in
-// parallel into the zero-filled cores.  Duplicate entries add (FP64 global
-// atomics, so the order of their sum is not fixed).
+// block_col.  Two ways to number them:
+//   bitmap path (at most 2^28 block positions): one bit per position is set
+//     for every nonzero entry, and a block's number is the count of set bits
+//     before its own (word popcounts + a prefix sum), so no sort is needed;
+//   sort path (larger position spaces): the keys are radix-sorted, block
+//     heads flagged and numbered by a prefix sum.
+// The cores are then zero-filled and every entry and every unit entry is
+// scattered into them in parallel.  Duplicate entries add (FP64 global
+// atomics, so the order of their sum is not fixed).  The filling kernels
+// check on the device that the block count equals the rank the caller sized
+// the cores for and that no index was out of range, and write nothing
+// otherwise, so one call needs a single host synchronisation.
 #include <hipcub/hipcub.hpp>
+
+#include <mutex>
+#include <vector>
 
 #include "tnrsvd_internal.h"
 
@@ -22,9 +33,141 @@ namespace tnr {
 
 namespace {
 
+constexpr uint64_t kBitmapMax = uint64_t(1) << 28;   // largest position count of the bitmap path
+constexpr size_t kCacheMax = size_t(256) << 20;      // largest scratch kept between calls
+
+// One core k >= 2 (0-based k >= 1) as the unit-entry kernels see it.
+struct UnitCore {
+  double* p;
+  int64_t Ik, Jk;
+  int64_t rdiv, cdiv;   // digit k of a block row / column index = (index / div) mod dim
+  int64_t last;         // core (N, Ik, Jk, 1) instead of (N, Ik, Jk, N)
+};
+
+// The filling kernels run only when the count (cnt[0], at least 1) equals the
+// rank the caller sized the cores for and no index was out of range (cnt[1]).
+__device__ inline bool fill_ok(const int* cnt, int64_t expect) {
+  const int64_t n = cnt[0] > 0 ? cnt[0] : 1;
+  return cnt[1] == 0 && n == expect;
+}
+
+__device__ inline bool in_matrix(int64_t i, int64_t j, int64_t M, int64_t Nc) {
+  return i >= 0 && i < M && j >= 0 && j < Nc;
+}
+
+// the unit entry of every core k >= 2 for block t with the given key
+__device__ inline void write_units(uint64_t key, int64_t t, int64_t nbc, const UnitCore* uc,
+                                   int nk, int64_t N) {
+  const int64_t br = (int64_t)(key / (uint64_t)nbc), bc = (int64_t)(key % (uint64_t)nbc);
+  for (int k = 0; k < nk; ++k) {
+    const UnitCore c = uc[k];
+    const int64_t ik = (br / c.rdiv) % c.Ik, jk = (bc / c.cdiv) % c.Jk;
+    const int64_t at = (t * c.Ik + ik) * c.Jk + jk;
+    c.p[c.last ? at : at * N + t] = 1.0;
+  }
+}
+
+// ---------------------------------------------------------------- bitmap path
+
+// Set the bit of every nonzero entry's block; an index outside the matrix
+// raises bad[0].  Neighbouring entries mostly share a block, so a wave first
+// ORs the bits of lanes with the same bitmap word together and one lane sets
+// them, only if they are not already set (read at device scope, past the CU's
+// cache): the atomics stay few even when every entry hits a handful of words.
+__global__ void k_mark(const int64_t* __restrict__ row, const int64_t* __restrict__ col,
+                       const double* __restrict__ val, int64_t nnz, int64_t M, int64_t Nc,
+                       int64_t I1, int64_t J1, int64_t nbc, unsigned* __restrict__ bm,
+                       int* __restrict__ bad) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // the loop bound is uniform over a wave, so every lane takes part in the shuffles
+  for (int64_t wb = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); wb < nnz;
+       wb += stride) {
+    const int64_t e = wb + lane;
+    bool has = false;
+    unsigned w = 0, bit = 0;
+    if (e < nnz) {
+      const int64_t i = row[e], j = col[e];
+      if (!in_matrix(i, j, M, Nc)) {
+        bad[0] = 1;
+      } else if (val[e] != 0.0) {
+        const uint64_t key = (uint64_t)((i / I1) * nbc + j / J1);
+        has = true;
+        w = (unsigned)(key >> 5);
+        bit = 1u << (key & 31);
+      }
+    }
+    uint64_t pending = __ballot(has);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const unsigned lw = __shfl(w, leader);
+      const bool mine = has && w == lw;
+      unsigned b = mine ? bit : 0u;
+      for (int off = 32; off > 0; off >>= 1) b |= __shfl_xor(b, off);
+      if (lane == leader) {
+        const unsigned cur = __hip_atomic_load(bm + lw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((cur & b) != b) atomicOr(bm + lw, b);
+      }
+      pending &= ~__ballot(mine);
+    }
+  }
+}
+
+__global__ void k_popc(const unsigned* __restrict__ bm, int64_t nw, int* __restrict__ pc) {
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw;
+       w += (int64_t)gridDim.x * blockDim.x)
+    pc[w] = __popc(bm[w]);
+}
+
+// cnt[0] = number of blocks (ws = inclusive prefix sum of the word popcounts)
+__global__ void k_total(const int* __restrict__ ws, int64_t nw, int* __restrict__ cnt) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[0] = ws[nw - 1];
+}
+
+// block number of a marked key: set bits before it
+__device__ inline int64_t block_of(const unsigned* bm, const int* ws, uint64_t key) {
+  const unsigned word = bm[key >> 5];
+  return ws[key >> 5] - __popc(word) + __popc(word & ((1u << (key & 31)) - 1u));
+}
+
+// X_t[x, y] += value for every nonzero entry, into core 1 (1, I1, J1, N)
+__global__ void k_scatter_bm(const int64_t* __restrict__ row, const int64_t* __restrict__ col,
+                             const double* __restrict__ val, int64_t nnz, int64_t I1, int64_t J1,
+                             int64_t nbc, const unsigned* __restrict__ bm,
+                             const int* __restrict__ ws, const int* __restrict__ cnt,
+                             int64_t expect, double* __restrict__ core1) {
+  if (!fill_ok(cnt, expect)) return;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = val[e];
+    if (v == 0.0) continue;
+    const int64_t i = row[e], j = col[e];
+    const int64_t t = block_of(bm, ws, (uint64_t)((i / I1) * nbc + j / J1));
+    atomicAdd(core1 + ((i % I1) * J1 + j % J1) * expect + t, v);
+  }
+}
+
+// unit entries of cores k >= 2: one thread per block position, working where its bit is set
+__global__ void k_units_bm(const unsigned* __restrict__ bm, const int* __restrict__ ws,
+                           int64_t nw, int64_t nbc, const UnitCore* __restrict__ uc, int nk,
+                           const int* __restrict__ cnt, int64_t expect) {
+  if (!fill_ok(cnt, expect)) return;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nw * 32;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned word = bm[g >> 5];
+    const unsigned b = (unsigned)(g & 31);
+    if (!((word >> b) & 1u)) continue;
+    const int64_t t = ws[g >> 5] - __popc(word) + __popc(word & ((1u << b) - 1u));
+    write_units((uint64_t)g, t, nbc, uc, nk, expect);
+  }
+}
+
+// ------------------------------------------------------------------ sort path
+
 // Sort key of entry e, or the sentinel `none` (the number of block positions)
-// for an explicit zero, which sorts after every block and forms none; the
-// entry's position goes to idx.  An index outside the matrix raises bad[0].
+// for an explicit zero or an index outside the matrix (which raises bad[0]);
+// either sorts after every block and forms none.  The entry's position goes to
+// idx.
 __global__ void k_block_keys(const int64_t* __restrict__ row, const int64_t* __restrict__ col,
                              const double* __restrict__ val, int64_t nnz, int64_t M, int64_t Nc,
                              int64_t I1, int64_t J1, int64_t nbc, uint64_t none,
@@ -33,7 +176,7 @@ __global__ void k_block_keys(const int64_t* __restrict__ row, const int64_t* __r
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = row[e], j = col[e];
-    const bool in = i >= 0 && i < M && j >= 0 && j < Nc;
+    const bool in = in_matrix(i, j, M, Nc);
     if (!in) bad[0] = 1;
     key[e] = (in && val[e] != 0.0) ? (uint64_t)((i / I1) * nbc + j / J1) : none;
     idx[e] = e;
@@ -48,52 +191,50 @@ __global__ void k_heads(const uint64_t* __restrict__ key, int64_t nnz, uint64_t 
     flag[e] = (key[e] != none && (e == 0 || key[e] != key[e - 1])) ? 1 : 0;
 }
 
-// key of every block (scan = inclusive prefix sum of the heads) and the block
-// count
+// key of every block (scan = inclusive prefix sum of the heads) and the count
 __global__ void k_block_ids(const uint64_t* __restrict__ key, const int* __restrict__ flag,
                             const int* __restrict__ scan, int64_t nnz, uint64_t* __restrict__ bkey,
-                            int* __restrict__ nblk) {
+                            int* __restrict__ cnt) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
        e += (int64_t)gridDim.x * blockDim.x) {
     if (flag[e]) bkey[scan[e] - 1] = key[e];
-    if (e == nnz - 1) nblk[0] = scan[e];
+    if (e == nnz - 1) cnt[0] = scan[e];
   }
 }
 
-// X_t[x, y] += value for every nonzero entry, into core 1 (1, I1, J1, N)
-__global__ void k_scatter_blocks(const uint64_t* __restrict__ key, const int64_t* __restrict__ idx,
+__global__ void k_scatter_sorted(const uint64_t* __restrict__ key, const int64_t* __restrict__ idx,
                                  const int* __restrict__ scan, const int64_t* __restrict__ row,
                                  const int64_t* __restrict__ col, const double* __restrict__ val,
-                                 int64_t nnz, uint64_t none, int64_t I1, int64_t J1, int64_t N,
+                                 int64_t nnz, uint64_t none, int64_t I1, int64_t J1,
+                                 const int* __restrict__ cnt, int64_t expect,
                                  double* __restrict__ core1) {
+  if (!fill_ok(cnt, expect)) return;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
        e += (int64_t)gridDim.x * blockDim.x) {
     if (key[e] == none) continue;
     const int64_t src = idx[e];
     const int64_t t = scan[e] - 1;
     const int64_t x = row[src] % I1, y = col[src] % J1;
-    atomicAdd(core1 + (x * J1 + y) * N + t, val[src]);
+    atomicAdd(core1 + (x * J1 + y) * expect + t, val[src]);
   }
 }
 
-// unit entry of core k >= 2 for every block t: digit k of its row and column
-// block index, digit = (index / div) mod dim
-__global__ void k_unit_entries(const uint64_t* __restrict__ bkey, int64_t N, int64_t nbc,
-                               int64_t rdiv, int64_t cdiv, int64_t Ik, int64_t Jk, int last,
-                               double* __restrict__ core) {
+__global__ void k_units_sorted(const uint64_t* __restrict__ bkey, int64_t nbc,
+                               const UnitCore* __restrict__ uc, int nk, const int* __restrict__ cnt,
+                               int64_t expect) {
+  if (!fill_ok(cnt, expect)) return;
+  const int64_t N = cnt[0];
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t br = (int64_t)(bkey[t] / (uint64_t)nbc), bc = (int64_t)(bkey[t] % (uint64_t)nbc);
-    const int64_t ik = (br / rdiv) % Ik, jk = (bc / cdiv) % Jk;
-    if (last)
-      core[(t * Ik + ik) * Jk + jk] = 1.0;
-    else
-      core[((t * Ik + ik) * Jk + jk) * N + t] = 1.0;
-  }
+       t += (int64_t)gridDim.x * blockDim.x)
+    write_units(bkey[t], t, nbc, uc, nk, expect);
 }
 
-// p[0..n) = 0, 16-byte stores over the aligned body
-__global__ void k_zero(double* __restrict__ p, int64_t n) {
+// ------------------------------------------------------------------- filling
+
+// p[0..n) = 0 with 16-byte stores over the aligned body (when the fill is allowed)
+__global__ void k_zero(double* __restrict__ p, int64_t n, const int* __restrict__ cnt,
+                       int64_t expect) {
+  if (!fill_ok(cnt, expect)) return;
   const int64_t head = (int64_t)(((16 - ((uintptr_t)p & 15)) & 15) / sizeof(double));
   const int64_t h = head < n ? head : n;
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -102,9 +243,7 @@ __global__ void k_zero(double* __restrict__ p, int64_t n) {
   double2* q = reinterpret_cast<double2*>(p + h);
   const int64_t n2 = (n - h) / 2;
   for (int64_t e = tid; e < n2; e += stride) q[e] = double2{0.0, 0.0};
-  if ((n - h) & 1) {
-    if (tid == 0) p[n - 1] = 0.0;
-  }
+  if (((n - h) & 1) && tid == 0) p[n - 1] = 0.0;
 }
 
 int grid_n(int64_t n) {
@@ -114,105 +253,191 @@ int grid_n(int64_t n) {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Scratch kept per device between calls (up to kCacheMax bytes); the mutex is
+// held for a whole call, which ends with a stream synchronisation.
+std::mutex g_scratch_mu;
+std::vector<std::pair<char*, size_t>> g_scratch;
+
 }  // namespace
 
-// Counts the nonzero blocks (*nblocks) and, when cores is not null and the
-// count equals `expect` (the rank the cores were sized for), fills the d
-// caller-allocated FP64 cores.  Shapes are validated by the caller; indices
-// outside the matrix are reported through *bad_index and then no core is
-// written.  One scratch allocation per call; the stream is synchronised to
-// read the block count back.
+// Counts the nonzero blocks (*nblocks) and, when cores is not null, fills the
+// d caller-allocated FP64 cores if the count equals `expect` (the rank they
+// were sized for).  Shapes are validated by the caller; an index outside the
+// matrix is reported through *bad_index and then no core is written.
 hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
                          const int64_t* row, const int64_t* col, const double* val,
                          int64_t expect, int64_t* nblocks, double* const* cores, int* bad_index,
                          hipStream_t s) {
-  int64_t M = 1, Nc = 1, nbc = 1;
+  int64_t M = 1, Nc = 1;
   for (int k = 0; k < d; ++k) {
     M *= I[k];
     Nc *= J[k];
   }
-  nbc = Nc / J[0];
+  const int64_t nbc = Nc / J[0];
   const uint64_t none = (uint64_t)(M / I[0]) * (uint64_t)nbc;   // number of block positions
+  const bool bitmap = none <= kBitmapMax;
+  const int n = (int)(nnz > 0 ? nnz : 1);
+  const int64_t nw = (int64_t)((none + 31) / 32);
   int end_bit = 1;
   while (end_bit < 64 && (none >> end_bit) != 0) ++end_bit;
-  const int n = (int)(nnz > 0 ? nnz : 1);
 
-  size_t tmp_sort = 0, tmp_scan = 0;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_sort, (uint64_t*)nullptr,
-                                                    (uint64_t*)nullptr, (int64_t*)nullptr,
-                                                    (int64_t*)nullptr, n, 0, end_bit, s);
-  if (e == hipSuccess)
-    e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp_scan, (int*)nullptr, (int*)nullptr, n, s);
-  if (e != hipSuccess) return e;
-  // scratch: key, skey, bkey (u64), idx, sidx (i64), flag, scan (int), nblk+bad (int), tmp
-  const size_t o_key = 0, o_skey = o_key + align_up(8 * (size_t)n),
-               o_bkey = o_skey + align_up(8 * (size_t)n), o_idx = o_bkey + align_up(8 * (size_t)n),
-               o_sidx = o_idx + align_up(8 * (size_t)n), o_flag = o_sidx + align_up(8 * (size_t)n),
-               o_scan = o_flag + align_up(4 * (size_t)n), o_cnt = o_scan + align_up(4 * (size_t)n),
-               o_tmp = o_cnt + 256,
-               total = o_tmp + align_up(tmp_sort > tmp_scan ? tmp_sort : tmp_scan);
-  char* base = nullptr;
-  e = hipMalloc((void**)&base, total);
-  if (e != hipSuccess) return e;
-  uint64_t* key = (uint64_t*)(base + o_key);
-  uint64_t* skey = (uint64_t*)(base + o_skey);
-  uint64_t* bkey = (uint64_t*)(base + o_bkey);
-  int64_t* idx = (int64_t*)(base + o_idx);
-  int64_t* sidx = (int64_t*)(base + o_sidx);
-  int* flag = (int*)(base + o_flag);
-  int* scan = (int*)(base + o_scan);
-  int* cnt = (int*)(base + o_cnt);   // cnt[0] blocks, cnt[1] bad index
-  void* tmp = base + o_tmp;
-  size_t tmp_bytes = total - o_tmp;
-
-  int hc[2] = {0, 0};
-  e = hipMemsetAsync(cnt, 0, 2 * sizeof(int), s);
-  if (e == hipSuccess && nnz > 0) {
-    k_block_keys<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, M, Nc, I[0], J[0], nbc, none, key,
-                                             idx, cnt + 1);
-    e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, skey, idx, sidx, (int)nnz, 0,
-                                           end_bit, s);
-    if (e == hipSuccess) {
-      k_heads<<<grid_n(nnz), 256, 0, s>>>(skey, nnz, none, flag);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, flag, scan, (int)nnz, s);
-    if (e == hipSuccess) {
-      k_block_ids<<<grid_n(nnz), 256, 0, s>>>(skey, flag, scan, nnz, bkey, cnt);
-      e = hipGetLastError();
+  // unit-entry table of cores 2..d
+  std::vector<UnitCore> uc;
+  if (cores) {
+    int64_t rdiv = 1, cdiv = 1;
+    for (int k = 1; k < d; ++k) {
+      uc.push_back(UnitCore{cores[k], I[k], J[k], rdiv, cdiv, k == d - 1 ? 1 : 0});
+      rdiv *= I[k];
+      cdiv *= J[k];
     }
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(hc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  const int N = hc[0];
-  *bad_index = hc[1];
-  // the zero matrix is one zero rank-1 term
-  const int64_t Nr = N > 0 ? N : 1;
-  if (e == hipSuccess) *nblocks = Nr;
-  if (e == hipSuccess && cores && !hc[1] && Nr == expect) {
-    for (int k = 0; k < d && e == hipSuccess; ++k) {
-      const int64_t a = k == 0 ? 1 : Nr, b = (k == d - 1) ? 1 : Nr;
-      const int64_t len = a * I[k] * J[k] * b;
-      k_zero<<<grid_n(len / 2 + 1), 256, 0, s>>>(cores[k], len);
-      e = hipGetLastError();
+  const size_t uc_bytes = align_up(sizeof(UnitCore) * (uc.size() + 1));
+
+  hipError_t e = hipSuccess;
+  size_t tmp_bytes = 0;
+  size_t o_a, o_b, o_c, o_d, o_e, o_f, o_cnt, o_uc, o_tmp, total;
+  if (bitmap) {
+    // a: bitmap, b: word popcounts, c: their inclusive prefix sum
+    e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, (int*)nullptr, (int*)nullptr,
+                                         (int)nw, s);
+    o_a = 0;
+    o_b = o_a + align_up(4 * (size_t)nw);
+    o_c = o_b + align_up(4 * (size_t)nw);
+    o_d = o_e = o_f = o_c + align_up(4 * (size_t)nw);
+  } else {
+    // a: keys, b: sorted keys, c: block keys, d: positions, e: sorted positions, f: heads + scan
+    size_t t_sort = 0, t_scan = 0;
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, t_sort, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                           (int64_t*)nullptr, (int64_t*)nullptr, n, 0, end_bit, s);
+    if (e == hipSuccess)
+      e = hipcub::DeviceScan::InclusiveSum(nullptr, t_scan, (int*)nullptr, (int*)nullptr, n, s);
+    tmp_bytes = t_sort > t_scan ? t_sort : t_scan;
+    o_a = 0;
+    o_b = o_a + align_up(8 * (size_t)n);
+    o_c = o_b + align_up(8 * (size_t)n);
+    o_d = o_c + align_up(8 * (size_t)n);
+    o_e = o_d + align_up(8 * (size_t)n);
+    o_f = o_e + align_up(8 * (size_t)n);
+  }
+  if (e != hipSuccess) return e;
+  o_cnt = (bitmap ? o_d : o_f + 2 * align_up(4 * (size_t)n));
+  o_uc = o_cnt + 256;
+  o_tmp = o_uc + uc_bytes;
+  total = o_tmp + align_up(tmp_bytes > 0 ? tmp_bytes : 1);
+
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, {nullptr, 0});
+  char* base = nullptr;
+  bool owned = false;
+  if (total <= kCacheMax) {
+    auto& sc = g_scratch[dev];
+    if (sc.second < total) {
+      if (sc.first) (void)hipFree(sc.first);
+      sc = {nullptr, 0};
+      e = hipMalloc((void**)&sc.first, total);
+      if (e != hipSuccess) {
+        sc.first = nullptr;
+        return e;
+      }
+      sc.second = total;
     }
-    if (e == hipSuccess && N > 0) {
-      k_scatter_blocks<<<grid_n(nnz), 256, 0, s>>>(skey, sidx, scan, row, col, val, nnz, none,
-                                                   I[0], J[0], Nr, cores[0]);
+    base = sc.first;
+  } else {
+    e = hipMalloc((void**)&base, total);
+    if (e != hipSuccess) return e;
+    owned = true;
+  }
+  int* cnt = (int*)(base + o_cnt);   // cnt[0] blocks, cnt[1] index outside the matrix
+  UnitCore* duc = (UnitCore*)(base + o_uc);
+  void* tmp = base + o_tmp;
+
+  e = hipMemsetAsync(cnt, 0, 2 * sizeof(int), s);
+  if (e == hipSuccess && !uc.empty())
+    e = hipMemcpyAsync(duc, uc.data(), sizeof(UnitCore) * uc.size(), hipMemcpyHostToDevice, s);
+  const int nk = (int)uc.size();
+  if (bitmap) {
+    unsigned* bm = (unsigned*)(base + o_a);
+    int* pc = (int*)(base + o_b);
+    int* ws = (int*)(base + o_c);
+    if (e == hipSuccess) e = hipMemsetAsync(bm, 0, 4 * (size_t)nw, s);
+    if (e == hipSuccess && nnz > 0) {
+      k_mark<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, M, Nc, I[0], J[0], nbc, bm, cnt + 1);
+      k_popc<<<grid_n(nw), 256, 0, s>>>(bm, nw, pc);
       e = hipGetLastError();
-      int64_t rdiv = 1, cdiv = 1;
-      for (int k = 1; k < d && e == hipSuccess; ++k) {
-        k_unit_entries<<<grid_n(N), 256, 0, s>>>(bkey, N, nbc, rdiv, cdiv, I[k], J[k],
-                                                 k == d - 1, cores[k]);
+      if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, pc, ws, (int)nw, s);
+      if (e == hipSuccess) {
+        k_total<<<1, 64, 0, s>>>(ws, nw, cnt);
         e = hipGetLastError();
-        rdiv *= I[k];
-        cdiv *= J[k];
       }
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && cores) {
+      for (int k = 0; k < d && e == hipSuccess; ++k) {
+        const int64_t len = (k == 0 ? 1 : expect) * I[k] * J[k] * (k == d - 1 ? 1 : expect);
+        k_zero<<<grid_n(len / 2 + 1), 256, 0, s>>>(cores[k], len, cnt, expect);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess && nnz > 0) {
+        k_scatter_bm<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, I[0], J[0], nbc, bm, ws, cnt,
+                                                 expect, cores[0]);
+        if (nk > 0) k_units_bm<<<grid_n(nw * 32), 256, 0, s>>>(bm, ws, nw, nbc, duc, nk, cnt, expect);
+        e = hipGetLastError();
+      }
+    }
+  } else {
+    uint64_t* key = (uint64_t*)(base + o_a);
+    uint64_t* skey = (uint64_t*)(base + o_b);
+    uint64_t* bkey = (uint64_t*)(base + o_c);
+    int64_t* idx = (int64_t*)(base + o_d);
+    int64_t* sidx = (int64_t*)(base + o_e);
+    int* flag = (int*)(base + o_f);
+    int* scan = (int*)(base + o_f + align_up(4 * (size_t)n));
+    if (e == hipSuccess && nnz > 0) {
+      k_block_keys<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, M, Nc, I[0], J[0], nbc, none,
+                                               key, idx, cnt + 1);
+      e = hipGetLastError();
+      if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, skey, idx, sidx, (int)nnz, 0,
+                                               end_bit, s);
+      if (e == hipSuccess) {
+        k_heads<<<grid_n(nnz), 256, 0, s>>>(skey, nnz, none, flag);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess)
+        e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, flag, scan, (int)nnz, s);
+      if (e == hipSuccess) {
+        k_block_ids<<<grid_n(nnz), 256, 0, s>>>(skey, flag, scan, nnz, bkey, cnt);
+        e = hipGetLastError();
+      }
+    }
+    if (e == hipSuccess && cores) {
+      for (int k = 0; k < d && e == hipSuccess; ++k) {
+        const int64_t len = (k == 0 ? 1 : expect) * I[k] * J[k] * (k == d - 1 ? 1 : expect);
+        k_zero<<<grid_n(len / 2 + 1), 256, 0, s>>>(cores[k], len, cnt, expect);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess && nnz > 0) {
+        k_scatter_sorted<<<grid_n(nnz), 256, 0, s>>>(skey, sidx, scan, row, col, val, nnz, none,
+                                                     I[0], J[0], cnt, expect, cores[0]);
+        if (nk > 0) k_units_sorted<<<grid_n(nnz), 256, 0, s>>>(bkey, nbc, duc, nk, cnt, expect);
+        e = hipGetLastError();
+      }
+    }
   }
-  const hipError_t ef = hipFree(base);
-  return e != hipSuccess ? e : ef;
+  int hc[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(hc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) {
+    *bad_index = hc[1];
+    *nblocks = hc[0] > 0 ? hc[0] : 1;   // the zero matrix is one zero rank-1 term
+  }
+  if (owned) {
+    const hipError_t ef = hipFree(base);
+    if (e == hipSuccess) e = ef;
+  }
+  return e;
 }
 
 }  // namespace tnr

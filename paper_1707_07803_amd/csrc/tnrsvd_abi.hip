@@ -1264,6 +1264,13 @@ tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* co
   const int64_t expect = cores ? *nblocks : -1;
   if (cores) {
     if (expect < 1) return fail(TNRSVD_E_INVALID, "*nblocks must hold the rank of the cores");
+    if (expect > (nnz > 0 ? nnz : 1))
+      return fail(TNRSVD_E_SHAPE, "rank %lld exceeds the number of entries", (long long)expect);
+    for (int k = 0; k < d; ++k) {
+      const int64_t len = sat_mul(sat_mul(k == 0 ? 1 : expect, rows[k]),
+                                  sat_mul(cols[k], k == d - 1 ? 1 : expect));
+      if (len >= kSat) return fail(TNRSVD_E_SHAPE, "core %d would exceed 2^40 entries", k);
+    }
     for (int k = 0; k < d; ++k)
       if (!cores[k]) return fail(TNRSVD_E_INVALID, "null core %d", k);
   }

@@ -76,5 +76,8 @@ def test_sparse_to_mpo_rejects_bad_arguments_on_the_host(lib):
         ((2, A2(2, 2), A2(2, 2), 0, None, None, None, ctypes.byref(nb),
           (ctypes.c_void_p * 2)(8, 8), None), -1),                   # *nblocks = 0 with cores
     ]
+    nb5 = ctypes.c_int64(5)           # rank 5 from no entries: E_SHAPE before any device call
+    cases.append(((2, A2(2, 2), A2(2, 2), 0, None, None, None, ctypes.byref(nb5),
+                   (ctypes.c_void_p * 2)(8, 8), None), -2))
     for args, want in cases:
         assert f(*args) == want, args

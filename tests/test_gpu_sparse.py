@@ -69,12 +69,15 @@ def test_paper_2x6_example():
     ([3, 4], [7, 2], 3),                              # d = 2
     ([64, 2, 2, 2, 2, 2, 2], [64, 2, 2, 2, 2, 2, 2], 4),   # 4096 x 4096, d = 7
     ([40, 5, 3], [24, 4, 4], 5),                       # ragged blocks, d = 3
+    # more than 2^28 block positions: the sort path
+    ([2] * 16, [2] * 16, 6),                           # 2^30 positions
+    ([4] + [8] * 7, [2] + [8] * 7, 7),                 # 2^42 positions, rectangular
 ])
 def test_random_patterns_bit_exact(rows, cols, seed):
     M, N = int(np.prod(rows)), int(np.prod(cols))
     rng = np.random.default_rng(seed)
-    nnz = max(1, min((M * N) // 40, 400))
-    pos = rng.choice(M * N, size=min(nnz, M * N), replace=False)
+    nnz = max(1, min((M * N) // 40, 400 if len(rows) <= 7 else 100))
+    pos = np.unique(rng.integers(0, M * N, size=nnz))
     r, c = pos // N, pos % N
     v = rng.standard_normal(r.size)
     perm = rng.permutation(r.size)                    # input order is irrelevant
@@ -146,15 +149,15 @@ def test_index_errors_and_rank_mismatch():
     # cores sized for another rank: E_SHAPE and no core written
     L = load_library()
     dev = torch.device("cuda:0")
-    R = torch.tensor([0, 5], dtype=torch.int64, device=dev)     # blocks (0,0) and (1,0)
-    C = torch.tensor([1, 2], dtype=torch.int64, device=dev)
-    V = torch.tensor([1.0, 2.0], dtype=torch.float64, device=dev)
+    R = torch.tensor([0, 5, 1], dtype=torch.int64, device=dev)  # blocks (0,0) and (1,0)
+    C = torch.tensor([1, 2, 0], dtype=torch.int64, device=dev)
+    V = torch.tensor([1.0, 2.0, 3.0], dtype=torch.float64, device=dev)
     cores = [torch.full((1, 4, 4, 3), float("nan"), dtype=torch.float64, device=dev),
              torch.full((3, 2, 2, 1), float("nan"), dtype=torch.float64, device=dev)]
     ptrs = (ctypes.c_void_p * 2)(*[x.data_ptr() for x in cores])
     nb = ctypes.c_int64(3)
     I64 = ctypes.c_int64 * 2
-    st = L.tnrsvd_sparse_to_mpo(2, I64(*rows), I64(*cols), 2, ctypes.c_void_p(R.data_ptr()),
+    st = L.tnrsvd_sparse_to_mpo(2, I64(*rows), I64(*cols), 3, ctypes.c_void_p(R.data_ptr()),
                                 ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(V.data_ptr()),
                                 ctypes.byref(nb), ptrs, None)
     assert st == -2 and nb.value == 2
