@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct tnrsvd_s* tnrsvd_t;
+typedef struct tnrsvd_rounded_s* tnrsvd_rounded_t;
 
 typedef enum {
   TNRSVD_OK = 0,
@@ -325,6 +326,41 @@ tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* co
                                    const int64_t* coo_row, const int64_t* coo_col,
                                    const double* coo_val, int64_t* nblocks, double* const* cores,
                                    void* stream);
+
+/*
+ * tnrsvd_sparse_round -- the SVD-based rounding of Sec. 3 applied to the MPO
+ * that Algorithm 4.1 (tnrsvd_sparse_to_mpo) builds from the same COO input,
+ * computed without forming that MPO.  The rounding is the one the paper uses
+ * on its converted matrices (Sec. 6.1): orthogonalise right to left, then
+ * truncate left to right with singular-value tail delta = round_tol * |A|_F /
+ * sqrt(d - 1) per bond (ranks capped at max_rank when max_rank > 0, and >= 1).
+ * Result, in C order: core 0 (1, I_1, J_1, r_1), core k (r_k, I_k, J_k,
+ * r_{k+1}), last core (r_{d-1}, I_d, J_d, 1); cores 0..d-2 are
+ * left-orthonormal, with each left singular vector signed so that its entry
+ * of largest magnitude (the first on ties) is positive, and the last core
+ * carries the rest.  Since the selection cores orthogonalise exactly, only the
+ * first core's truncated SVD is large (I_1 J_1 x R, R nonzero blocks): it runs
+ * as a TSQR over all CUs; every later core is one small SVD.
+ * Arguments as tnrsvd_sparse_to_mpo.  The zero matrix gives all-zero rank-1
+ * cores; d = 1 gives the matrix itself.  Limits: at most 2^28 block
+ * positions (I / I_1)(J / J_1) and 16384 nonzero blocks.
+ * stream: hipStream_t (NULL: null stream); the call allocates its own
+ * workspace, frees it, and synchronises the stream.
+ * *out receives a handle owning the rounded cores (device memory) until
+ * tnrsvd_rounded_destroy.  tnrsvd_rounded_ranks writes the d + 1 ranks
+ * r_0 = 1, ..., r_d = 1 (HOST array).  tnrsvd_rounded_copy copies core k into
+ * the DEVICE buffer dst (r_k I_k J_k r_{k+1} doubles) and synchronises.
+ * Errors: E_INVALID (null argument, round_tol negative or not finite,
+ * max_rank < 0, k out of range); E_SHAPE (as tnrsvd_sparse_to_mpo, or a
+ * limit above exceeded); E_DEVICE.
+ */
+tnrsvd_status tnrsvd_sparse_round(int d, const int64_t* rows, const int64_t* cols, int64_t nnz,
+                                  const int64_t* coo_row, const int64_t* coo_col,
+                                  const double* coo_val, double round_tol, int max_rank,
+                                  void* stream, tnrsvd_rounded_t* out);
+tnrsvd_status tnrsvd_rounded_ranks(tnrsvd_rounded_t r, int64_t* ranks);
+tnrsvd_status tnrsvd_rounded_copy(tnrsvd_rounded_t r, int k, double* dst);
+tnrsvd_status tnrsvd_rounded_destroy(tnrsvd_rounded_t r);
 
 /* tnrsvd_destroy -- free every device buffer of the handle (NULL is a no-op). */
 tnrsvd_status tnrsvd_destroy(tnrsvd_t h);

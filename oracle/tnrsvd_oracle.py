@@ -49,7 +49,7 @@ __all__ = [
     "round_sweep", "tnrsvd", "TNrSVDResult", "dense_rsvd",
     "tnrsvd_paper_orientation", "reverse_mpo",
     "merge_tail_adjoint", "sigma_sum_grad",
-    "sparse_to_mpo",
+    "sparse_to_mpo", "round_mpo",
 ]
 
 # --------------------------------------------------------------------------
@@ -749,3 +749,25 @@ def sparse_to_mpo(coo_row: np.ndarray, coo_col: np.ndarray, coo_val: np.ndarray,
     if mpo is None:   # the zero matrix: one zero rank-1 term
         mpo = [np.zeros((1, rows[k], cols[k], 1)) for k in range(d)]
     return mpo
+
+
+def round_mpo(cores: Sequence[np.ndarray], eps: float, rmax: int = 0) -> List[np.ndarray]:
+    """SVD-based rounding of an MPO (Sec. 3): the MPS rounding of the chain
+    whose core k has its row and column indices grouped into one index of
+    size I_k J_k (C order, row index slower), i.e. round_sweep with a K leg of
+    size 1.  Right-to-left LQ, then left-to-right truncated SVDs with tail
+    delta = eps |A|_F / sqrt(d - 1); the last core keeps the remaining factor
+    (Q R of its final QR).  Returns cores (r, I, J, r'), cores 1..d-1
+    left-orthonormal with sign-fixed singular vectors.  Reading taken for the
+    zero matrix (the paper does not treat it): all-zero rank-1 cores.
+    """
+    d = len(cores)
+    dims = [(c.shape[1], c.shape[2]) for c in cores]
+    if not any(np.any(c) for c in cores):
+        return [np.zeros((1, I, J, 1)) for (I, J) in dims]
+    C = [np.asarray(c, dtype=np.float64).reshape(c.shape[0], c.shape[1] * c.shape[2], c.shape[3])
+         for c in cores]
+    out = round_sweep(C, eps, rmax, last="qr")
+    res = out["cores"]
+    res[-1] = np.tensordot(res[-1], out["R"], axes=(2, 0))
+    return [c.reshape(c.shape[0], I, J, c.shape[2]) for c, (I, J) in zip(res, dims)]

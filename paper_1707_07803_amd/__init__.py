@@ -6,8 +6,8 @@ kernels of ``libtnrsvd.so`` behind the C ABI of ``include/tnrsvd.h``.  This
 package holds the build script and a thin ctypes binding.
 """
 
-from .tnrsvd import (TNrSVD, TNrSVDError, TNrSVDFunction, solve, sparse_to_mpo,  # noqa: F401
+from .tnrsvd import (TNrSVD, TNrSVDError, TNrSVDFunction, solve, sparse_to_mpo, sparse_round,  # noqa: F401
                      load_library, omega_flat, LIB_PATH, EXPORTS, PRECISIONS)
 
-__all__ = ["TNrSVD", "TNrSVDError", "TNrSVDFunction", "solve", "sparse_to_mpo", "load_library", "omega_flat", "LIB_PATH",
+__all__ = ["TNrSVD", "TNrSVDError", "TNrSVDFunction", "solve", "sparse_to_mpo", "sparse_round", "load_library", "omega_flat", "LIB_PATH",
            "EXPORTS", "PRECISIONS"]

@@ -1,0 +1,414 @@
+// Rounding (Sec. 3) of the MPO that Algorithm 4.1 builds: the linear-algebra
+// kernels.
+//
+// Once the selection cores 2..d are orthogonalised (an exact relabelling, done
+// in kernels_sparse.hip), the rounding needs the truncated SVD of core 1, a
+// tall panel P with I_1 J_1 rows and one column per nonzero block, and then of
+// a chain of small panels.  P is factorised by TSQR: independent workgroups
+// take the blocked Householder QR of row tiles ("leaves"), the R factors are
+// stacked in pairs and factorised again up a binary tree, and the root R is
+// diagonalised by one-sided Jacobi (Hestenes).  The kept left singular vectors
+// are formed by applying the tree's reflectors top-down to those of R, so they
+// are orthonormal to working accuracy however small the kept singular values
+// are.  Each small panel is handled by one workgroup: Householder QR when it
+// is taller than wide, Jacobi, reflector application, sign convention.
+#include "tnrsvd_internal.h"
+#include "wg_linalg.h"
+
+namespace tnr {
+
+namespace {
+
+constexpr int AR = kSweepArena;
+constexpr int RC = AR - 64 - 2 * QBMAX * QBMAX;   // LDS for the panel and the GEMM tiles
+
+__device__ inline double* lds_Ts(double* a) { return a + AR - 32 - 2 * QBMAX * QBMAX; }
+__device__ inline double* lds_Gs(double* a) { return a + AR - 32 - QBMAX * QBMAX; }
+__device__ inline double* lds_red(double* a) { return a + AR - 16; }
+
+__host__ __device__ inline int pick_qb(int64_t m) { return m * (QBMAX + 1) <= RC ? QBMAX : QB; }
+
+// Householder QR (diag(R) >= 0) of the m x n column-major X (ld ld) in place.
+// ws holds qr_ws_doubles(m, n): the blocked update's workspace, then m doubles
+// for the reflector of an unblocked step when m exceeds the LDS (else LDS).
+__device__ void wg_qr(double* X, int m, int n, int64_t ld, double* tau, double* ws, double* arena) {
+  const int qb = pick_qb(m);
+  double* v = m <= RC ? arena : ws + (int64_t)m * qb + 2 * (int64_t)qb * n;
+  wg_geqrf(X, m, n, tau, v, lds_red(arena), ws, arena, RC, lds_Ts(arena), lds_Gs(arena), ld, qb);
+}
+
+// Y <- H_0 ... H_{k-1} Y for the m x s matrix Y with element (r, c) at
+// Y[r ys + c], reflectors stored as by wg_geqr2 in V (ld ldv).  One wave per
+// column of Y.
+__device__ void wg_apply_q_rows(const double* V, const double* tau, int m, int k, double* Y, int s,
+                                int64_t ldv, int64_t ys) {
+  const int lane = threadIdx.x & 63, w = wave_id();
+  for (int c = w; c < s; c += NW) {
+    double* yc = Y + c;
+    for (int j = k - 1; j >= 0; --j) {
+      const double tj = tau[j];
+      if (tj == 0.0) continue;
+      const double* vj = V + (int64_t)j * ldv;
+      const int r0 = j & ~63;
+      double part = 0.0;
+      for (int r = r0 + lane; r < m; r += 64) {
+        if (r == j) part += yc[(int64_t)r * ys];
+        else if (r > j) part += vj[r] * yc[(int64_t)r * ys];
+      }
+      part = wave_sum(part);
+      const double f = tj * part;
+      for (int r = r0 + lane; r < m; r += 64) {
+        if (r == j) yc[(int64_t)r * ys] -= f;
+        else if (r > j) yc[(int64_t)r * ys] -= f * vj[r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Smallest rank >= 1 whose discarded tail satisfies sum_{l >= rho} sig_l^2 <=
+// delta^2 (sig descending, kk values), then capped at rmax (> 0) and at kk.
+__device__ int tail_rank(const double* sig, int kk, double delta, int rmax) {
+  const double d2 = delta * delta;
+  double tail = 0.0;
+  int rho = kk;
+  for (int cand = kk - 1; cand >= 1; --cand) {
+    tail += sig[cand] * sig[cand];
+    if (tail <= d2)
+      rho = cand;
+    else
+      break;
+  }
+  if (rmax > 0 && rho > rmax) rho = rmax;
+  return rho < 1 ? 1 : rho;
+}
+
+// ------------------------------------------------------------------- TSQR
+
+// Leaf l: QR of the h x N column-major tile l of Pw; R goes to the parent's
+// 2N x N stack (rows (l & 1) N ..), or to the root (ld N) when there is one leaf.
+__global__ __launch_bounds__(NT) void k_tsqr_leaf(double* Pw, int h, int N, double* tau,
+                                                  double* ws, int64_t wss, double* up, int single) {
+  __shared__ double arena[AR];
+  const int l = blockIdx.x;
+  double* X = Pw + (int64_t)l * h * N;
+  wg_qr(X, h, N, h, tau + (int64_t)l * N, ws + (int64_t)l * wss, arena);
+  double* S = single ? up : up + (int64_t)(l >> 1) * 2 * N * N + (l & 1) * N;
+  const int64_t ls = single ? N : 2 * (int64_t)N;
+  for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+    const int64_t c = e / N, r = e % N;
+    S[c * ls + r] = r <= c ? X[c * h + r] : 0.0;
+  }
+}
+
+// Tree node i of one level: QR of its stacked pair (2N x N, ld 2N); R to the
+// parent's stack, or to the root when the level has one node.
+__global__ __launch_bounds__(NT) void k_tsqr_node(double* S, int N, double* tau, double* ws,
+                                                  int64_t wss, double* up, int single) {
+  __shared__ double arena[AR];
+  const int i = blockIdx.x;
+  const int64_t m = 2 * (int64_t)N;
+  double* X = S + (int64_t)i * m * N;
+  wg_qr(X, (int)m, N, m, tau + (int64_t)i * N, ws + (int64_t)i * wss, arena);
+  double* D = single ? up : up + (int64_t)(i >> 1) * m * N + (i & 1) * N;
+  const int64_t ls = single ? N : m;
+  for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+    const int64_t c = e / N, r = e % N;
+    D[c * ls + r] = r <= c ? X[c * m + r] : 0.0;
+  }
+}
+
+// SVD of the root R (N x N, column-major) by one-sided Jacobi on its rows:
+// R = U diag(sig) V^T.  Rank by the tail rule with delta = eps |R|_F /
+// sqrt(d - 1) (|R|_F = |A|_F), capped at rmax and min(n1, N).  Writes rho,
+// delta, Y0 = U(:, kept) (N x rho, ld N) and T = diag(sig) V^T (rho x N,
+// row-major).  Signs are fixed later on the full left vectors.
+__global__ __launch_bounds__(NT) void k_root_svd(const double* Rf, int N, int64_t n1, double eps,
+                                                 int dm1, int rmax, double* B, double* U,
+                                                 double* nrm, double* sig, int* perm, int* flag,
+                                                 double* Y0, double* T, int* rho_out,
+                                                 double* delta_out) {
+  __shared__ double red[16];
+  __shared__ int srho;
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int64_t e = tid; e < (int64_t)N * N; e += NT) {
+    const int64_t p = e / N, c = e % N;
+    const double x = Rf[c * N + p];
+    B[e] = x;                         // vector p = row p of R
+    part += x * x;
+  }
+  const double nrm2 = block_sum(part, red);
+  const double delta = eps * sqrt(nrm2) / sqrt((double)dm1);
+  wg_jacobi(B, N, N, N, U, flag, red, delta * delta / (double)N);
+  wg_norms_sorted(B, N, N, N, sig, perm, nrm);
+  if (tid == 0) {
+    const int kk = (int)(n1 < N ? n1 : N);
+    srho = tail_rank(sig, kk, delta, rmax);
+    rho_out[0] = srho;
+    delta_out[0] = delta;
+  }
+  __syncthreads();
+  const int rho = srho;
+  for (int64_t e = tid; e < (int64_t)N * rho; e += NT) {
+    const int64_t k = e / N, r = e % N;
+    Y0[e] = U[(int64_t)perm[k] * N + r];
+    T[k * N + r] = B[(int64_t)perm[k] * N + r];
+  }
+}
+
+// Top-down application of a tree level: node i takes rows (i & 1) N .. of its
+// parent's Y (2N x rho, ld 2N; Y0 with ld N at the root), pads them with N zero
+// rows and applies its reflectors.
+__global__ __launch_bounds__(NT) void k_tsqr_apply_node(const double* S, const double* tau, int N,
+                                                        int rho, const double* Yup, int root,
+                                                        double* Yl) {
+  const int i = blockIdx.x;
+  const int64_t m = 2 * (int64_t)N;
+  const double* src = root ? Yup : Yup + (int64_t)(i >> 1) * m * rho + (i & 1) * N;
+  const int64_t ls = root ? N : m;
+  double* Y = Yl + (int64_t)i * m * rho;
+  for (int64_t e = threadIdx.x; e < m * rho; e += NT) {
+    const int64_t c = e / m, r = e % m;
+    Y[e] = r < N ? src[c * ls + r] : 0.0;
+  }
+  __syncthreads();
+  wg_apply_q(S + (int64_t)i * m * N, tau + (int64_t)i * N, (int)m, N, Y, rho, m);
+}
+
+// Leaf l: rows l h .. of core 1 (row-major n1 x rho) = the leaf's reflectors
+// applied to [its rows of the parent's Y; 0].  Only the leaf's rows that exist
+// (< n1) are touched: padding rows of P are zero, so no reflector reaches them.
+__global__ __launch_bounds__(NT) void k_tsqr_apply_leaf(const double* Pw, const double* tau, int h,
+                                                        int N, int rho, int64_t n1,
+                                                        const double* Yup, int single,
+                                                        double* core1) {
+  const int l = blockIdx.x;
+  const int64_t row0 = (int64_t)l * h;
+  const int ml = (int)((n1 - row0) < h ? (n1 - row0) : h);
+  const double* src = single ? Yup : Yup + (int64_t)(l >> 1) * 2 * N * rho + (l & 1) * N;
+  const int64_t ls = single ? N : 2 * (int64_t)N;
+  double* Y = core1 + row0 * rho;
+  for (int64_t e = threadIdx.x; e < (int64_t)ml * rho; e += NT) {
+    const int64_t r = e / rho, c = e % rho;
+    Y[e] = r < N ? src[c * ls + r] : 0.0;
+  }
+  __syncthreads();
+  wg_apply_q_rows(Pw + (int64_t)l * h * N, tau + (int64_t)l * N, ml, ml < N ? ml : N, Y, rho, h,
+                  rho);
+}
+
+// Per chunk of 1024 rows and per column of the row-major n1 x rho matrix X:
+// the largest magnitude and the first row holding it.
+constexpr int kColChunk = 1024;
+__global__ __launch_bounds__(NT) void k_colmax(const double* X, int64_t n1, int rho, double* pv,
+                                               int64_t* pi) {
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int64_t r0 = (int64_t)blockIdx.x * kColChunk;
+  const int64_t r1 = (r0 + kColChunk) < n1 ? (r0 + kColChunk) : n1;
+  for (int c = w; c < rho; c += NW) {
+    double best = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int64_t r = r0 + lane; r < r1; r += 64) {
+      const double a = fabs(X[r * rho + c]);
+      if (a > best) {       // rows rise along a lane, so the first maximum is kept
+        best = a;
+        bi = r;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int64_t oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      pv[(int64_t)blockIdx.x * rho + c] = best;
+      pi[(int64_t)blockIdx.x * rho + c] = bi;
+    }
+  }
+}
+
+// Sign of the largest-magnitude entry of every column (first row on ties),
+// from the per-chunk maxima; sgn[c] = +-1.
+__global__ __launch_bounds__(NT) void k_colsign(const double* X, int rho, const double* pv,
+                                                const int64_t* pi, int nchunk, double* sgn) {
+  for (int c = threadIdx.x; c < rho; c += NT) {
+    double best = -1.0;
+    int64_t bi = 0;
+    for (int k = 0; k < nchunk; ++k) {
+      const double v = pv[(int64_t)k * rho + c];
+      if (v > best) {     // chunks in row order: a tie keeps the earlier row
+        best = v;
+        bi = pi[(int64_t)k * rho + c];
+      }
+    }
+    sgn[c] = X[bi * rho + c] < 0.0 ? -1.0 : 1.0;
+  }
+}
+
+// X (row-major n1 x rho) columns and T (rho x N) rows times sgn.
+__global__ void k_apply_sign(double* X, int64_t n1, int rho, double* T, int N, const double* sgn) {
+  const int64_t tot = n1 * rho, tt = (int64_t)rho * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot + tt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < tot)
+      X[e] *= sgn[e % rho];
+    else
+      T[e - tot] *= sgn[(e - tot) / N];
+  }
+}
+
+// ------------------------------------------------------------ small panels
+
+// One core k of the left-to-right truncation (1 < k < d).  T (rp x cp,
+// row-major) is the carried factor; column c of it belongs to class c of the
+// orthogonalised selection core, whose single unit entry sits at mode index
+// pm[c] and right class nx[c] (an injective map, so the panel is a scatter):
+//   M[(a n + pm[c]), nx[c]] = T[a, c],   M is (rp n) x q.
+// Truncated SVD of M (QR first when it is taller than wide), rank by the tail
+// rule, left vectors sign-fixed (largest-magnitude entry positive), core =
+// those vectors (row-major (rp n) x rho), Tn = diag(sig) V^T with the same
+// signs (rho x q).
+__global__ __launch_bounds__(NT) void k_round_level(const double* T, int rp, int cp, const int* pm,
+                                                    const int* nx, int n, int q,
+                                                    const double* delta_p, int rmax, double* M,
+                                                    double* ws, double* tau, double* B, double* U,
+                                                    double* nrm, double* sig, int* perm,
+                                                    double* sgn, int* flag, double* Y,
+                                                    double* core, double* Tn, int* rho_out) {
+  __shared__ double arena[AR];
+  __shared__ int srho;
+  const int tid = threadIdx.x;
+  const int64_t nv = (int64_t)rp * n;
+  const double delta = delta_p[0];
+  for (int64_t e = tid; e < nv * q; e += NT) M[e] = 0.0;
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)rp * cp; e += NT) {
+    const int64_t a = e / cp, c = e % cp;
+    M[(int64_t)nx[c] * nv + a * n + pm[c]] = T[e];
+  }
+  __syncthreads();
+  const bool tall = nv > q;
+  const int nvv = tall ? q : (int)nv;   // Jacobi vectors: rows of R, or rows of M
+  if (tall) {
+    wg_qr(M, (int)nv, q, nv, tau, ws, arena);
+    for (int64_t e = tid; e < (int64_t)q * q; e += NT) {
+      const int64_t p = e / q, c = e % q;
+      B[e] = c >= p ? M[c * nv + p] : 0.0;
+    }
+  } else {
+    for (int64_t e = tid; e < nv * q; e += NT) {
+      const int64_t p = e / q, c = e % q;
+      B[e] = M[c * nv + p];
+    }
+  }
+  __syncthreads();
+  wg_jacobi(B, nvv, q, q, U, flag, lds_red(arena), delta * delta / (double)nvv);
+  wg_norms_sorted(B, nvv, q, q, sig, perm, nrm);
+  if (tid == 0) {
+    const int kk = (int)(nv < q ? nv : q);
+    srho = tail_rank(sig, kk, delta, rmax);
+    rho_out[0] = srho;
+  }
+  __syncthreads();
+  const int rho = srho;
+  // left vectors, column-major nv x rho
+  for (int64_t e = tid; e < nv * rho; e += NT) {
+    const int64_t k = e / nv, r = e % nv;
+    Y[e] = r < nvv ? U[(int64_t)perm[k] * nvv + r] : 0.0;
+  }
+  __syncthreads();
+  if (tall) wg_apply_q(M, tau, (int)nv, q, Y, rho, nv);
+  for (int k = tid; k < rho; k += NT) sgn[k] = sign_of_max(Y + (int64_t)k * nv, (int)nv, 1);
+  __syncthreads();
+  for (int64_t e = tid; e < nv * rho; e += NT) {
+    const int64_t r = e / rho, k = e % rho;
+    core[e] = Y[k * nv + r] * sgn[k];
+  }
+  for (int64_t e = tid; e < (int64_t)rho * q; e += NT) {
+    const int64_t k = e / q, c = e % q;
+    Tn[e] = B[(int64_t)perm[k] * q + c] * sgn[k];
+  }
+}
+
+// The last core: core[a n + pm[c]] = T[a, c] (row-major rp x n), zero elsewhere.
+__global__ __launch_bounds__(NT) void k_round_last(const double* T, int rp, int cp, const int* pm,
+                                                   int n, double* core) {
+  for (int64_t e = threadIdx.x; e < (int64_t)rp * n; e += NT) core[e] = 0.0;
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < (int64_t)rp * cp; e += NT) {
+    const int64_t a = e / cp, c = e % cp;
+    core[a * n + pm[c]] = T[e];
+  }
+}
+
+}  // namespace
+
+int64_t qr_ws_doubles(int64_t m, int64_t n) { return m * pick_qb(m) + 2 * (int64_t)pick_qb(m) * n + m; }
+
+hipError_t launch_tsqr_leaf(double* Pw, int h, int N, int L, double* tau, double* ws, int64_t wss,
+                            double* up, hipStream_t s) {
+  k_tsqr_leaf<<<L, NT, 0, s>>>(Pw, h, N, tau, ws, wss, up, L == 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_tsqr_node(double* S, int N, int cnt, double* tau, double* ws, int64_t wss,
+                            double* up, hipStream_t s) {
+  k_tsqr_node<<<cnt, NT, 0, s>>>(S, N, tau, ws, wss, up, cnt == 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_root_svd(const double* Rf, int N, int64_t n1, double eps, int dm1, int rmax,
+                           double* B, double* U, double* nrm, double* sig, int* perm, int* flag,
+                           double* Y0, double* T, int* rho_out, double* delta_out, hipStream_t s) {
+  k_root_svd<<<1, NT, 0, s>>>(Rf, N, n1, eps, dm1, rmax, B, U, nrm, sig, perm, flag, Y0, T,
+                              rho_out, delta_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tsqr_apply_node(const double* S, const double* tau, int N, int rho, int cnt,
+                                  const double* Yup, int root, double* Yl, hipStream_t s) {
+  k_tsqr_apply_node<<<cnt, NT, 0, s>>>(S, tau, N, rho, Yup, root, Yl);
+  return hipGetLastError();
+}
+
+hipError_t launch_tsqr_apply_leaf(const double* Pw, const double* tau, int h, int N, int rho,
+                                  int64_t n1, int L, const double* Yup, double* core1,
+                                  hipStream_t s) {
+  k_tsqr_apply_leaf<<<L, NT, 0, s>>>(Pw, tau, h, N, rho, n1, Yup, L == 1, core1);
+  return hipGetLastError();
+}
+
+int64_t colsign_chunks(int64_t n1) { return (n1 + kColChunk - 1) / kColChunk; }
+
+hipError_t launch_colsign(double* X, int64_t n1, int rho, double* T, int N, double* pv,
+                          int64_t* pi, double* sgn, hipStream_t s) {
+  const int64_t nch = colsign_chunks(n1);
+  k_colmax<<<(unsigned)nch, NT, 0, s>>>(X, n1, rho, pv, pi);
+  k_colsign<<<1, NT, 0, s>>>(X, rho, pv, pi, (int)nch, sgn);
+  const int64_t tot = n1 * rho + (int64_t)rho * N;
+  const int64_t g = (tot + 255) / 256;
+  k_apply_sign<<<(unsigned)(g > 16384 ? 16384 : g), 256, 0, s>>>(X, n1, rho, T, N, sgn);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_level(const double* T, int rp, int cp, const int* pm, const int* nx, int n,
+                              int q, const double* delta_p, int rmax, double* M, double* ws,
+                              double* tau, double* B, double* U, double* nrm, double* sig,
+                              int* perm, double* sgn, int* flag, double* Y, double* core,
+                              double* Tn, int* rho_out, hipStream_t s) {
+  k_round_level<<<1, NT, 0, s>>>(T, rp, cp, pm, nx, n, q, delta_p, rmax, M, ws, tau, B, U, nrm,
+                                 sig, perm, sgn, flag, Y, core, Tn, rho_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_last(const double* T, int rp, int cp, const int* pm, int n, double* core,
+                             hipStream_t s) {
+  k_round_last<<<1, NT, 0, s>>>(T, rp, cp, pm, n, core);
+  return hipGetLastError();
+}
+
+}  // namespace tnr

@@ -253,6 +253,83 @@ int grid_n(int64_t n) {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ------------------------------------------------- rounding: block structure
+
+// key of every block t (t = rank of its bit)
+__global__ void k_block_list(const unsigned* __restrict__ bm, const int* __restrict__ ws,
+                             int64_t nw, uint64_t* __restrict__ bkey) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nw * 32;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned word = bm[g >> 5];
+    const unsigned b = (unsigned)(g & 31);
+    if ((word >> b) & 1u) bkey[ws[g >> 5] - __popc(word) + __popc(word & ((1u << b) - 1u))] = g;
+  }
+}
+
+// Suffix of block t from level k on: its block row and column divided by the
+// products of the mode sizes of levels 2..k-1 (rdiv, cdiv), as one key over
+// (rows / rdiv) x (nsc = nbc / cdiv) positions.
+__device__ inline uint64_t suffix_key(uint64_t key, int64_t nbc, int64_t rdiv, int64_t cdiv,
+                                      int64_t nsc) {
+  const uint64_t br = key / (uint64_t)nbc, bc = key % (uint64_t)nbc;
+  return (br / (uint64_t)rdiv) * (uint64_t)nsc + bc / (uint64_t)cdiv;
+}
+
+__global__ void k_suffix_mark(const uint64_t* __restrict__ bkey, int64_t N, int64_t nbc,
+                              int64_t rdiv, int64_t cdiv, int64_t nsc, unsigned* __restrict__ bm) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t sk = suffix_key(bkey[t], nbc, rdiv, cdiv, nsc);
+    atomicOr(bm + (sk >> 5), 1u << (sk & 31));
+  }
+}
+
+// class of block t at one level = rank of its suffix's bit
+__global__ void k_suffix_class(const uint64_t* __restrict__ bkey, int64_t N, int64_t nbc,
+                               int64_t rdiv, int64_t cdiv, int64_t nsc,
+                               const unsigned* __restrict__ bm, const int* __restrict__ ws,
+                               int* __restrict__ cls) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
+       t += (int64_t)gridDim.x * blockDim.x)
+    cls[t] = (int)block_of(bm, ws, suffix_key(bkey[t], nbc, rdiv, cdiv, nsc));
+}
+
+// For class c of level k: the mode index of its unit entry in the
+// orthogonalised selection core (digit k of row and column) and its class at
+// level k + 1 (0 on the last level).  Every block of a class writes the same
+// values.
+__global__ void k_class_info(const uint64_t* __restrict__ bkey, int64_t N, int64_t nbc,
+                             int64_t rdiv, int64_t cdiv, int64_t Ik, int64_t Jk,
+                             const int* __restrict__ cls, const int* __restrict__ cls_next,
+                             int* __restrict__ pm, int* __restrict__ nx) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t br = (int64_t)(bkey[t] / (uint64_t)nbc), bc = (int64_t)(bkey[t] % (uint64_t)nbc);
+    const int c = cls ? cls[t] : (int)t;
+    pm[c] = (int)(((br / rdiv) % Ik) * Jk + (bc / cdiv) % Jk);
+    nx[c] = cls_next ? cls_next[t] : 0;
+  }
+}
+
+// Core 1 as row tiles for TSQR: entry (i, j) of block t adds into tile
+// l = m / h, element (m mod h, t) of the h x N column-major tile, where
+// m = (i mod I1) J1 + (j mod J1) is its row of core 1.
+__global__ void k_scatter_tiles(const int64_t* __restrict__ row, const int64_t* __restrict__ col,
+                                const double* __restrict__ val, int64_t nnz, int64_t I1, int64_t J1,
+                                int64_t nbc, const unsigned* __restrict__ bm,
+                                const int* __restrict__ ws, int64_t h, int64_t N,
+                                double* __restrict__ Pw) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = val[e];
+    if (v == 0.0) continue;
+    const int64_t i = row[e], j = col[e];
+    const int64_t t = block_of(bm, ws, (uint64_t)((i / I1) * nbc + j / J1));
+    const int64_t m = (i % I1) * J1 + j % J1;
+    atomicAdd(Pw + (m / h) * h * N + t * h + m % h, v);
+  }
+}
+
 // Scratch kept per device between calls (up to kCacheMax bytes); the mutex is
 // held for a whole call, which ends with a stream synchronisation.
 std::mutex g_scratch_mu;
@@ -438,6 +515,298 @@ hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
     if (e == hipSuccess) e = ef;
   }
   return e;
+}
+
+
+namespace {
+
+// Device allocations of one call, freed together except those released.
+struct DevArena {
+  std::vector<void*> ptrs;
+  hipError_t e = hipSuccess;
+  template <typename P>
+  P* get(int64_t count) {
+    if (e != hipSuccess) return nullptr;
+    void* p = nullptr;
+    e = hipMalloc(&p, sizeof(P) * (size_t)(count > 0 ? count : 1));
+    if (e != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return (P*)p;
+  }
+  void release(const void* p) {
+    for (auto& q : ptrs)
+      if (q == p) q = nullptr;
+  }
+  ~DevArena() {
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+// Prefix sums of the popcounts of the nw bitmap words into ws; *count = total.
+hipError_t scan_words(DevArena& A, const unsigned* bm, int* ws, int64_t nw, int* count,
+                      hipStream_t s) {
+  int* pc = A.get<int>(nw);
+  size_t tb = 0;
+  hipError_t e = A.e;
+  if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(nullptr, tb, pc, ws, (int)nw, s);
+  char* tmp = e == hipSuccess ? A.get<char>((int64_t)tb) : nullptr;
+  if (e == hipSuccess) e = A.e;
+  if (e != hipSuccess) return e;
+  k_popc<<<grid_n(nw), 256, 0, s>>>(bm, nw, pc);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(tmp, tb, pc, ws, (int)nw, s);
+  if (e == hipSuccess) {
+    k_total<<<1, 64, 0, s>>>(ws, nw, count);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace
+
+// SVD-based rounding (Sec. 3: right-to-left orthogonalisation, then
+// left-to-right truncated SVDs with delta = eps |A|_F / sqrt(d - 1), ranks
+// capped at rmax when rmax > 0) of the MPO that Algorithm 4.1 builds from the
+// COO matrix, without forming that MPO.  Its cores 2..d are 0/1 selection
+// tensors, so their right-to-left orthogonalisation is exact relabelling: at
+// level k the blocks fall into classes of equal digits k..d (suffixes), the
+// orthogonalised core k has one unit entry per class (at the class's digit k
+// and its class at level k + 1), and the carried factors are selections, so
+// core 1 stays the matrix P of vectorised blocks.  What remains is the
+// truncated SVD of P (TSQR, multi-workgroup) and of one small panel per core.
+hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, const int64_t* row,
+                        const int64_t* col, const double* val, double eps, int rmax,
+                        RoundedMpo* out, int* why, hipStream_t s) {
+  *why = 0;
+  int64_t M = 1, Nc = 1;
+  for (int k = 0; k < d; ++k) {
+    M *= I[k];
+    Nc *= J[k];
+  }
+  const int64_t nbc = Nc / J[0], nbr = M / I[0];
+  const uint64_t none = (uint64_t)nbr * (uint64_t)nbc;
+  if (none > kBitmapMax) {
+    *why = 2;
+    return hipSuccess;
+  }
+  const int64_t n1 = I[0] * J[0];
+  DevArena A;
+  hipError_t e = hipSuccess;
+  auto read_back = [&](void* host, const void* dev, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  };
+  auto zero = [&](void* p, int64_t bytes) {
+    if (e == hipSuccess) e = hipMemsetAsync(p, 0, (size_t)bytes, s);
+  };
+
+  // 1. block numbering; cnt[0] blocks, cnt[1] bad index, cnt[k] classes at level k >= 2
+  int* cnt = A.get<int>(d + 2);
+  const int64_t nw = (int64_t)((none + 31) / 32);
+  unsigned* bm = A.get<unsigned>(nw);
+  int* wsb = A.get<int>(nw);
+  if ((e = A.e) != hipSuccess) return e;
+  zero(cnt, sizeof(int) * (d + 2));
+  zero(bm, 4 * nw);
+  if (e == hipSuccess && nnz > 0) {
+    k_mark<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, M, Nc, I[0], J[0], nbc, bm, cnt + 1);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = scan_words(A, bm, wsb, nw, cnt, s);
+  }
+  int hc[2] = {0, 0};
+  read_back(hc, cnt, 2 * sizeof(int));
+  if (e != hipSuccess) return e;
+  if (hc[1]) {
+    *why = 1;
+    return hipSuccess;
+  }
+  const int64_t N = hc[0];
+  if (N > 16384) {
+    *why = 3;
+    return hipSuccess;
+  }
+  out->ranks.assign(d + 1, 1);
+  out->cores.assign(d, nullptr);
+  std::vector<double*> cores(d, nullptr);
+  auto finish = [&]() {
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < d; ++k) {
+      A.release(cores[k]);
+      out->cores[k] = cores[k];
+    }
+    return hipSuccess;
+  };
+  if (N == 0 || d == 1) {
+    // the zero matrix: rank-1 zero cores; a single core: the matrix itself
+    for (int k = 0; k < d && e == hipSuccess; ++k) {
+      cores[k] = A.get<double>(I[k] * J[k]);
+      if ((e = A.e) == hipSuccess) zero(cores[k], 8 * I[k] * J[k]);
+    }
+    if (e == hipSuccess && N > 0) {
+      k_scatter_tiles<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, I[0], J[0], nbc, bm, wsb,
+                                                   n1, 1, cores[0]);
+      e = hipGetLastError();
+    }
+    return finish();
+  }
+
+  // 2. block keys; classes of the suffixes at levels 2..d-1 (level 1: the blocks)
+  uint64_t* bkey = A.get<uint64_t>(N);
+  if ((e = A.e) != hipSuccess) return e;
+  k_block_list<<<grid_n(nw * 32), 256, 0, s>>>(bm, wsb, nw, bkey);
+  e = hipGetLastError();
+  std::vector<int*> cls(d, nullptr), pm(d, nullptr), nx(d, nullptr);
+  std::vector<int64_t> rdiv(d, 1), cdiv(d, 1);
+  for (int k = 2; k < d; ++k) {
+    rdiv[k] = rdiv[k - 1] * I[k - 1];
+    cdiv[k] = cdiv[k - 1] * J[k - 1];
+  }
+  for (int k = 2; k < d && e == hipSuccess; ++k) {
+    const int64_t nsc = nbc / cdiv[k], space = (nbr / rdiv[k]) * nsc;
+    const int64_t snw = (space + 31) / 32;
+    unsigned* sbm = A.get<unsigned>(snw);
+    int* sws = A.get<int>(snw);
+    cls[k] = A.get<int>(N);
+    if ((e = A.e) != hipSuccess) break;
+    zero(sbm, 4 * snw);
+    if (e != hipSuccess) break;
+    k_suffix_mark<<<grid_n(N), 256, 0, s>>>(bkey, N, nbc, rdiv[k], cdiv[k], nsc, sbm);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = scan_words(A, sbm, sws, snw, cnt + k, s);
+    if (e == hipSuccess) {
+      k_suffix_class<<<grid_n(N), 256, 0, s>>>(bkey, N, nbc, rdiv[k], cdiv[k], nsc, sbm, sws,
+                                               cls[k]);
+      e = hipGetLastError();
+    }
+  }
+  for (int k = 1; k < d && e == hipSuccess; ++k) {
+    pm[k] = A.get<int>(N);
+    nx[k] = A.get<int>(N);
+    if ((e = A.e) != hipSuccess) break;
+    k_class_info<<<grid_n(N), 256, 0, s>>>(bkey, N, nbc, rdiv[k], cdiv[k], I[k], J[k],
+                                           k == 1 ? nullptr : cls[k],
+                                           k + 1 < d ? cls[k + 1] : nullptr, pm[k], nx[k]);
+    e = hipGetLastError();
+  }
+  std::vector<int> hcnt(d + 2, 0);
+  read_back(hcnt.data(), cnt, sizeof(int) * (d + 2));
+  if (e != hipSuccess) return e;
+  std::vector<int64_t> r(d, 1);   // r[k]: classes at level k (columns of the factor entering core k)
+  r[1] = N;
+  for (int k = 2; k < d; ++k) r[k] = hcnt[k];
+
+  // 3. core 1: TSQR of P in row tiles of h rows (h >= N)
+  const int64_t h = N <= 960 ? 960 : (N + 63) / 64 * 64;
+  const int64_t L = (n1 + h - 1) / h;
+  double* Pw = A.get<double>(L * h * N);
+  double* tauL = A.get<double>(L * N);
+  const int64_t wssL = qr_ws_doubles(h, N);
+  double* wsL = A.get<double>(L * wssL);
+  std::vector<int64_t> lv;   // node counts of the tree levels above the leaves
+  for (int64_t c = L; c > 1;) {
+    c = (c + 1) / 2;
+    lv.push_back(c);
+  }
+  const int64_t wssN = qr_ws_doubles(2 * N, N);
+  std::vector<double*> S(lv.size()), tauS(lv.size()), wsS(lv.size());
+  for (size_t j = 0; j < lv.size(); ++j) {
+    S[j] = A.get<double>(lv[j] * 2 * N * N);
+    tauS[j] = A.get<double>(lv[j] * N);
+    wsS[j] = A.get<double>(lv[j] * wssN);
+    if (A.e == hipSuccess) zero(S[j], 8 * lv[j] * 2 * N * N);
+  }
+  double* Rf = A.get<double>(N * N);
+  if (e == hipSuccess) e = A.e;
+  zero(Pw, 8 * L * h * N);
+  if (e != hipSuccess) return e;
+  k_scatter_tiles<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, I[0], J[0], nbc, bm, wsb, h, N,
+                                               Pw);
+  e = hipGetLastError();
+  if (e == hipSuccess)
+    e = launch_tsqr_leaf(Pw, (int)h, (int)N, (int)L, tauL, wsL, wssL, L == 1 ? Rf : S[0], s);
+  for (size_t j = 0; j < lv.size() && e == hipSuccess; ++j)
+    e = launch_tsqr_node(S[j], (int)N, (int)lv[j], tauS[j], wsS[j], wssN,
+                         j + 1 < lv.size() ? S[j + 1] : Rf, s);
+
+  // 4. SVD of the root R, rank of core 1
+  double* B = A.get<double>(N * N);
+  double* U = A.get<double>(N * N);
+  double* nrm = A.get<double>(N);
+  double* sig = A.get<double>(N);
+  int* perm = A.get<int>(N);
+  int* flag = A.get<int>(4);
+  double* Y0 = A.get<double>(N * N);
+  double* T = A.get<double>(N * N);
+  int* rho_d = A.get<int>(d + 1);
+  double* delta_d = A.get<double>(1);
+  if (e == hipSuccess) e = A.e;
+  if (e == hipSuccess)
+    e = launch_root_svd(Rf, (int)N, n1, eps, d - 1, rmax, B, U, nrm, sig, perm, flag, Y0, T,
+                        rho_d + 1, delta_d, s);
+  int rho1 = 0;
+  read_back(&rho1, rho_d + 1, sizeof(int));
+  if (e != hipSuccess) return e;
+  out->ranks[1] = rho1;
+
+  // 5. left vectors of P: the tree's reflectors top-down, then the leaves'
+  cores[0] = A.get<double>(n1 * rho1);
+  std::vector<double*> Yl(lv.size());
+  for (size_t j = 0; j < lv.size(); ++j) Yl[j] = A.get<double>(lv[j] * 2 * N * rho1);
+  const int64_t nch = colsign_chunks(n1);
+  double* pv = A.get<double>(nch * rho1);
+  int64_t* pi = A.get<int64_t>(nch * rho1);
+  double* sgn = A.get<double>(rho1);
+  if ((e = A.e) != hipSuccess) return e;
+  for (int j = (int)lv.size() - 1; j >= 0 && e == hipSuccess; --j) {
+    const bool top = j == (int)lv.size() - 1;
+    e = launch_tsqr_apply_node(S[j], tauS[j], (int)N, rho1, (int)lv[j], top ? Y0 : Yl[j + 1],
+                               top, Yl[j], s);
+  }
+  if (e == hipSuccess)
+    e = launch_tsqr_apply_leaf(Pw, tauL, (int)h, (int)N, rho1, n1, (int)L,
+                               L == 1 ? Y0 : Yl[0], cores[0], s);
+  if (e == hipSuccess) e = launch_colsign(cores[0], n1, rho1, T, (int)N, pv, pi, sgn, s);
+
+  // 6. cores 2..d-1: one truncated SVD per core
+  int64_t rp = rho1, cp = N;
+  for (int k = 1; k < d - 1 && e == hipSuccess; ++k) {
+    const int64_t n = I[k] * J[k], q = r[k + 1], nv = rp * n;
+    const int64_t mn = nv < q ? nv : q;
+    const int64_t cap = (rmax > 0 && rmax < mn) ? rmax : mn;
+    double* Mw = A.get<double>(nv * q);
+    double* wsk = A.get<double>(qr_ws_doubles(nv, q));
+    double* tauk = A.get<double>(q);
+    double* Bk = A.get<double>(nv * q);
+    double* Uk = A.get<double>(mn * mn);
+    double* nrmk = A.get<double>(mn);
+    double* sigk = A.get<double>(mn);
+    int* permk = A.get<int>(mn);
+    double* sgnk = A.get<double>(cap);
+    double* Yk = A.get<double>(nv * cap);
+    cores[k] = A.get<double>(nv * cap);
+    double* Tn = A.get<double>(cap * q);
+    if ((e = A.e) != hipSuccess) break;
+    e = launch_round_level(T, (int)rp, (int)cp, pm[k], nx[k], (int)n, (int)q, delta_d, rmax, Mw,
+                           wsk, tauk, Bk, Uk, nrmk, sigk, permk, sgnk, flag, Yk, cores[k], Tn,
+                           rho_d + k + 1, s);
+    int rk = 0;
+    read_back(&rk, rho_d + k + 1, sizeof(int));
+    if (e != hipSuccess) break;
+    out->ranks[k + 1] = rk;
+    T = Tn;
+    rp = rk;
+    cp = q;
+  }
+  // 7. the last core: the carried factor placed at each class's unit entry
+  if (e == hipSuccess) {
+    const int64_t n = I[d - 1] * J[d - 1];
+    cores[d - 1] = A.get<double>(rp * n);
+    if ((e = A.e) == hipSuccess)
+      e = launch_round_last(T, (int)rp, (int)cp, pm[d - 1], (int)n, cores[d - 1], s);
+  }
+  return finish();
 }
 
 }  // namespace tnr

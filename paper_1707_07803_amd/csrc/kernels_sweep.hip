@@ -16,469 +16,11 @@
 #include <type_traits>
 
 #include "tnrsvd_internal.h"
+#include "wg_linalg.h"
 
 namespace tnr {
 
 namespace {
-
-constexpr int NT = kSweepThreads;
-constexpr int NW = NT / 64;
-
-// DPP move of a double (both 32-bit halves), zero where the source lane is invalid.
-template <int CTRL, int ROWMASK = 0xf>
-__device__ __forceinline__ double dpp_d(double x) {
-  const int lo = __double2loint(x), hi = __double2hiint(x);
-  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xf, true);
-  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xf, true);
-  return __hiloint2double(h2, l2);
-}
-
-// Sum over the 64 lanes of a wave, returned to every lane: shift-adds within
-// each row of 16 lanes, row broadcasts 15 and 31 to fold the four rows into
-// lane 63, then a read of lane 63.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_d<0x111>(v);          // row_shr:1
-  v += dpp_d<0x112>(v);          // row_shr:2
-  v += dpp_d<0x114>(v);          // row_shr:4
-  v += dpp_d<0x118>(v);          // row_shr:8
-  v += dpp_d<0x142, 0xa>(v);     // row_bcast:15 into rows 1 and 3
-  v += dpp_d<0x143, 0xc>(v);     // row_bcast:31 into rows 2 and 3
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-// Workgroup barrier that orders LDS only: global stores still in flight are
-// not waited for (a plain __syncthreads drains them, which costs an L2 round
-// trip).  Only for loops whose global writes nobody reads before the next full
-// barrier.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-// Sum over the workgroup; every thread receives the total.  `red` holds NW doubles.
-__device__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, w = wave_id();
-  __syncthreads();
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int k = 0; k < NW; ++k) t += red[k];
-  return t;
-}
-
-// Householder QR with nonnegative diagonal of the m x n column-major X (ld m
-// unless given),
-// in place: R on and above the diagonal of the first min(m,n) rows, the
-// Householder vectors (unit leading entry implicit) below it, scalars in tau.
-// Each reflector maps its column x to +||x|| e_1, using Parlett's form of the
-// leading entry when x_1 > 0 so that no cancellation occurs.
-__device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double* red,
-                         int64_t ld = -1) {
-  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
-  const int kmax = m < n ? m : n;
-  if (ld < 0) ld = m;
-  for (int j = 0; j < kmax; ++j) {
-    double* col = X + (int64_t)j * ld;
-    const double alpha = col[j];
-    double s2 = 0.0;
-    for (int r = j + 1 + tid; r < m; r += NT) {
-      const double t = col[r];
-      s2 += t * t;
-    }
-    s2 = block_sum(s2, red);
-    double tj, beta, inv_v0;
-    if (s2 == 0.0) {
-      inv_v0 = 0.0;
-      if (alpha >= 0.0) {
-        tj = 0.0;
-        beta = alpha;
-      } else {
-        tj = 2.0;
-        beta = -alpha;
-      }
-    } else {
-      const double nrm = sqrt(alpha * alpha + s2);
-      const double v0 = (alpha <= 0.0) ? alpha - nrm : -s2 / (alpha + nrm);
-      tj = 2.0 * v0 * v0 / (s2 + v0 * v0);
-      beta = nrm;
-      inv_v0 = 1.0 / v0;
-    }
-    for (int r = j + 1 + tid; r < m; r += NT) {
-      const double vr = col[r] * inv_v0;
-      v[r] = vr;
-      col[r] = vr;
-    }
-    if (tid == 0) {
-      v[j] = 1.0;
-      col[j] = beta;
-      tau[j] = tj;
-    }
-    __syncthreads();
-    if (tj != 0.0) {
-      const int r0 = j & ~63;
-      for (int c = j + 1 + w; c < n; c += NW) {
-        double* xc = X + (int64_t)c * ld;
-        double part = 0.0;
-        for (int r = r0 + lane; r < m; r += 64)
-          if (r >= j) part += v[r] * xc[r];
-        part = wave_sum(part);
-        const double f = tj * part;
-        for (int r = r0 + lane; r < m; r += 64)
-          if (r >= j) xc[r] -= f * v[r];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// C (M x N) = beta C + alpha A (M x K) B (K x N) with FP64 accumulation, by
-// the whole workgroup.  Element (i, k) of A is A[i sai + k sak], (k, j) of B
-// is B[k sbk + j sbj] (type TB, widened to FP64) and (i, j) of C is
-// C[i sci + j scj]; C may be in global memory or LDS.  TM x TN output tiles
-// (64 x 64, or 128 x 32 for products only a few columns wide); K goes through
-// LDS GK at a time, the next chunk's loads (clamped in-bounds addresses,
-// mapped so the unit-stride index runs across lanes) in flight while the
-// current one is multiplied; each thread owns a 4 x 2 block of a tile, and
-// when beta != 0 its C values are loaded before the K loop.  beta == 0 never
-// reads C.  `lds` holds GEMM_LDS doubles.  Ends with a barrier.
-constexpr int GK = 32;
-constexpr int GEMM_LDS = GK * (128 + 1) + GK * (64 + 1);
-template <int TM, int TN, typename TB>
-__device__ void wg_gemm_t(int M, int N, int K, double alpha, const double* A, int64_t sai,
-                          int64_t sak, const TB* B, int64_t sbk, int64_t sbj, double beta,
-                          double* C, int64_t sci, int64_t scj, double* lds) {
-  constexpr int TX = TN / 2, TY = NT / TX;           // threads across columns / rows
-  static_assert(TY * 4 == TM, "4 rows per thread");
-  constexpr int ALD = TM + 1, BLD = TN + 1;
-  constexpr int NA = TM * GK / NT, NB = TN * GK / NT;  // loads per thread and chunk
-  const int tid = threadIdx.x;
-  double* As = lds;             // As[k * ALD + i]
-  double* Bs = lds + GK * ALD;  // Bs[k * BLD + j]
-  const int ty = tid / TX, tx = tid % TX;
-  const bool a_ifast = sai == 1, b_jfast = sbj == 1;
-  int ai[NA], ak[NA], bk[NB], bj[NB];
-#pragma unroll
-  for (int t = 0; t < NA; ++t) {
-    const int e = tid + t * NT;
-    ai[t] = a_ifast ? (e % TM) : (e / GK);
-    ak[t] = a_ifast ? (e / TM) : (e % GK);
-  }
-#pragma unroll
-  for (int t = 0; t < NB; ++t) {
-    const int e = tid + t * NT;
-    bj[t] = b_jfast ? (e % TN) : (e / GK);
-    bk[t] = b_jfast ? (e / TN) : (e % GK);
-  }
-  for (int i0 = 0; i0 < M; i0 += TM) {
-    for (int j0 = 0; j0 < N; j0 += TN) {
-      double acc[4][2], cold[4][2];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          acc[r][c] = 0.0;
-          const int i = i0 + ty * 4 + r, j = j0 + tx + TX * c;
-          const bool ok = beta != 0.0 && i < M && j < N;
-          const double v = C[ok ? (int64_t)i * sci + (int64_t)j * scj : 0];
-          cold[r][c] = ok ? v : 0.0;
-        }
-      double av[NA], bv[NB];
-      auto fetch = [&](int k0) {
-#pragma unroll
-        for (int t = 0; t < NA; ++t) {
-          const bool oka = i0 + ai[t] < M && k0 + ak[t] < K;
-          const double va = A[oka ? (int64_t)(i0 + ai[t]) * sai + (int64_t)(k0 + ak[t]) * sak : 0];
-          av[t] = oka ? va : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < NB; ++t) {
-          const bool okb = j0 + bj[t] < N && k0 + bk[t] < K;
-          const double vb =
-              (double)B[okb ? (int64_t)(k0 + bk[t]) * sbk + (int64_t)(j0 + bj[t]) * sbj : 0];
-          bv[t] = okb ? vb : 0.0;
-        }
-      };
-      fetch(0);
-      for (int k0 = 0; k0 < K; k0 += GK) {
-#pragma unroll
-        for (int t = 0; t < NA; ++t) As[ak[t] * ALD + ai[t]] = av[t];
-#pragma unroll
-        for (int t = 0; t < NB; ++t) Bs[bk[t] * BLD + bj[t]] = bv[t];
-        __syncthreads();
-        if (k0 + GK < K) fetch(k0 + GK);
-#pragma unroll 8
-        for (int k = 0; k < GK; ++k) {
-          const double b0 = Bs[k * BLD + tx], b1 = Bs[k * BLD + tx + TX];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const double a = As[k * ALD + ty * 4 + r];
-            acc[r][0] += a * b0;
-            acc[r][1] += a * b1;
-          }
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int i = i0 + ty * 4 + r, j = j0 + tx + TX * c;
-          if (i < M && j < N)
-            C[(int64_t)i * sci + (int64_t)j * scj] = beta * cold[r][c] + alpha * acc[r][c];
-        }
-    }
-  }
-  __syncthreads();
-}
-
-template <typename TB>
-__device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int64_t sai,
-                        int64_t sak, const TB* B, int64_t sbk, int64_t sbj, double beta, double* C,
-                        int64_t sci, int64_t scj, double* lds) {
-  wg_gemm_t<64, 64, TB>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, sci, scj, lds);
-}
-
-// Blocked Householder QR (same output as wg_geqr2: R on and above the
-// diagonal, reflectors below it, tau) of the m x n column-major X (ld ld,
-// default m), for
-// panels too large for registers.  Each block of QB columns is factorised by
-// wg_geqr2; its reflectors are applied to the trailing columns at once in the
-// compact WY form H_0 ... H_{b-1} = I - V T V^T (T upper triangular):
-//   C <- C - V (C^T V T)^T,  three GEMMs (the two skinny ones in 128 x 32 tiles).
-// A panel that fits in lds (lds_cap doubles, at least GEMM_LDS) is factorised
-// there; otherwise in place in global memory with v as the LDS vector.
-// qb: block width (<= QBMAX).  ws: m qb + 2 qb n doubles of global workspace;
-// Ts, Gs: QBMAX x QBMAX doubles each in LDS outside lds.
-constexpr int QB = 16;      // block width of the left-to-right pass
-constexpr int QBMAX = 32;   // widest block; Ts and Gs are QBMAX x QBMAX
-__device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double* red, double* ws,
-                         double* lds, int64_t lds_cap, double* Ts, double* Gs, int64_t ld = -1,
-                         int qb = QB) {
-  const int tid = threadIdx.x;
-  if (ld < 0) ld = m;
-  const int kmax = m < n ? m : n;
-  for (int j0 = 0; j0 < kmax; j0 += qb) {
-    const int jb = (kmax - j0) < qb ? (kmax - j0) : qb;
-    const int mp = m - j0;
-    double* P0 = X + (int64_t)j0 * ld + j0;  // panel (mp x jb), ld ld
-    const int nc = n - j0 - jb;
-    double* Vp = ws;                          // explicit V (mp x jb, column-major)
-    if ((int64_t)mp * (jb + 1) <= lds_cap) {
-      // factorise the panel in LDS (v in lds[0, mp), panel after it, ld mp)
-      double* PL = lds + mp;
-      for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
-        const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
-        PL[e] = P0[(int64_t)c * ld + r];
-      }
-      __syncthreads();
-      wg_geqr2(PL, mp, jb, tau + j0, lds, red, mp);
-      for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
-        const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
-        P0[(int64_t)c * ld + r] = PL[e];
-        if (nc > 0) Vp[e] = r > c ? PL[e] : (r == c ? 1.0 : 0.0);
-      }
-      __syncthreads();
-      if (nc <= 0) continue;
-    } else {
-      wg_geqr2(P0, mp, jb, tau + j0, v, red, ld);
-      if (nc <= 0) continue;
-      for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
-        const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
-        Vp[e] = r > c ? P0[(int64_t)c * ld + r] : (r == c ? 1.0 : 0.0);
-      }
-      __syncthreads();
-    }
-    // G = V^T V (jb x jb, row-major in LDS), then T by the forward recurrence
-    //   T_ii = tau_i,  T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-    wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QBMAX, 1, lds);
-    if (tid < 64) {
-      for (int i = 0; i < jb; ++i) {
-        const double ti = tau[j0 + i];
-        if (tid < i) {
-          double acc = 0.0;
-          for (int c = tid; c < i; ++c) acc += Ts[tid * QBMAX + c] * Gs[c * QBMAX + i];
-          Ts[tid * QBMAX + i] = -ti * acc;
-        } else if (tid < QBMAX) {
-          Ts[tid * QBMAX + i] = tid == i ? ti : 0.0;
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    __syncthreads();
-    double* C = X + (int64_t)(j0 + jb) * ld + j0;  // trailing block (mp x nc), ld ld
-    double* Wt = ws + (int64_t)mp * qb;             // W^T = C^T V, nc x jb (ld qb)
-    double* Wt2 = Wt + (int64_t)qb * n;             // W^T T, nc x jb (ld qb)
-    wg_gemm_t<128, 32, double>(nc, jb, mp, 1.0, C, ld, 1, Vp, 1, mp, 0.0, Wt, qb, 1, lds);
-    wg_gemm_t<128, 32, double>(nc, jb, jb, 1.0, Wt, qb, 1, Ts, QBMAX, 1, 0.0, Wt2, qb, 1, lds);
-    // C -= V (W^T T)^T
-    wg_gemm<double>(mp, nc, jb, -1.0, Vp, 1, mp, Wt2, 1, qb, 1.0, C, 1, ld, lds);
-  }
-  __syncthreads();
-}
-
-// Y <- H_0 H_1 ... H_{k-1} Y for the m x s column-major Y (ld m), with the
-// reflectors stored as by wg_geqr2 in V (ld ldv, default m).  One wave per column of Y;
-// columns are independent, so no barrier is needed between reflectors.
-__device__ void wg_apply_q(const double* V, const double* tau, int m, int k, double* Y, int s,
-                           int64_t ldv = -1) {
-  const int lane = threadIdx.x & 63, w = wave_id();
-  if (ldv < 0) ldv = m;
-  for (int c = w; c < s; c += NW) {
-    double* yc = Y + (int64_t)c * m;
-    for (int j = k - 1; j >= 0; --j) {
-      const double tj = tau[j];
-      if (tj == 0.0) continue;
-      const double* vj = V + (int64_t)j * ldv;
-      const int r0 = j & ~63;
-      double part = 0.0;
-      for (int r = r0 + lane; r < m; r += 64) {
-        if (r == j) part += yc[r];
-        else if (r > j) part += vj[r] * yc[r];
-      }
-      part = wave_sum(part);
-      const double f = tj * part;
-      for (int r = r0 + lane; r < m; r += 64) {
-        if (r == j) yc[r] -= f;
-        else if (r > j) yc[r] -= f * vj[r];
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// One-sided Jacobi (Hestenes 1958): rotate the nv vectors b_k = B + k*ldb (length
-// len) pairwise until they are mutually orthogonal to working accuracy, and
-// accumulate the rotations in U (nv x nv, column-major).  Pairs follow the
-// round-robin (circle) ordering so a round's pairs are disjoint and each is
-// handled by one wave.  Returns the number of sweeps.
-__device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* flag, double* red,
-                          double skip2 = 0.0) {
-  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
-  for (int t = tid; t < nv * nv; t += NT) U[t] = ((t % nv) == (t / nv)) ? 1.0 : 0.0;
-  __syncthreads();
-  if (nv < 2) return 0;
-  // Vectors whose norm is below 16 eps |B|_F (rotations keep |B|_F) are
-  // rounding noise, e.g. the null space when nv > len; rotating them cannot
-  // change any singular value above that level, and their relative
-  // orthogonality would never converge, so pairs with one are left alone.
-  double part = 0.0;
-  for (int e = tid; e < nv * len; e += NT) {
-    const double x = B[(int64_t)(e / len) * ldb + e % len];
-    part += x * x;
-  }
-  const double tiny = 256.0 * 4.930380657631324e-32 * block_sum(part, red);
-  // A pair whose squared norms sum to at most skip2 (the caller passes
-  // delta^2 / nv when the rank will be cut at tail delta^2) needs no rotation:
-  // every vector that small ends in the discarded tail (nv of them sum to at
-  // most delta^2), and the tail's Frobenius norm does not depend on rotations
-  // among its vectors.
-  // Convergence threshold len * eps on |<b_p,b_q>| / (|b_p| |b_q|): above the
-  // rounding level of the computed inner products, so a converged pair is
-  // never rotated again and the sweep count stays small.
-  const double tol = 2.220446049250313e-16 * (double)(len > 16 ? len : 16);
-  const int nn = nv + (nv & 1);
-  int sweep = 0;
-  for (; sweep < 40; ++sweep) {
-    if (tid == 0) *flag = 0;
-    __syncthreads();
-    for (int rnd = 0; rnd < nn - 1; ++rnd) {
-      for (int t = w; t < nn / 2; t += NW) {
-        int p, q;
-        if (t == 0) {
-          p = nn - 1;
-          q = rnd;
-        } else {
-          p = (rnd + t) % (nn - 1);
-          q = (rnd - t + nn - 1) % (nn - 1);
-        }
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        if (q >= nv) continue;
-        double* bp = B + (int64_t)p * ldb;
-        double* bq = B + (int64_t)q * ldb;
-        double a = 0.0, b = 0.0, c = 0.0;
-        for (int r = lane; r < len; r += 64) {
-          const double x = bp[r], y = bq[r];
-          a += x * x;
-          b += y * y;
-          c += x * y;
-        }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        c = wave_sum(c);
-        if (a <= tiny || b <= tiny || a + b <= skip2 || fabs(c) <= tol * sqrt(a) * sqrt(b))
-          continue;
-        const double zeta = (b - a) / (2.0 * c);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-        for (int r = lane; r < len; r += 64) {
-          const double x = bp[r], y = bq[r];
-          bp[r] = cs * x - sn * y;
-          bq[r] = sn * x + cs * y;
-        }
-        double* up = U + (int64_t)p * nv;
-        double* uq = U + (int64_t)q * nv;
-        for (int r = lane; r < nv; r += 64) {
-          const double x = up[r], y = uq[r];
-          up[r] = cs * x - sn * y;
-          uq[r] = sn * x + cs * y;
-        }
-        if (lane == 0) *flag = 1;
-      }
-      __syncthreads();
-    }
-    const int any = *flag;
-    __syncthreads();
-    if (!any) break;
-  }
-  return sweep;
-}
-
-// Norms of the nv vectors, then a stable descending sort: sig[pos], perm[pos].
-__device__ void wg_norms_sorted(const double* B, int nv, int len, int ldb, double* sig, int* perm,
-                                double* nrm) {
-  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
-  for (int k = w; k < nv; k += NW) {
-    const double* bk = B + (int64_t)k * ldb;
-    double part = 0.0;
-    for (int r = lane; r < len; r += 64) part += bk[r] * bk[r];
-    part = wave_sum(part);
-    if (lane == 0) nrm[k] = sqrt(part);
-  }
-  __syncthreads();
-  for (int k = tid; k < nv; k += NT) {
-    const double sk = nrm[k];
-    int pos = 0;
-    for (int j = 0; j < nv; ++j) {
-      const double sj = nrm[j];
-      if (sj > sk || (sj == sk && j < k)) ++pos;
-    }
-    perm[pos] = k;
-    sig[pos] = sk;
-  }
-  __syncthreads();
-}
-
-// Sign of the entry of largest magnitude (first one on ties) of x[0..n).
-__device__ inline double sign_of_max(const double* x, int n, int stride) {
-  double best = -1.0, val = 1.0;
-  for (int r = 0; r < n; ++r) {
-    const double a = fabs(x[(int64_t)r * stride]);
-    if (a > best) {
-      best = a;
-      val = x[(int64_t)r * stride];
-    }
-  }
-  return val < 0.0 ? -1.0 : 1.0;
-}
 
 // ---------------------------------------------------------------------------
 // Register-resident Householder QR (panels up to 256 x 128).

@@ -1241,12 +1241,16 @@ tnrsvd_status tnrsvd_get_product_ranks(tnrsvd_t h, int b, int64_t* P_out, int64_
   return TNRSVD_OK;
 }
 
-tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* cols, int64_t nnz,
-                                   const int64_t* coo_row, const int64_t* coo_col,
-                                   const double* coo_val, int64_t* nblocks, double* const* cores,
-                                   void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks shared by the sparse entry points; M and Nc receive the matrix size.
+tnrsvd_status check_coo(int d, const int64_t* rows, const int64_t* cols, int64_t nnz,
+                        const int64_t* coo_row, const int64_t* coo_col, const double* coo_val,
+                        int64_t* M_out, int64_t* Nc_out) {
   if (d < 1) return fail(TNRSVD_E_SHAPE, "d must be >= 1");
-  if (!rows || !cols || !nblocks) return fail(TNRSVD_E_INVALID, "null rows/cols/nblocks");
+  if (!rows || !cols) return fail(TNRSVD_E_INVALID, "null rows/cols");
   if (nnz < 0 || nnz > INT32_MAX) return fail(TNRSVD_E_SHAPE, "nnz must be in [0, 2^31)");
   if (nnz > 0 && (!coo_row || !coo_col || !coo_val))
     return fail(TNRSVD_E_INVALID, "null COO array");
@@ -1261,6 +1265,30 @@ tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* co
   }
   if ((M / rows[0]) > kIdxCap / (Nc / cols[0]))
     return fail(TNRSVD_E_SHAPE, "number of block positions exceeds 2^62");
+  *M_out = M;
+  *Nc_out = Nc;
+  return TNRSVD_OK;
+}
+
+}  // namespace
+
+// The rounded MPO of tnrsvd_sparse_round.
+struct tnrsvd_rounded_s {
+  int d = 0;
+  std::vector<int64_t> rows, cols, ranks;
+  std::vector<double*> cores;
+  hipStream_t stream = nullptr;
+};
+
+extern "C" {
+
+tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* cols, int64_t nnz,
+                                   const int64_t* coo_row, const int64_t* coo_col,
+                                   const double* coo_val, int64_t* nblocks, double* const* cores,
+                                   void* stream) {
+  int64_t M = 0, Nc = 0;
+  TRY(check_coo(d, rows, cols, nnz, coo_row, coo_col, coo_val, &M, &Nc));
+  if (!nblocks) return fail(TNRSVD_E_INVALID, "null nblocks");
   const int64_t expect = cores ? *nblocks : -1;
   if (cores) {
     if (expect < 1) return fail(TNRSVD_E_INVALID, "*nblocks must hold the rank of the cores");
@@ -1285,6 +1313,69 @@ tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* co
   if (cores && nb != expect)
     return fail(TNRSVD_E_SHAPE, "the matrix has %lld nonzero blocks, cores sized for %lld",
                 (long long)nb, (long long)expect);
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_sparse_round(int d, const int64_t* rows, const int64_t* cols, int64_t nnz,
+                                  const int64_t* coo_row, const int64_t* coo_col,
+                                  const double* coo_val, double round_tol, int max_rank,
+                                  void* stream, tnrsvd_rounded_t* out) {
+  if (!out) return fail(TNRSVD_E_INVALID, "null out");
+  *out = nullptr;
+  int64_t M = 0, Nc = 0;
+  TRY(check_coo(d, rows, cols, nnz, coo_row, coo_col, coo_val, &M, &Nc));
+  if (!(round_tol >= 0.0) || std::isinf(round_tol))
+    return fail(TNRSVD_E_INVALID, "round_tol must be finite and >= 0");
+  if (max_rank < 0) return fail(TNRSVD_E_INVALID, "max_rank must be >= 0");
+  if (sat_mul(rows[0], cols[0]) >= kSat)
+    return fail(TNRSVD_E_SHAPE, "first core larger than 2^40 entries");
+  RoundedMpo res;
+  int why = 0;
+  TRY(dev_check(sparse_round(d, rows, cols, nnz, coo_row, coo_col, coo_val, round_tol, max_rank,
+                             &res, &why, (hipStream_t)stream),
+                "sparse rounding"));
+  if (why == 1)
+    return fail(TNRSVD_E_SHAPE, "COO index outside the %lld x %lld matrix", (long long)M,
+                (long long)Nc);
+  if (why == 2)
+    return fail(TNRSVD_E_SHAPE, "more than 2^28 block positions (I / I_1) x (J / J_1)");
+  if (why == 3) return fail(TNRSVD_E_SHAPE, "more than 16384 nonzero blocks");
+  auto* r = new (std::nothrow) tnrsvd_rounded_s;
+  if (!r) {
+    for (double* p : res.cores) (void)hipFree(p);
+    return fail(TNRSVD_E_NOMEM, "host allocation");
+  }
+  r->d = d;
+  r->rows.assign(rows, rows + d);
+  r->cols.assign(cols, cols + d);
+  r->ranks = res.ranks;
+  r->cores = res.cores;
+  r->stream = (hipStream_t)stream;
+  *out = r;
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_rounded_ranks(tnrsvd_rounded_t r, int64_t* ranks) {
+  if (!r || !ranks) return fail(TNRSVD_E_INVALID, "null argument");
+  for (int k = 0; k <= r->d; ++k) ranks[k] = r->ranks[k];
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_rounded_copy(tnrsvd_rounded_t r, int k, double* dst) {
+  if (!r || !dst) return fail(TNRSVD_E_INVALID, "null argument");
+  if (k < 0 || k >= r->d) return fail(TNRSVD_E_INVALID, "core index out of range");
+  const int64_t n = r->ranks[k] * r->rows[k] * r->cols[k] * r->ranks[k + 1];
+  TRY(dev_check(hipMemcpyAsync(dst, r->cores[k], sizeof(double) * (size_t)n,
+                               hipMemcpyDeviceToDevice, r->stream),
+                "copy core"));
+  return dev_check(hipStreamSynchronize(r->stream), "synchronise");
+}
+
+tnrsvd_status tnrsvd_rounded_destroy(tnrsvd_rounded_t r) {
+  if (!r) return TNRSVD_OK;
+  for (double* p : r->cores)
+    if (p) (void)hipFree(p);
+  delete r;
   return TNRSVD_OK;
 }
 

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <vector>
 
 namespace tnr {
 
@@ -150,6 +151,42 @@ hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
                          const int64_t* row, const int64_t* col, const double* val,
                          int64_t expect, int64_t* nblocks, double* const* cores, int* bad_index,
                          hipStream_t s);
+// Rounding of Algorithm 4.1's MPO (kernels_round.hip; orchestrated in kernels_sparse.hip).
+int64_t qr_ws_doubles(int64_t m, int64_t n);
+int64_t colsign_chunks(int64_t n1);
+hipError_t launch_tsqr_leaf(double* Pw, int h, int N, int L, double* tau, double* ws, int64_t wss,
+                            double* up, hipStream_t s);
+hipError_t launch_tsqr_node(double* S, int N, int cnt, double* tau, double* ws, int64_t wss,
+                            double* up, hipStream_t s);
+hipError_t launch_root_svd(const double* Rf, int N, int64_t n1, double eps, int dm1, int rmax,
+                           double* B, double* U, double* nrm, double* sig, int* perm, int* flag,
+                           double* Y0, double* T, int* rho_out, double* delta_out, hipStream_t s);
+hipError_t launch_tsqr_apply_node(const double* S, const double* tau, int N, int rho, int cnt,
+                                  const double* Yup, int root, double* Yl, hipStream_t s);
+hipError_t launch_tsqr_apply_leaf(const double* Pw, const double* tau, int h, int N, int rho,
+                                  int64_t n1, int L, const double* Yup, double* core1,
+                                  hipStream_t s);
+hipError_t launch_colsign(double* X, int64_t n1, int rho, double* T, int N, double* pv,
+                          int64_t* pi, double* sgn, hipStream_t s);
+hipError_t launch_round_level(const double* T, int rp, int cp, const int* pm, const int* nx, int n,
+                              int q, const double* delta_p, int rmax, double* M, double* ws,
+                              double* tau, double* B, double* U, double* nrm, double* sig,
+                              int* perm, double* sgn, int* flag, double* Y, double* core,
+                              double* Tn, int* rho_out, hipStream_t s);
+hipError_t launch_round_last(const double* T, int rp, int cp, const int* pm, int n, double* core,
+                             hipStream_t s);
+
+// Result of sparse_round: ranks (d + 1) and d device cores (C order (r, I, J, r')),
+// owned by the caller of sparse_round (hipFree each).
+struct RoundedMpo {
+  std::vector<int64_t> ranks;
+  std::vector<double*> cores;
+};
+// Status beyond hipError_t: 1 = an index outside the matrix, 2 = more block
+// positions than the bitmap path takes, 3 = more blocks than the rounding takes.
+hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, const int64_t* row,
+                        const int64_t* col, const double* val, double eps, int rmax,
+                        RoundedMpo* out, int* why, hipStream_t s);
 hipError_t launch_merge_pair_bwd(const double* T, const double* C, const double* dN, double* dT,
                                  double* dC, int a, int I1, int J1, int r, int I2, int J2, int b,
                                  hipStream_t s);

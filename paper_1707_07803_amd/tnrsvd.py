@@ -27,7 +27,8 @@ EXPORTS = [
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
-    "tnrsvd_sparse_to_mpo", "tnrsvd_last_error", "tnrsvd_version",
+    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_round", "tnrsvd_rounded_ranks",
+    "tnrsvd_rounded_copy", "tnrsvd_rounded_destroy", "tnrsvd_last_error", "tnrsvd_version",
 ]
 
 # kernel kinds reported by tnrsvd_profile_read
@@ -101,6 +102,12 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_sparse_to_mpo.argtypes = [I, P64, P64, ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, P64,
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
+    L.tnrsvd_sparse_round.argtypes = [I, P64, P64, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, I,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.tnrsvd_rounded_ranks.argtypes = [ctypes.c_void_p, P64]
+    L.tnrsvd_rounded_copy.argtypes = [ctypes.c_void_p, I, ctypes.c_void_p]
+    L.tnrsvd_rounded_destroy.argtypes = [ctypes.c_void_p]
     L.tnrsvd_last_error.restype = ctypes.c_char_p
     L.tnrsvd_last_error.argtypes = []
     L.tnrsvd_version.restype = ctypes.c_char_p
@@ -381,6 +388,52 @@ def sparse_to_mpo(rows, cols, coo_row, coo_col, coo_val):
     cores = [torch.empty(s, dtype=torch.float64, device=dev) for s in shapes]
     ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
     _check(L.tnrsvd_sparse_to_mpo(d, rr, cc, nnz, *args, ctypes.byref(nb), ptrs, stream))
+    return cores
+
+
+def _coo_args(rows, cols, coo_row, coo_col, coo_val):
+    import torch
+    d = len(rows)
+    if len(cols) != d:
+        raise ValueError("rows and cols differ in length")
+    nnz = int(coo_val.numel())
+    for t, dt in ((coo_row, torch.int64), (coo_col, torch.int64), (coo_val, torch.float64)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != nnz:
+            raise ValueError("COO arrays must be contiguous device tensors of equal length "
+                             "(int64 indices, float64 values)")
+    rr = _dptr([int(x) for x in rows], ntype=ctypes.c_int64)
+    cc = _dptr([int(x) for x in cols], ntype=ctypes.c_int64)
+    ptrs = (ctypes.c_void_p(coo_row.data_ptr()), ctypes.c_void_p(coo_col.data_ptr()),
+            ctypes.c_void_p(coo_val.data_ptr()))
+    stream = ctypes.c_void_p(torch.cuda.current_stream(coo_val.device).cuda_stream)
+    return d, rr, cc, nnz, ptrs, stream
+
+
+def sparse_round(rows, cols, coo_row, coo_col, coo_val, round_tol: float, max_rank: int = 0):
+    """SVD-based rounding (Sec. 3) of the MPO that Algorithm 4.1 builds from a
+    COO matrix, computed by tnrsvd_sparse_round on the current stream.
+
+    Returns the rounded cores as float64 device tensors (r_k, I_k, J_k, r_{k+1}),
+    the first d - 1 left-orthonormal.
+    """
+    import torch
+
+    L = load_library()
+    d, rr, cc, nnz, ptrs, stream = _coo_args(rows, cols, coo_row, coo_col, coo_val)
+    h = ctypes.c_void_p()
+    _check(L.tnrsvd_sparse_round(d, rr, cc, nnz, *ptrs, float(round_tol), int(max_rank), stream,
+                                 ctypes.byref(h)))
+    try:
+        ranks = (ctypes.c_int64 * (d + 1))()
+        _check(L.tnrsvd_rounded_ranks(h, ranks))
+        cores = []
+        for k in range(d):
+            t = torch.empty((ranks[k], rows[k], cols[k], ranks[k + 1]), dtype=torch.float64,
+                            device=coo_val.device)
+            _check(L.tnrsvd_rounded_copy(h, k, ctypes.c_void_p(t.data_ptr())))
+            cores.append(t)
+    finally:
+        L.tnrsvd_rounded_destroy(h)
     return cores
 
 

@@ -29,6 +29,11 @@ duplicates merged (one entry per position, as a stored sparse matrix has):
                  (d = 7), bandwidth 200, ~4 entries per row, 115 far pairs
 * ``circuit150k`` 150102 x 150102, I = J = (1614, 31, 3) (d = 3), bandwidth
                  1962, s = 400, ~5 entries per row
+* ``power16k_stencil``, ``circuit150k_stencil``  the same sizes and
+                 partitions with a fixed stencil (every row has its entries at
+                 the same offsets with the same values, cut at the matrix
+                 edge): banded Toeplitz matrices, whose Algorithm 4.1 MPOs
+                 round to small ranks as the paper's matrices do (Sec. 6.1)
 """
 
 from __future__ import annotations
@@ -41,7 +46,8 @@ import numpy as np
 __all__ = ["Workload", "random_mpo", "gaussian_omega", "orthonormal_mps",
            "known_spectrum_mpo", "small", "spectrum", "large", "batched",
            "grad", "get", "WORKLOADS", "SparseWorkload", "banded_sparse", "power16k",
-           "circuit150k", "SPARSE_WORKLOADS"]
+           "circuit150k", "stencil_sparse", "power16k_stencil", "circuit150k_stencil",
+           "SPARSE_WORKLOADS", "ROUND_WORKLOADS"]
 
 
 @dataclass
@@ -226,3 +232,35 @@ def circuit150k() -> SparseWorkload:
 
 
 SPARSE_WORKLOADS = {"power16k": power16k, "circuit150k": circuit150k}
+
+
+def stencil_sparse(n: int, n_used: int, half_bw: int, n_off: int,
+                   seed) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """COO of an n x n banded Toeplitz matrix supported on its leading
+    n_used x n_used part: offset 0 (value 4 + |N(0,1)|) and n_off - 1 further
+    distinct offsets drawn uniformly from [-half_bw, half_bw], each with one
+    N(0,1) value shared by every row.  Sorted by (row, col)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    others = rng.choice(np.setdiff1d(np.arange(-half_bw, half_bw + 1), [0]), n_off - 1,
+                        replace=False)
+    offs = np.concatenate([[0], np.sort(others)]).astype(np.int64)
+    vals = np.concatenate([[4.0 + abs(rng.standard_normal())], rng.standard_normal(n_off - 1)])
+    i = np.repeat(np.arange(n_used, dtype=np.int64), n_off)
+    j = i + np.tile(offs, n_used)
+    v = np.tile(vals, n_used)
+    ok = (j >= 0) & (j < n_used)
+    return i[ok], j[ok], v[ok]
+
+
+def power16k_stencil() -> SparseWorkload:
+    r, c, v = stencil_sparse(16384, 15838, 200, 7, 23)
+    return SparseWorkload("power16k_stencil", [256] + [2] * 6, [256] + [2] * 6, r, c, v)
+
+
+def circuit150k_stencil() -> SparseWorkload:
+    r, c, v = stencil_sparse(150102, 150102, 1962, 9, 24)
+    return SparseWorkload("circuit150k_stencil", [1614, 31, 3], [1614, 31, 3], r, c, v)
+
+
+ROUND_WORKLOADS = {"power16k_stencil": power16k_stencil,
+                   "circuit150k_stencil": circuit150k_stencil, "power16k": power16k}
