@@ -343,7 +343,9 @@ tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* co
  * as a TSQR over all CUs; every later core is one small SVD.
  * Arguments as tnrsvd_sparse_to_mpo.  The zero matrix gives all-zero rank-1
  * cores; d = 1 gives the matrix itself.  Limits: at most 2^28 block
- * positions (I / I_1)(J / J_1) and 16384 nonzero blocks.
+ * positions (I / I_1)(J / J_1), 16384 nonzero blocks, and I_1 J_1 < 2^31.
+ * Rows of the first core without any nonzero entry add nothing to its R
+ * factor and get zero rows in the result, so the TSQR runs over the others.
  * stream: hipStream_t (NULL: null stream); the call allocates its own
  * workspace, frees it, and synchronises the stream.
  * *out receives a handle owning the rounded cores (device memory) until

@@ -311,13 +311,39 @@ __global__ void k_class_info(const uint64_t* __restrict__ bkey, int64_t N, int64
   }
 }
 
+// Rows of core 1 (m = (i mod I1) J1 + (j mod J1)) that hold a nonzero entry.
+__global__ void k_mark_rows(const int64_t* __restrict__ row, const int64_t* __restrict__ col,
+                            const double* __restrict__ val, int64_t nnz, int64_t I1, int64_t J1,
+                            unsigned* __restrict__ rbm) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (val[e] == 0.0) continue;
+    const uint64_t m = (uint64_t)((row[e] % I1) * J1 + col[e] % J1);
+    const unsigned bit = 1u << (m & 31);
+    if (!(rbm[m >> 5] & bit)) atomicOr(rbm + (m >> 5), bit);
+  }
+}
+
+// row of core 1 held by each compact row (rank of its bit)
+__global__ void k_row_list(const unsigned* __restrict__ rbm, const int* __restrict__ rws,
+                           int64_t nw, int64_t* __restrict__ rlist) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nw * 32;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned word = rbm[g >> 5];
+    const unsigned b = (unsigned)(g & 31);
+    if ((word >> b) & 1u) rlist[rws[g >> 5] - __popc(word) + __popc(word & ((1u << b) - 1u))] = g;
+  }
+}
+
 // Core 1 as row tiles for TSQR: entry (i, j) of block t adds into tile
-// l = m / h, element (m mod h, t) of the h x N column-major tile, where
-// m = (i mod I1) J1 + (j mod J1) is its row of core 1.
+// l = m / h, element (m mod h, t) of the h x N column-major tile, where m is
+// its row of core 1, or that row's rank among the nonzero rows when rbm is
+// given.
 __global__ void k_scatter_tiles(const int64_t* __restrict__ row, const int64_t* __restrict__ col,
                                 const double* __restrict__ val, int64_t nnz, int64_t I1, int64_t J1,
                                 int64_t nbc, const unsigned* __restrict__ bm,
-                                const int* __restrict__ ws, int64_t h, int64_t N,
+                                const int* __restrict__ ws, const unsigned* __restrict__ rbm,
+                                const int* __restrict__ rws, int64_t h, int64_t N,
                                 double* __restrict__ Pw) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -325,9 +351,18 @@ __global__ void k_scatter_tiles(const int64_t* __restrict__ row, const int64_t* 
     if (v == 0.0) continue;
     const int64_t i = row[e], j = col[e];
     const int64_t t = block_of(bm, ws, (uint64_t)((i / I1) * nbc + j / J1));
-    const int64_t m = (i % I1) * J1 + j % J1;
+    int64_t m = (i % I1) * J1 + j % J1;
+    if (rbm) m = block_of(rbm, rws, (uint64_t)m);
     atomicAdd(Pw + (m / h) * h * N + t * h + m % h, v);
   }
+}
+
+// core1[rlist[r], :] = Uc[r, :] (row-major, rho columns); other rows stay zero
+__global__ void k_expand_rows(const double* __restrict__ Uc, const int64_t* __restrict__ rlist,
+                              int64_t nc, int64_t rho, double* __restrict__ core1) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nc * rho;
+       e += (int64_t)gridDim.x * blockDim.x)
+    core1[rlist[e / rho] * rho + e % rho] = Uc[e];
 }
 
 // Scratch kept per device between calls (up to kCacheMax bytes); the mutex is
@@ -646,7 +681,7 @@ hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, 
     }
     if (e == hipSuccess && N > 0) {
       k_scatter_tiles<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, I[0], J[0], nbc, bm, wsb,
-                                                   n1, 1, cores[0]);
+                                                   nullptr, nullptr, n1, 1, cores[0]);
       e = hipGetLastError();
     }
     return finish();
@@ -690,16 +725,33 @@ hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, 
                                            k + 1 < d ? cls[k + 1] : nullptr, pm[k], nx[k]);
     e = hipGetLastError();
   }
+  // nonzero rows of core 1 (cnt[d]): the TSQR runs over those alone, since
+  // zero rows add nothing to R and the left singular vectors vanish on them
+  const int64_t nwr = (n1 + 31) / 32;
+  unsigned* rbm = A.get<unsigned>(nwr);
+  int* rws = A.get<int>(nwr);
+  if (e == hipSuccess) e = A.e;
+  zero(rbm, 4 * nwr);
+  if (e == hipSuccess) {
+    k_mark_rows<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, I[0], J[0], rbm);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = scan_words(A, rbm, rws, nwr, cnt + d, s);
   std::vector<int> hcnt(d + 2, 0);
   read_back(hcnt.data(), cnt, sizeof(int) * (d + 2));
   if (e != hipSuccess) return e;
   std::vector<int64_t> r(d, 1);   // r[k]: classes at level k (columns of the factor entering core k)
   r[1] = N;
   for (int k = 2; k < d; ++k) r[k] = hcnt[k];
+  const int64_t n1c = hcnt[d];
+  int64_t* rlist = A.get<int64_t>(n1c);
+  if ((e = A.e) != hipSuccess) return e;
+  k_row_list<<<grid_n(nwr * 32), 256, 0, s>>>(rbm, rws, nwr, rlist);
+  e = hipGetLastError();
 
-  // 3. core 1: TSQR of P in row tiles of h rows (h >= N)
+  // 3. core 1: TSQR of P (its n1c nonzero rows) in row tiles of h rows (h >= N)
   const int64_t h = N <= 960 ? 960 : (N + 63) / 64 * 64;
-  const int64_t L = (n1 + h - 1) / h;
+  const int64_t L = (n1c + h - 1) / h;
   double* Pw = A.get<double>(L * h * N);
   double* tauL = A.get<double>(L * N);
   const int64_t wssL = qr_ws_doubles(h, N);
@@ -721,8 +773,8 @@ hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, 
   if (e == hipSuccess) e = A.e;
   zero(Pw, 8 * L * h * N);
   if (e != hipSuccess) return e;
-  k_scatter_tiles<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, I[0], J[0], nbc, bm, wsb, h, N,
-                                               Pw);
+  k_scatter_tiles<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, I[0], J[0], nbc, bm, wsb, rbm,
+                                               rws, h, N, Pw);
   e = hipGetLastError();
   if (e == hipSuccess)
     e = launch_tsqr_leaf(Pw, (int)h, (int)N, (int)L, tauL, wsL, wssL, L == 1 ? Rf : S[0], s);
@@ -743,7 +795,7 @@ hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, 
   double* delta_d = A.get<double>(1);
   if (e == hipSuccess) e = A.e;
   if (e == hipSuccess)
-    e = launch_root_svd(Rf, (int)N, n1, eps, d - 1, rmax, B, U, nrm, sig, perm, flag, Y0, T,
+    e = launch_root_svd(Rf, (int)N, n1c, eps, d - 1, rmax, B, U, nrm, sig, perm, flag, Y0, T,
                         rho_d + 1, delta_d, s);
   int rho1 = 0;
   read_back(&rho1, rho_d + 1, sizeof(int));
@@ -751,10 +803,12 @@ hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, 
   out->ranks[1] = rho1;
 
   // 5. left vectors of P: the tree's reflectors top-down, then the leaves'
+  // (compact rows), signs, and the rows put back in place
   cores[0] = A.get<double>(n1 * rho1);
+  double* Uc = A.get<double>(n1c * rho1);
   std::vector<double*> Yl(lv.size());
   for (size_t j = 0; j < lv.size(); ++j) Yl[j] = A.get<double>(lv[j] * 2 * N * rho1);
-  const int64_t nch = colsign_chunks(n1);
+  const int64_t nch = colsign_chunks(n1c);
   double* pv = A.get<double>(nch * rho1);
   int64_t* pi = A.get<int64_t>(nch * rho1);
   double* sgn = A.get<double>(rho1);
@@ -765,9 +819,14 @@ hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, 
                                top, Yl[j], s);
   }
   if (e == hipSuccess)
-    e = launch_tsqr_apply_leaf(Pw, tauL, (int)h, (int)N, rho1, n1, (int)L,
-                               L == 1 ? Y0 : Yl[0], cores[0], s);
-  if (e == hipSuccess) e = launch_colsign(cores[0], n1, rho1, T, (int)N, pv, pi, sgn, s);
+    e = launch_tsqr_apply_leaf(Pw, tauL, (int)h, (int)N, rho1, n1c, (int)L,
+                               L == 1 ? Y0 : Yl[0], Uc, s);
+  if (e == hipSuccess) e = launch_colsign(Uc, n1c, rho1, T, (int)N, pv, pi, sgn, s);
+  zero(cores[0], 8 * n1 * rho1);
+  if (e == hipSuccess) {
+    k_expand_rows<<<grid_n(n1c * rho1), 256, 0, s>>>(Uc, rlist, n1c, rho1, cores[0]);
+    e = hipGetLastError();
+  }
 
   // 6. cores 2..d-1: one truncated SVD per core
   int64_t rp = rho1, cp = N;
