@@ -363,16 +363,17 @@ def rounding_section(steps, cpu_baseline_on):
 
 def measured_traffic(precision):
     """HBM bytes per sweep from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
-    or None when the sweep kernel's source no longer matches the profiled one."""
+    or None when the sweep kernel's sources (the kernel file and the workgroup
+    linear-algebra header it includes) no longer match the profiled ones."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_rl_pass_spectrum_{precision}_traffic.md")
     try:
         text = open(path).read()
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-        src = open(os.path.join(ROOT, blob["source"]), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in blob["sources"])
     except (OSError, IndexError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest() != blob["source_sha256"]:
+    if hashlib.sha256(src).hexdigest() != blob["sources_sha256"]:
         return None
     return blob["read_bytes_per_launch"] + blob["write_bytes_per_launch"]
 
