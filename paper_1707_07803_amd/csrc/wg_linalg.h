@@ -166,30 +166,36 @@ __device__ void wg_geqr2(double* X, int m, int n, double* tau, double* v, double
   }
 }
 
-// C (M x N) = beta C + alpha A (M x K) B (K x N) with FP64 accumulation, by
-// the whole workgroup.  Element (i, k) of A is A[i sai + k sak], (k, j) of B
-// is B[k sbk + j sbj] (type TB, widened to FP64) and (i, j) of C is
-// C[i sci + j scj]; C may be in global memory or LDS.  TM x TN output tiles
-// (64 x 64, or 128 x 32 for products only a few columns wide); K goes through
-// LDS GK at a time, the next chunk's loads (clamped in-bounds addresses,
-// mapped so the unit-stride index runs across lanes) in flight while the
-// current one is multiplied; each thread owns a 4 x 2 block of a tile, and
-// when beta != 0 its C values are loaded before the K loop.  beta == 0 never
-// reads C.  `lds` holds GEMM_LDS doubles.  Ends with a barrier.
+// C (M x N) = beta C + alpha A (M x K) B (K x N) in FP64 by the whole
+// workgroup, on the FP64 matrix cores (v_mfma_f64_16x16x4f64: a wave
+// multiplies a 16 x 4 block of A by a 4 x 16 block of B into a 16 x 16
+// accumulator; lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+// holds D[4 j + l / 16][l % 16] in its j-th accumulator double).  Element
+// (i, k) of A is A[i sai + k sak], (k, j) of B is B[k sbk + j sbj] (type TB,
+// widened to FP64) and (i, j) of C is C[i sci + j scj]; C may be in global
+// memory or LDS.  TM x TN output tiles (64 x 64, or 128 x 32 for products
+// only a few columns wide): the eight waves form a 4 x 2 grid, each owning
+// TM/64 x TN/32 accumulator blocks.  K goes through LDS GK at a time, the next
+// chunk's loads (clamped in-bounds addresses, mapped so the unit-stride index
+// runs across lanes) held in registers while the current one is multiplied.
+// beta == 0 never reads C.  `lds` holds GEMM_LDS doubles.  Ends with a barrier.
 constexpr int GK = 32;
 constexpr int GEMM_LDS = GK * (128 + 1) + GK * (64 + 1);
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 template <int TM, int TN, typename TB>
 __device__ void wg_gemm_t(int M, int N, int K, double alpha, const double* A, int64_t sai,
                           int64_t sak, const TB* B, int64_t sbk, int64_t sbj, double beta,
                           double* C, int64_t sci, int64_t scj, double* lds) {
-  constexpr int TX = TN / 2, TY = NT / TX;           // threads across columns / rows
-  static_assert(TY * 4 == TM, "4 rows per thread");
+  static_assert((TM == 64 || TM == 128) && (TN == 32 || TN == 64), "tile shapes");
+  constexpr int WR = TM / 64, CB = TN / 32;          // accumulator blocks per wave
   constexpr int ALD = TM + 1, BLD = TN + 1;
   constexpr int NA = TM * GK / NT, NB = TN * GK / NT;  // loads per thread and chunk
-  const int tid = threadIdx.x;
+  static_assert(GK * (ALD + BLD) <= GEMM_LDS, "LDS tiles");
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w & 3, wc = w >> 2;
+  const int r16 = lane & 15, q4 = lane >> 4;
   double* As = lds;             // As[k * ALD + i]
   double* Bs = lds + GK * ALD;  // Bs[k * BLD + j]
-  const int ty = tid / TX, tx = tid % TX;
   const bool a_ifast = sai == 1, b_jfast = sbj == 1;
   int ai[NA], ak[NA], bk[NB], bj[NB];
 #pragma unroll
@@ -206,17 +212,11 @@ __device__ void wg_gemm_t(int M, int N, int K, double alpha, const double* A, in
   }
   for (int i0 = 0; i0 < M; i0 += TM) {
     for (int j0 = 0; j0 < N; j0 += TN) {
-      double acc[4][2], cold[4][2];
+      dbl4 acc[WR][CB];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int a = 0; a < WR; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          acc[r][c] = 0.0;
-          const int i = i0 + ty * 4 + r, j = j0 + tx + TX * c;
-          const bool ok = beta != 0.0 && i < M && j < N;
-          const double v = C[ok ? (int64_t)i * sci + (int64_t)j * scj : 0];
-          cold[r][c] = ok ? v : 0.0;
-        }
+        for (int c = 0; c < CB; ++c) acc[a][c] = dbl4{0.0, 0.0, 0.0, 0.0};
       double av[NA], bv[NB];
       auto fetch = [&](int k0) {
 #pragma unroll
@@ -241,26 +241,35 @@ __device__ void wg_gemm_t(int M, int N, int K, double alpha, const double* A, in
         for (int t = 0; t < NB; ++t) Bs[bk[t] * BLD + bj[t]] = bv[t];
         __syncthreads();
         if (k0 + GK < K) fetch(k0 + GK);
-#pragma unroll 8
-        for (int k = 0; k < GK; ++k) {
-          const double b0 = Bs[k * BLD + tx], b1 = Bs[k * BLD + tx + TX];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const double a = As[k * ALD + ty * 4 + r];
-            acc[r][0] += a * b0;
-            acc[r][1] += a * b1;
+        for (int kk = 0; kk < GK; kk += 4) {
+          const int k = kk + q4;
+          double b[CB];
+#pragma unroll
+          for (int c = 0; c < CB; ++c) b[c] = Bs[k * BLD + wc * (TN / 2) + c * 16 + r16];
+#pragma unroll
+          for (int a = 0; a < WR; ++a) {
+            const double x = As[k * ALD + wr * (TM / 4) + a * 16 + r16];
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+              acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, b[c], acc[a][c], 0, 0, 0);
           }
         }
         __syncthreads();
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int a = 0; a < WR; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int i = i0 + ty * 4 + r, j = j0 + tx + TX * c;
-          if (i < M && j < N)
-            C[(int64_t)i * sci + (int64_t)j * scj] = beta * cold[r][c] + alpha * acc[r][c];
-        }
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int i = i0 + wr * (TM / 4) + a * 16 + 4 * jj + q4;
+            const int j = j0 + wc * (TN / 2) + c * 16 + r16;
+            if (i < M && j < N) {
+              double* cp = C + (int64_t)i * sci + (int64_t)j * scj;
+              *cp = alpha * acc[a][c][jj] + (beta != 0.0 ? beta * *cp : 0.0);
+            }
+          }
     }
   }
   __syncthreads();
