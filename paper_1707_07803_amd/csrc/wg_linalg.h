@@ -295,11 +295,13 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
 // Ts, Gs: QBMAX x QBMAX doubles each in LDS outside lds.
 constexpr int QB = 16;      // block width of the left-to-right pass
 constexpr int QBMAX = 32;   // widest block; Ts and Gs are QBMAX x QBMAX
-__device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double* red, double* ws,
-                         double* lds, int64_t lds_cap, double* Ts, double* Gs, int64_t ld = -1,
-                         int qb = QB) {
+// A panel too tall for LDS at width qb is itself factorised in QB-wide blocks
+// in LDS (NEST) when those fit, else column by column in global memory.
+template <bool NEST>
+__device__ void wg_geqrf_impl(double* X, int m, int n, double* tau, double* v, double* red,
+                              double* ws, double* lds, int64_t lds_cap, double* Ts, double* Gs,
+                              int64_t ld, int qb) {
   const int tid = threadIdx.x;
-  if (ld < 0) ld = m;
   const int kmax = m < n ? m : n;
   for (int j0 = 0; j0 < kmax; j0 += qb) {
     const int jb = (kmax - j0) < qb ? (kmax - j0) : qb;
@@ -324,7 +326,10 @@ __device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double
       __syncthreads();
       if (nc <= 0) continue;
     } else {
-      wg_geqr2(P0, mp, jb, tau + j0, v, red, ld);
+      if (NEST && jb > QB && (int64_t)mp * (QB + 1) <= lds_cap)
+        wg_geqrf_impl<false>(P0, mp, jb, tau + j0, v, red, ws, lds, lds_cap, Ts, Gs, ld, QB);
+      else
+        wg_geqr2(P0, mp, jb, tau + j0, v, red, ld);
       if (nc <= 0) continue;
       for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
         const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
@@ -358,6 +363,12 @@ __device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double
     wg_gemm<double>(mp, nc, jb, -1.0, Vp, 1, mp, Wt2, 1, qb, 1.0, C, 1, ld, lds);
   }
   __syncthreads();
+}
+
+__device__ void wg_geqrf(double* X, int m, int n, double* tau, double* v, double* red, double* ws,
+                         double* lds, int64_t lds_cap, double* Ts, double* Gs, int64_t ld = -1,
+                         int qb = QB) {
+  wg_geqrf_impl<true>(X, m, n, tau, v, red, ws, lds, lds_cap, Ts, Gs, ld < 0 ? m : ld, qb);
 }
 
 // Y <- H_0 H_1 ... H_{k-1} Y for the m x s column-major Y (ld m), with the
