@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--sparse", choices=["on", "off", "only"], default="on",
                     help="time the sparse-to-MPO conversion (Algorithm 4.1) too / not / alone")
     ap.add_argument("--sparse-steps", type=int, default=20)
+    ap.add_argument("--batched-full", action="store_true",
+                    help="time the whole 512-MPO uneven batch once (minutes) and exit")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the timings of the other workloads (plain FP64, large, "
                          "batched uneven subset, gradient)")
@@ -361,6 +363,40 @@ def rounding_section(steps, cpu_baseline_on):
     return out
 
 
+def batched_full(precisions):
+    """The whole uneven batch (512 MPOs, d in [10,40], I=J in {2,4}, ranks in [4,32],
+    k=8 p=8 q=1, r_max=32) as one handle: one warm-up solve and one timed solve per
+    precision, with per-kernel event times.  The largest members bound the batch."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1707_07803_amd import TNrSVD
+
+    Ws = wl.batched(512)
+    out = {"workload": "512 uneven MPOs (d in [10,40], I=J in {2,4}, ranks in [4,32], N(0,1/R)), "
+                       "k=8 p=8 q=1, r_max=32, one handle, persistent launches"}
+    for p in precisions:
+        td = torch.float64 if p == "f64" else torch.float32
+        mpos = [[torch.as_tensor(c, dtype=td).cuda() for c in w.cores] for w in Ws]
+        h = TNrSVD(mpos, 8, 8, 1, seed=9, precision=p, max_rank=32)
+        del mpos
+        h.run(False)
+        torch.cuda.synchronize()
+        print(f"[bench] full batch {p}: warm-up solve done", file=sys.stderr, flush=True)
+        h.profile(True)
+        t0 = time.perf_counter()
+        h.run(False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kern = {k: round(h.profile_read(k)[0], 1) for k in ("contract", "rl_sweep", "lr_sweep")}
+        h.profile(False)
+        h.close()
+        out[p] = {"seconds_per_batch": round(dt, 3), "solves_per_s": round(512 / dt, 3),
+                  "kernel_ms": kern}
+        print(f"[bench] full batch {p}: {dt:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
 def measured_traffic(precision):
     """HBM bytes per sweep from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
     or None when the sweep kernel's sources (the kernel file and the workgroup
@@ -423,6 +459,9 @@ def main():
                                    "described in DESIGN.md and not launched",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.batched_full:
+        print(json.dumps({"batched_full": batched_full(args.precisions.split(",")[:2])}))
+        return
     import numpy as np
     import torch
     import workloads as wl
