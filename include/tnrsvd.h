@@ -82,7 +82,29 @@ typedef struct {
   int64_t max_rank;          /* rounding rank cap r_max (0: none)            */
   int check_finite;          /* nonzero: scan input cores for NaN/Inf        */
   void* stream;              /* hipStream_t, borrowed; NULL = null stream    */
+  int orientation;           /* tnrsvd_orientation                           */
 } tnrsvd_opts;
+
+/*
+ * Orientation of the K leg (the paper's Sec. 5: Omega, Y and Q carry their K
+ * columns on the FIRST core and the sweeps run right to left).
+ *   TNRSVD_K_LAST  (0): the library's own layout, K on the last core.
+ *   TNRSVD_K_FIRST (1): the paper's layout.  The MPO is read in reversed core
+ *     order with each core's rank legs swapped (the same matrix with row and
+ *     column digits reversed, so the same singular values), solved in the
+ *     library's layout, and every result is returned reversed back:
+ *     tnrsvd_copy_factor writes core k of the paper's layout (the K leg on
+ *     core 0, shape (K, n, r) there), tnrsvd_get_ranks lists the bonds from
+ *     the first core, tnrsvd_backward takes dcores in the caller's order.
+ *     The leading cores are merged until I_1, J_1 >= K (as in Sec. 6.3).
+ *     tnrsvd_get_factor reports the paper-layout shape with *dev_ptr = NULL
+ *     (the core exists only in the library's layout); tnrsvd_get_omega /
+ *     tnrsvd_set_omega and tnrsvd_get_product_ranks keep the library's order.
+ */
+typedef enum {
+  TNRSVD_K_LAST = 0,
+  TNRSVD_K_FIRST = 1
+} tnrsvd_orientation;
 
 /*
  * tnrsvd_create -- validate, plan and stage `batch` independent MPOs.
@@ -233,8 +255,10 @@ tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice);
 
 /*
  * tnrsvd_get_factor -- borrow a device pointer to one core of a result.
- *   which 0: U (row space, last core (r, I, k)), available after solve;
- *   which 1: V (column space, last core (s, J, k)), after solve;
+ *   which 0: U (row space, last core (r, I, K)), available after solve;
+ *   which 1: V (column space, last core (s, J, K)), after solve; U and V
+ *            keep all K singular vectors of the projected core, the first
+ *            k columns belonging to the returned sigma_1..sigma_k;
  *   which 2: the current basis (Q after an orthogonalize; last core (r,n,K));
  *   which 3: the first product Y = A Omega of the last run (last (R,I,K)),
  *            valid until the next tnrsvd_mult.

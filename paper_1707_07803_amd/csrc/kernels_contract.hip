@@ -246,6 +246,63 @@ hipError_t launch_convert_core(const void* in, int in_dtype, void* out, int out_
   return hipGetLastError();
 }
 
+// out (R1, I, J, R0) = in (R0, I, J, R1) with the two rank legs swapped: one
+// core of an MPO (J = 1: of an MPS) read in the reversed core order.
+template <typename T>
+__global__ void k_swap_legs(const T* __restrict__ in, T* __restrict__ out, int64_t R0, int64_t I,
+                            int64_t J, int64_t R1) {
+  const int64_t n = R0 * I * J * R1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e % R1, ij = (e / R1) % (I * J), a = e / (R1 * I * J);
+    out[(b * I * J + ij) * R0 + a] = in[e];
+  }
+}
+
+hipError_t launch_swap_legs(const void* in, int dtype, void* out, int64_t R0, int64_t I, int64_t J,
+                            int64_t R1, hipStream_t s) {
+  const int64_t n = R0 * I * J * R1;
+  if (n <= 0) return hipSuccess;
+  const int g = grid_for(n, 256, 4096);
+  by_dtype(dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
+    k_swap_legs<T><<<g, 256, 0, s>>>((const T*)in, (T*)out, R0, I, J, R1);
+  });
+  return hipGetLastError();
+}
+
+// out (R1, n, R0) = in (R0, n, R1) with the rank legs swapped and the mode
+// index n, little-endian in the digits of radices rad[0..nd-1] (eq. (1)),
+// rewritten little-endian in the reversed digit order: one core of an MPS whose
+// cores, some of them merged, are read in the reversed order.
+template <typename T>
+__global__ void k_reverse_core(const T* __restrict__ in, T* __restrict__ out, int64_t R0, int64_t n,
+                               int64_t R1, Radices rad) {
+  const int64_t total = R0 * n * R1;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e % R1, a = e / (R1 * n);
+    int64_t idx = (e / R1) % n, rev = 0;
+    for (int k = 0; k < rad.nd; ++k) {   // digit k weighs the radices after it
+      rev += (idx % rad.r[k]) * rad.below[k];
+      idx /= rad.r[k];
+    }
+    out[(b * n + rev) * R0 + a] = in[e];
+  }
+}
+
+hipError_t launch_reverse_core(const void* in, int dtype, void* out, int64_t R0, int64_t n,
+                               int64_t R1, const Radices& rad, hipStream_t s) {
+  const int64_t total = R0 * n * R1;
+  if (total <= 0) return hipSuccess;
+  const int g = grid_for(total, 256, 4096);
+  by_dtype(dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
+    k_reverse_core<T><<<g, 256, 0, s>>>((const T*)in, (T*)out, R0, n, R1, rad);
+  });
+  return hipGetLastError();
+}
+
 hipError_t launch_check_finite(const void* in, int dtype, int64_t n, int* flag, hipStream_t s) {
   const int g = grid_for(n, 256, 4096);
   if (dtype == 0)

@@ -52,6 +52,10 @@ constexpr int kKinds = 6;  // contract, rl, lr, form_u, load_omega, copy_y0
 
 struct tnrsvd_s {
   int device = 0;
+  // TNRSVD_K_FIRST: the caller's MPO b was read reversed (core i of the caller is
+  // core d - 1 - i here, rank legs swapped); paper_shape[b] keeps the caller's cores
+  int orientation = 0;
+  std::vector<std::vector<std::array<int64_t, 4>>> paper_shape;
   hipStream_t stream = nullptr;
   int batch = 0;
   int dtype = 0;         // contraction storage of A, X, Z: kF64, kF32 or kBF16
@@ -205,8 +209,8 @@ tnrsvd_status tnrsvd_destroy(tnrsvd_t h) {
   return TNRSVD_OK;
 }
 
-tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
-                            const tnrsvd_opts* o) {
+static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
+                                const tnrsvd_opts* o) {
   g_err.clear();
   if (!out || !mpos || !o) return fail(TNRSVD_E_INVALID, "null argument");
   *out = nullptr;
@@ -577,6 +581,72 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
     }
   }
   *out = h;
+  return TNRSVD_OK;
+}
+
+// TNRSVD_K_FIRST: stage every MPO reversed (core order reversed, rank legs
+// swapped) and plan it as usual; results are reversed back on the way out.
+tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
+                            const tnrsvd_opts* o) {
+  g_err.clear();
+  if (!out || !mpos || !o) return fail(TNRSVD_E_INVALID, "null argument");
+  if (o->orientation != TNRSVD_K_LAST && o->orientation != TNRSVD_K_FIRST)
+    return fail(TNRSVD_E_INVALID, "unknown orientation %d", o->orientation);
+  if (o->orientation == TNRSVD_K_LAST) return create_lib(out, batch, mpos, o);
+  *out = nullptr;
+  if (batch < 1) return fail(TNRSVD_E_INVALID, "batch must be >= 1");
+  const hipStream_t s = (hipStream_t)o->stream;
+  std::vector<void*> temps;
+  std::vector<std::vector<int64_t>> rk(batch), rw(batch), cl(batch);
+  std::vector<std::vector<const void*>> cp(batch);
+  std::vector<tnrsvd_mpo> rev(batch);
+  std::vector<std::vector<std::array<int64_t, 4>>> shapes(batch);
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : temps) (void)hipFree(p);
+  };
+  for (int b = 0; b < batch; ++b) {
+    const tnrsvd_mpo& a = mpos[b];
+    if (a.d < 1) return cleanup(), fail(TNRSVD_E_SHAPE, "d must be >= 1");
+    if (!a.rank || !a.rows || !a.cols || !a.core)
+      return cleanup(), fail(TNRSVD_E_INVALID, "null rank/rows/cols/core array");
+    if (a.dtype != TNRSVD_F64 && a.dtype != TNRSVD_F32)
+      return cleanup(), fail(TNRSVD_E_INVALID, "core dtype must be F64 or F32");
+    const int d = a.d;
+    const int dt = a.dtype == TNRSVD_F64 ? kF64 : kF32;
+    rk[b].resize(d + 1);
+    rw[b].resize(d);
+    cl[b].resize(d);
+    cp[b].resize(d);
+    for (int i = 0; i <= d; ++i) rk[b][i] = a.rank[d - i];
+    for (int i = 0; i < d; ++i) {
+      const int src = d - 1 - i;
+      const int64_t R0 = a.rank[src], I = a.rows[src], J = a.cols[src], R1 = a.rank[src + 1];
+      if (R0 < 1 || I < 1 || J < 1 || R1 < 1 || !a.core[src])
+        return cleanup(), fail(TNRSVD_E_SHAPE, "MPO %d core %d: bad shape or null core", b, src);
+      rw[b][i] = I;
+      cl[b][i] = J;
+      void* t = nullptr;
+      if (hipMalloc(&t, (size_t)(R0 * I * J * R1) * (dt == kF64 ? 8 : 4)) != hipSuccess) {
+        (void)hipGetLastError();
+        return cleanup(), fail(TNRSVD_E_NOMEM, "staging the reversed cores");
+      }
+      temps.push_back(t);
+      const hipError_t e = launch_swap_legs(a.core[src], dt, t, R0, I, J, R1, s);
+      if (e != hipSuccess) return cleanup(), dev_check(e, "reverse core");
+      cp[b][i] = t;
+    }
+    for (int i = 0; i < d; ++i)
+      shapes[b].push_back({a.rank[i], a.rows[i], a.cols[i], a.rank[i + 1]});
+    rev[b] = tnrsvd_mpo{d, rk[b].data(), rw[b].data(), cl[b].data(), cp[b].data(), a.dtype};
+  }
+  tnrsvd_opts lib = *o;
+  lib.orientation = TNRSVD_K_LAST;
+  const tnrsvd_status st = create_lib(out, batch, rev.data(), &lib);
+  cleanup();
+  if (st != TNRSVD_OK) return st;
+  (*out)->orientation = TNRSVD_K_FIRST;
+  (*out)->paper_shape = shapes;
   return TNRSVD_OK;
 }
 
@@ -999,7 +1069,7 @@ tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice) {
   return TNRSVD_OK;
 }
 
-tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores) {
+static tnrsvd_status backward_lib(tnrsvd_t h, const double* dsigma, void* const* dcores) {
   TRY(check_handle(h));
   if (!dcores) return fail(TNRSVD_E_INVALID, "null gradient pointer array");
   if (!h->solved) return fail(TNRSVD_E_STATE, "no solve to differentiate");
@@ -1079,6 +1149,48 @@ tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dco
   return TNRSVD_OK;
 }
 
+// TNRSVD_K_FIRST: gradients are formed in the library's layout in staging
+// buffers, then written reversed (core order and rank legs) to the caller's.
+tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores) {
+  TRY(check_handle(h));
+  if (h->orientation != TNRSVD_K_FIRST) return backward_lib(h, dsigma, dcores);
+  if (!dcores) return fail(TNRSVD_E_INVALID, "null gradient pointer array");
+  std::vector<void*> tmp;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(h->stream);
+    for (void* p : tmp) (void)hipFree(p);
+  };
+  for (int b = 0; b < h->batch; ++b) {
+    const size_t esz = elem_size(h->in_dtype[b]);
+    const auto& ps = h->paper_shape[b];
+    for (int i = 0; i < (int)ps.size(); ++i) {
+      const auto& c = ps[ps.size() - 1 - i];
+      void* t = nullptr;
+      if (hipMalloc(&t, (size_t)(c[0] * c[1] * c[2] * c[3]) * esz) != hipSuccess) {
+        (void)hipGetLastError();
+        return release(), fail(TNRSVD_E_NOMEM, "staging the gradient cores");
+      }
+      tmp.push_back(t);
+    }
+  }
+  tnrsvd_status st = backward_lib(h, dsigma, tmp.data());
+  int base = 0;
+  for (int b = 0; b < h->batch && st == TNRSVD_OK; ++b) {
+    const auto& ps = h->paper_shape[b];
+    const int d = (int)ps.size();
+    for (int i = 0; i < d && st == TNRSVD_OK; ++i) {
+      const auto& c = ps[d - 1 - i];   // library core i is the caller's core d - 1 - i
+      st = dev_check(launch_swap_legs(tmp[base + i], h->in_dtype[b], dcores[base + d - 1 - i],
+                                      c[3], c[1], c[2], c[0], h->stream),
+                     "reverse gradient");
+    }
+    base += d;
+  }
+  if (st == TNRSVD_OK) st = dev_check(hipStreamSynchronize(h->stream), "synchronise");
+  release();
+  return st;
+}
+
 tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merged) {
   TRY(check_handle(h));
   if (b < 0 || b >= h->batch) return fail(TNRSVD_E_INVALID, "MPO index out of range");
@@ -1090,12 +1202,15 @@ tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merg
   TRY(dev_check(hipMemcpy(tmp.data(), h->xr + md.r0, sizeof(int) * (md.d + 1),
                           hipMemcpyDeviceToHost),
                 "copy ranks"));
-  for (int i = 0; i <= md.d; ++i) host_out[i] = tmp[i];
+  for (int i = 0; i <= md.d; ++i)
+    host_out[i] = tmp[h->orientation == TNRSVD_K_FIRST ? md.d - i : i];
   return TNRSVD_OK;
 }
 
-tnrsvd_status tnrsvd_get_factor(tnrsvd_t h, int b, int which, int core, const void** dev_ptr,
-                                int64_t shape[4], int* dtype) {
+}  // extern "C"
+
+static tnrsvd_status get_factor_lib(tnrsvd_t h, int b, int which, int core, const void** dev_ptr,
+                                    int64_t shape[4], int* dtype) {
   TRY(check_handle(h));
   if (b < 0 || b >= h->batch) return fail(TNRSVD_E_INVALID, "MPO index out of range");
   const MpoDesc& md = h->mh[b];
@@ -1150,15 +1265,58 @@ tnrsvd_status tnrsvd_get_factor(tnrsvd_t h, int b, int which, int core, const vo
   return TNRSVD_OK;
 }
 
+// core index of the library's layout for the caller's core `core` of MPO b
+static int lib_core(tnrsvd_t h, int b, int core) {
+  if (h->orientation != TNRSVD_K_FIRST || b < 0 || b >= h->batch) return core;
+  return h->mh[b].d - 1 - core;
+}
+
+extern "C" {
+
+tnrsvd_status tnrsvd_get_factor(tnrsvd_t h, int b, int which, int core, const void** dev_ptr,
+                                int64_t shape[4], int* dtype) {
+  TRY(check_handle(h));
+  if (!dev_ptr || !shape || !dtype) return fail(TNRSVD_E_INVALID, "null output pointer");
+  TRY(get_factor_lib(h, b, which, lib_core(h, b, core), dev_ptr, shape, dtype));
+  if (h->orientation == TNRSVD_K_FIRST) {
+    std::swap(shape[0], shape[2]);
+    *dev_ptr = nullptr;
+  }
+  return TNRSVD_OK;
+}
+
 tnrsvd_status tnrsvd_copy_factor(tnrsvd_t h, int b, int which, int core, void* dst) {
   const void* src = nullptr;
   int64_t shape[4];
   int dt = 0;
-  TRY(tnrsvd_get_factor(h, b, which, core, &src, shape, &dt));
+  TRY(check_handle(h));
+  TRY(get_factor_lib(h, b, which, lib_core(h, b, core), &src, shape, &dt));
   if (!dst) return fail(TNRSVD_E_INVALID, "null destination");
-  const size_t bytes = (size_t)(shape[0] * shape[1] * shape[2]) * elem_size(dt);
-  TRY(dev_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream),
-                "copy factor"));
+  if (h->orientation == TNRSVD_K_FIRST) {
+    // the mode index of the merged core lists the caller's digits in reverse
+    const MpoDesc& md = h->mh[b];
+    const int lc = lib_core(h, b, core), m = lc == md.d - 1 ? h->mcount[b] : 1;
+    const bool cols = which == 1 || (which == 2 && h->space != kRow);
+    const auto& ps = h->paper_shape[b];
+    Radices rad{};
+    for (int j = 0; j < m; ++j) {   // library core d - m + j is the caller's core m - 1 - j
+      const int64_t r = m == 1 ? shape[1] : ps[m - 1 - j][cols ? 2 : 1];
+      if (r > 1) {
+        if (rad.nd == Radices::kMax) return fail(TNRSVD_E_SHAPE, "too many merged digits");
+        rad.r[rad.nd++] = r;
+      }
+    }
+    for (int k = rad.nd - 1; k >= 0; --k)
+      rad.below[k] = k == rad.nd - 1 ? 1 : rad.below[k + 1] * rad.r[k + 1];
+    if ((rad.nd ? rad.below[0] * rad.r[0] : 1) != shape[1])
+      return fail(TNRSVD_E_SHAPE, "merged digits do not match the core's mode size");
+    TRY(dev_check(launch_reverse_core(src, dt, dst, shape[0], shape[1], shape[2], rad, h->stream),
+                  "reverse factor"));
+  } else {
+    const size_t bytes = (size_t)(shape[0] * shape[1] * shape[2]) * elem_size(dt);
+    TRY(dev_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream),
+                  "copy factor"));
+  }
   return dev_check(hipStreamSynchronize(h->stream), "synchronise");
 }
 

@@ -119,6 +119,18 @@ hipError_t launch_merge_pair(const double* Tin, const double* C, double* out, in
 hipError_t launch_convert_core(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
                                hipStream_t s);
 hipError_t launch_check_finite(const void* in, int dtype, int64_t n, int* flag, hipStream_t s);
+// digits of a merged mode index, least significant first; below[k] is the
+// product of r[k+1..nd-1] (the digit's weight once the order is reversed)
+struct Radices {
+  static constexpr int kMax = 32;
+  int64_t r[kMax];
+  int64_t below[kMax];
+  int nd;
+};
+hipError_t launch_reverse_core(const void* in, int dtype, void* out, int64_t R0, int64_t n,
+                               int64_t R1, const Radices& rad, hipStream_t s);
+hipError_t launch_swap_legs(const void* in, int dtype, void* out, int64_t R0, int64_t I, int64_t J,
+                            int64_t R1, hipStream_t s);
 hipError_t launch_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch, uint64_t seed,
                         double* om, int64_t max_len, hipStream_t s);
 hipError_t launch_load_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch,

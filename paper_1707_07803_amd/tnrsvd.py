@@ -58,7 +58,12 @@ class _Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("p", ctypes.c_int), ("q", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int),
                 ("round_tol", ctypes.c_double), ("max_rank", ctypes.c_int64),
-                ("check_finite", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("check_finite", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("orientation", ctypes.c_int)]
+
+# where the K leg of Omega, Y, Q, U and V sits: "k_last" is the library's own
+# layout, "k_first" the paper's (Sec. 5), reached by reading the MPO reversed
+ORIENTATIONS = {"k_last": 0, "k_first": 1}
 
 
 _lib = None
@@ -135,11 +140,13 @@ class TNrSVD:
     mpos: list of MPOs, each a list of device tensors (R, I, J, R') in float64
     or float32 (C-contiguous).  The cores are copied (and the trailing ones
     merged) inside the library, so the tensors may be freed afterwards.
+    orientation "k_first" returns factors in the paper's layout (K leg on
+    core 0, leading cores merged); ranks() and factor() follow it.
     """
 
     def __init__(self, mpos, k: int, p: int = 0, q: int = 0, seed: int = 0,
                  precision: str = "f64", round_tol: float = 0.0, max_rank: int = 0,
-                 check_finite: bool = False, stream=None):
+                 check_finite: bool = False, stream=None, orientation: str = "k_last"):
         import torch
         L = load_library()
         if isinstance(mpos[0], torch.Tensor):
@@ -181,7 +188,9 @@ class TNrSVD:
         opts = _Opts(k=k, p=p, q=q, seed=seed, precision=PRECISIONS[precision],
                      round_tol=float(round_tol), max_rank=int(max_rank),
                      check_finite=1 if check_finite else 0,
-                     stream=ctypes.c_void_p(stream.cuda_stream))
+                     stream=ctypes.c_void_p(stream.cuda_stream),
+                     orientation=ORIENTATIONS[orientation])
+        self.orientation = orientation
         h = ctypes.c_void_p()
         _check(L.tnrsvd_create(ctypes.byref(h), self.batch, structs, ctypes.byref(opts)))
         self._h = h

@@ -81,3 +81,31 @@ def test_sparse_to_mpo_rejects_bad_arguments_on_the_host(lib):
                    (ctypes.c_void_p * 2)(8, 8), None), -2))
     for args, want in cases:
         assert f(*args) == want, args
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of tnrsvd_opts and tnrsvd_mpo have the C layout
+    (size and every field offset), as a C compiler lays them out."""
+    import shutil
+    import subprocess
+    from paper_1707_07803_amd import tnrsvd as binding
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"tnrsvd_opts": binding._Opts, "tnrsvd_mpo": binding._Mpo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tnrsvd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py)
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
