@@ -759,7 +759,8 @@ def round_mpo(cores: Sequence[np.ndarray], eps: float, rmax: int = 0) -> List[np
     delta = eps |A|_F / sqrt(d - 1); the last core keeps the remaining factor
     (Q R of its final QR).  Returns cores (r, I, J, r'), cores 1..d-1
     left-orthonormal with sign-fixed singular vectors.  Reading taken for the
-    zero matrix (the paper does not treat it): all-zero rank-1 cores.
+    zero matrix (the paper does not treat it): all-zero rank-1 cores, whether
+    every core is zero or only their product (|A|_F = 0 after the first pass).
     """
     d = len(cores)
     dims = [(c.shape[1], c.shape[2]) for c in cores]
@@ -768,6 +769,9 @@ def round_mpo(cores: Sequence[np.ndarray], eps: float, rmax: int = 0) -> List[np
     C = [np.asarray(c, dtype=np.float64).reshape(c.shape[0], c.shape[1] * c.shape[2], c.shape[3])
          for c in cores]
     out = round_sweep(C, eps, rmax, last="qr")
+    if out["norm"] == 0.0:
+        # a zero product of nonzero cores (e.g. one zero core): the same reading
+        return [np.zeros((1, I, J, 1)) for (I, J) in dims]
     res = out["cores"]
     res[-1] = np.tensordot(res[-1], out["R"], axes=(2, 0))
     return [c.reshape(c.shape[0], I, J, c.shape[2]) for c, (I, J) in zip(res, dims)]

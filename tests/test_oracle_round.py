@@ -103,3 +103,13 @@ def test_single_core_and_zero_matrix():
     Z = [np.zeros((1, 2, 2, 3)), np.zeros((3, 2, 2, 1))]
     R = o.round_mpo(Z, 1e-3)
     assert [c.shape for c in R] == [(1, 2, 2, 1), (1, 2, 2, 1)] and not any(np.any(c) for c in R)
+
+
+def test_zero_product_of_nonzero_cores_rounds_to_zero_cores():
+    """The zero-matrix reading also covers a product that vanishes because
+    one core is zero while the others are not."""
+    rng = np.random.default_rng(12)
+    C = [rng.standard_normal(s) for s in [(1, 2, 3, 3), (3, 2, 3, 3), (3, 2, 3, 3), (3, 2, 3, 1)]]
+    C[2] = np.zeros_like(C[2])
+    R = o.round_mpo(C, 1e-8)
+    assert [x.shape for x in R] == [(1, 2, 3, 1)] * 4 and not any(np.any(x) for x in R)

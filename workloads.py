@@ -29,6 +29,10 @@ duplicates merged (one entry per position, as a stored sparse matrix has):
                  (d = 7), bandwidth 200, ~4 entries per row, 115 far pairs
 * ``circuit150k`` 150102 x 150102, I = J = (1614, 31, 3) (d = 3), bandwidth
                  1962, s = 400, ~5 entries per row
+* ``hilbert(N)``  the 2^N x 2^(N-1) submatrix H(:, 1:2^(N-1)) of the Hilbert
+                 matrix (Sec. 6.3), 10 <= N <= 50: an MPO of N cores (2 x 2,
+                 the last 2 x 1) from an exponential sum for 1/x; rank-16
+                 approximation, K = 16+16, q = 2 (N <= 30), 3 (N <= 40), 4
 * ``power16k_stencil``, ``circuit150k_stencil``  the same sizes and
                  partitions with a fixed stencil (every row has its entries at
                  the same offsets with the same values, cut at the matrix
@@ -47,7 +51,7 @@ __all__ = ["Workload", "random_mpo", "gaussian_omega", "orthonormal_mps",
            "known_spectrum_mpo", "small", "spectrum", "large", "batched",
            "grad", "get", "WORKLOADS", "SparseWorkload", "banded_sparse", "power16k",
            "circuit150k", "stencil_sparse", "power16k_stencil", "circuit150k_stencil",
-           "SPARSE_WORKLOADS", "ROUND_WORKLOADS"]
+           "SPARSE_WORKLOADS", "ROUND_WORKLOADS", "hilbert_mpo", "hilbert", "HILBERT_N"]
 
 
 @dataclass
@@ -264,3 +268,55 @@ def circuit150k_stencil() -> SparseWorkload:
 
 ROUND_WORKLOADS = {"power16k_stencil": power16k_stencil,
                    "circuit150k_stencil": circuit150k_stencil, "power16k": power16k}
+
+
+# ------------------------------------------------------------------ Hilbert
+
+def hilbert_mpo(N: int, h: float = 0.3, tail: float = 1e-14) -> List[np.ndarray]:
+    """MPO of the 2^N x 2^(N-1) matrix A(i, j) = 1 / (i + j + 1) (0-based i, j:
+    the first 2^(N-1) columns of the Hilbert matrix), N cores with the
+    little-endian index of eq. (1): core k carries bit k of i and of j, and the
+    last core has J = 1 (bit N-1 of j is 0).
+
+    Built from the integral 1/x = int_R exp(t - x e^t) dt (x > 0), taken by the
+    trapezoidal rule with step h: 1/x ~ sum_l w_l exp(-a_l x), a_l = e^(t_l),
+    w_l = h e^(t_l), over t_l in [ln(tail / X), ln(-ln tail)] with X the largest
+    x.  The integrand is analytic in the strip |Im t| < pi/2, so the rule's
+    relative error is about exp(-pi^2 / h) (5e-15 at h = 0.3); the cut tails add
+    at most `tail` relative.  With x = 1 + sum_k 2^k (i_k + j_k) each term is a
+    Kronecker product of 2 x 2 factors exp(-a_l 2^k (i_k + j_k)), so the sum is an
+    MPO whose rank is the number of nodes (about 140 at N = 10, 240 at N = 50),
+    with diagonal cores.  Rounding brings it to the small ranks the matrix has.
+    """
+    if N < 2:
+        raise ValueError("N >= 2")
+    X = 2.0 ** N + 2.0 ** (N - 1) - 1.0
+    t0, t1 = np.log(tail / X), np.log(-np.log(tail))
+    t = np.arange(np.floor(t0 / h), np.ceil(t1 / h) + 1) * h
+    a, w = np.exp(t), h * np.exp(t)
+    R = a.size
+    cores = []
+    for k in range(N):
+        J = 1 if k == N - 1 else 2
+        f = np.exp(-np.multiply.outer(a * 2.0 ** k, np.add.outer(np.arange(2), np.arange(J))))
+        if k == 0:
+            c = (f * (w * np.exp(-a))[:, None, None]).transpose(1, 2, 0)[None]
+        elif k == N - 1:
+            c = f[:, :, :, None]
+        else:
+            c = np.zeros((R, 2, J, R))
+            c[np.arange(R), :, :, np.arange(R)] = f
+        cores.append(np.ascontiguousarray(c))
+    return cores
+
+
+HILBERT_N = (10, 15, 20, 25, 30, 35, 40, 45, 50)
+HILBERT_MPO_TOL = 1e-12   # rounding of the exponential-sum MPO (the paper's MPO: 1e-11)
+
+
+def hilbert(N: int) -> Workload:
+    """The Hilbert experiment of Sec. 6.3 at size N: rank 16 (K = 32), rounding
+    tolerance 1e-9, q by N as in the paper.  ``cores`` is the unrounded
+    exponential-sum MPO; it is rounded at HILBERT_MPO_TOL before the solve."""
+    q = 2 if N <= 30 else (3 if N <= 40 else 4)
+    return Workload(f"hilbert{N}", hilbert_mpo(N), k=16, p=16, q=q, eps=1e-9, omega_seed=70 + N)
