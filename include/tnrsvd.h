@@ -384,6 +384,31 @@ tnrsvd_status tnrsvd_sparse_round(int d, const int64_t* rows, const int64_t* col
                                   const int64_t* coo_row, const int64_t* coo_col,
                                   const double* coo_val, double round_tol, int max_rank,
                                   void* stream, tnrsvd_rounded_t* out);
+/*
+ * tnrsvd_round_mpo -- SVD-based rounding (Sec. 3) of any MPO a (device cores
+ * (r, I, J, r'), FP64 or FP32; FP32 is widened, all arithmetic is FP64).
+ * Core k is read as the (r_k) x (I_k J_k) x (r_{k+1}) core of an MPS (row
+ * and column index grouped, the row index slower).  Right to left, the LQ
+ * of each core k >= 2 (QR with diag(R) >= 0 of its transpose) leaves it with
+ * orthonormal rows and L goes into the left neighbour; then
+ * delta = round_tol |A|_F / sqrt(d - 1) and, left to right, the truncated SVD
+ * of the carried factor times core k keeps the smallest rank whose
+ * discarded singular values have squared sum <= delta^2 (capped at max_rank
+ * when > 0); left vectors are sign-fixed (largest-magnitude entry positive)
+ * and the last core carries the rest.  The result is left-orthonormal, and
+ * the rounded matrix is within round_tol |A|_F of A in Frobenius norm.  The
+ * zero matrix (|A|_F = 0) gives all-zero rank-1 cores; d = 1 gives the core.
+ * a is read only; the call allocates its own workspace, frees it, and
+ * synchronises `stream` (hipStream_t, NULL: null stream).  Limits: ranks up to
+ * 4096, and r I J and I J r' below 2^31 for every core.
+ * *out receives a handle owning the rounded cores, read with
+ * tnrsvd_rounded_ranks / tnrsvd_rounded_copy, freed by tnrsvd_rounded_destroy.
+ * Errors: E_INVALID (null argument, dtype, round_tol negative or not finite,
+ * max_rank < 0); E_SHAPE (rank[0] or rank[d] not 1, a bad or too large
+ * core); E_NOMEM; E_DEVICE.
+ */
+tnrsvd_status tnrsvd_round_mpo(const tnrsvd_mpo* a, double round_tol, int max_rank, void* stream,
+                               tnrsvd_rounded_t* out);
 tnrsvd_status tnrsvd_rounded_ranks(tnrsvd_rounded_t r, int64_t* ranks);
 tnrsvd_status tnrsvd_rounded_copy(tnrsvd_rounded_t r, int k, double* dst);
 tnrsvd_status tnrsvd_rounded_destroy(tnrsvd_rounded_t r);

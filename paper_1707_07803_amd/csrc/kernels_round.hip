@@ -263,34 +263,17 @@ __global__ void k_apply_sign(double* X, int64_t n1, int rho, double* T, int N, c
 
 // ------------------------------------------------------------ small panels
 
-// One core k of the left-to-right truncation (1 < k < d).  T (rp x cp,
-// row-major) is the carried factor; column c of it belongs to class c of the
-// orthogonalised selection core, whose single unit entry sits at mode index
-// pm[c] and right class nx[c] (an injective map, so the panel is a scatter):
-//   M[(a n + pm[c]), nx[c]] = T[a, c],   M is (rp n) x q.
-// Truncated SVD of M (QR first when it is taller than wide), rank by the tail
-// rule, left vectors sign-fixed (largest-magnitude entry positive), core =
-// those vectors (row-major (rp n) x rho), Tn = diag(sig) V^T with the same
-// signs (rho x q).
-__global__ __launch_bounds__(NT) void k_round_level(const double* T, int rp, int cp, const int* pm,
-                                                    const int* nx, int n, int q,
-                                                    const double* delta_p, int rmax, double* M,
-                                                    double* ws, double* tau, double* B, double* U,
-                                                    double* nrm, double* sig, int* perm,
-                                                    double* sgn, int* flag, double* Y,
-                                                    double* core, double* Tn, int* rho_out) {
-  __shared__ double arena[AR];
-  __shared__ int srho;
+// Truncated SVD of the nv x q column-major panel M (rows: carried rank x
+// mode, columns: the next bond): QR first when it is taller than wide, then
+// one-sided Jacobi, rank by the tail rule, left vectors sign-fixed (largest-
+// magnitude entry positive).  core = those vectors (row-major nv x rho), Tn =
+// diag(sig) V^T with the same signs (row-major rho x q); *rho_out = rho.
+__device__ void panel_svd(double* M, int64_t nv, int q, double delta, int rmax, double* ws,
+                          double* tau, double* B, double* U, double* nrm, double* sig, int* perm,
+                          double* sgn, int* flag, double* Y, double* core, double* Tn,
+                          int* rho_out, double* arena, int* srho_s) {
   const int tid = threadIdx.x;
-  const int64_t nv = (int64_t)rp * n;
-  const double delta = delta_p[0];
-  for (int64_t e = tid; e < nv * q; e += NT) M[e] = 0.0;
-  __syncthreads();
-  for (int64_t e = tid; e < (int64_t)rp * cp; e += NT) {
-    const int64_t a = e / cp, c = e % cp;
-    M[(int64_t)nx[c] * nv + a * n + pm[c]] = T[e];
-  }
-  __syncthreads();
+  int& srho = *srho_s;
   const bool tall = nv > q;
   const int nvv = tall ? q : (int)nv;   // Jacobi vectors: rows of R, or rows of M
   if (tall) {
@@ -334,6 +317,35 @@ __global__ __launch_bounds__(NT) void k_round_level(const double* T, int rp, int
   }
 }
 
+// One core k of the left-to-right truncation (1 < k < d).  T (rp x cp,
+// row-major) is the carried factor; column c of it belongs to class c of the
+// orthogonalised selection core, whose single unit entry sits at mode index
+// pm[c] and right class nx[c] (an injective map, so the panel is a scatter):
+//   M[(a n + pm[c]), nx[c]] = T[a, c],   M is (rp n) x q,
+// then its truncated SVD (panel_svd).
+__global__ __launch_bounds__(NT) void k_round_level(const double* T, int rp, int cp, const int* pm,
+                                                    const int* nx, int n, int q,
+                                                    const double* delta_p, int rmax, double* M,
+                                                    double* ws, double* tau, double* B, double* U,
+                                                    double* nrm, double* sig, int* perm,
+                                                    double* sgn, int* flag, double* Y,
+                                                    double* core, double* Tn, int* rho_out) {
+  __shared__ double arena[AR];
+  __shared__ int srho;
+  const int tid = threadIdx.x;
+  const int64_t nv = (int64_t)rp * n;
+  const double delta = delta_p[0];
+  for (int64_t e = tid; e < nv * q; e += NT) M[e] = 0.0;
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)rp * cp; e += NT) {
+    const int64_t a = e / cp, c = e % cp;
+    M[(int64_t)nx[c] * nv + a * n + pm[c]] = T[e];
+  }
+  __syncthreads();
+  panel_svd(M, nv, q, delta, rmax, ws, tau, B, U, nrm, sig, perm, sgn, flag, Y, core, Tn, rho_out,
+            arena, &srho);
+}
+
 // The last core: core[a n + pm[c]] = T[a, c] (row-major rp x n), zero elsewhere.
 __global__ __launch_bounds__(NT) void k_round_last(const double* T, int rp, int cp, const int* pm,
                                                    int n, double* core) {
@@ -343,6 +355,78 @@ __global__ __launch_bounds__(NT) void k_round_last(const double* T, int rp, int 
     const int64_t a = e / cp, c = e % cp;
     core[a * n + pm[c]] = T[e];
   }
+}
+
+// ------------------------------------------------- rounding of any MPO
+
+// Right-to-left step at core k >= 1 of the rounding of a general MPO: the LQ
+// of core k (r rows, m = n r' columns, row-major) as the QR with diag(R) >= 0
+// of its transpose X (m x r column-major: the same memory), rk = min(m, r).
+// Q (rk x m row-major) = the first rk columns of the QR's Q, transposed: the
+// new core k, with orthonormal rows.  Gpo (pn x rk) = Gp (pn x r) R^T: the
+// previous core with L = R^T absorbed.
+__global__ __launch_bounds__(NT) void k_lq_absorb(const double* G, int r, int m, const double* Gp,
+                                                  int pn, double* X, double* tau, double* ws,
+                                                  double* Rt, double* Q, double* Gpo) {
+  __shared__ double arena[AR];
+  const int tid = threadIdx.x;
+  const int rk = m < r ? m : r;
+  for (int64_t e = tid; e < (int64_t)m * r; e += NT) X[e] = G[e];
+  __syncthreads();
+  wg_qr(X, m, r, m, tau, ws, arena);
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)r * rk; e += NT) {   // Rt[b][c] = R[c][b]
+    const int64_t b = e / rk, c = e % rk;
+    Rt[e] = c <= b ? X[b * m + c] : 0.0;
+  }
+  for (int64_t e = tid; e < (int64_t)m * rk; e += NT) Q[e] = (e % m) == (e / m) ? 1.0 : 0.0;
+  __syncthreads();
+  wg_apply_q(X, tau, m, rk, Q, rk, m);
+  __syncthreads();
+  wg_gemm<double>(pn, rk, r, 1.0, Gp, r, 1, Rt, rk, 1, 0.0, Gpo, rk, 1, arena);
+}
+
+// |G|_F of the first core after the right-to-left pass (= |A|_F) and the
+// truncation threshold delta = eps |A|_F / sqrt(d - 1): out[0] = delta, out[1] = |A|_F.
+__global__ __launch_bounds__(NT) void k_norm_delta(const double* G, int64_t len, double eps,
+                                                   int dm1, double* out) {
+  __shared__ double red[NW];
+  double part = 0.0;
+  for (int64_t e = threadIdx.x; e < len; e += NT) part += G[e] * G[e];
+  const double nrm = sqrt(block_sum(part, red));
+  if (threadIdx.x == 0) {
+    out[0] = dm1 > 0 ? eps * nrm / sqrt((double)dm1) : 0.0;
+    out[1] = nrm;
+  }
+}
+
+// Left-to-right step at core k < d - 1: the panel M = T (s x r) times core k
+// (r x n q), reshaped (s n) x q column-major, then its truncated SVD.
+__global__ __launch_bounds__(NT) void k_round_step(const double* T, int s, int r, const double* G,
+                                                   int n, int q, const double* delta_p, int rmax,
+                                                   double* Mr, double* M, double* ws, double* tau,
+                                                   double* B, double* U, double* nrm, double* sig,
+                                                   int* perm, double* sgn, int* flag, double* Y,
+                                                   double* core, double* Tn, int* rho_out) {
+  __shared__ double arena[AR];
+  __shared__ int srho;
+  const int64_t nq = (int64_t)n * q, nv = (int64_t)s * n;
+  wg_gemm<double>(s, (int)nq, r, 1.0, T, r, 1, G, nq, 1, 0.0, Mr, nq, 1, arena);
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < nv * q; e += NT) {
+    const int64_t p = e / q, c = e % q;
+    M[c * nv + p] = Mr[e];
+  }
+  __syncthreads();
+  panel_svd(M, nv, q, delta_p[0], rmax, ws, tau, B, U, nrm, sig, perm, sgn, flag, Y, core, Tn,
+            rho_out, arena, &srho);
+}
+
+// The last core takes the carried factor: out (s x n) = T (s x r) G (r x n).
+__global__ __launch_bounds__(NT) void k_absorb_last(const double* T, int s, int r, const double* G,
+                                                    int n, double* out) {
+  __shared__ double arena[GEMM_LDS];
+  wg_gemm<double>(s, n, r, 1.0, T, r, 1, G, n, 1, 0.0, out, n, 1, arena);
 }
 
 }  // namespace
@@ -409,6 +493,124 @@ hipError_t launch_round_last(const double* T, int rp, int cp, const int* pm, int
                              hipStream_t s) {
   k_round_last<<<1, NT, 0, s>>>(T, rp, cp, pm, n, core);
   return hipGetLastError();
+}
+
+// SVD-based rounding (Sec. 3) of a general MPO: right-to-left LQ of cores
+// d..2 with each L absorbed into the left neighbour (k_lq_absorb), delta from
+// the first core's norm, then left-to-right truncated SVDs of the carried
+// factor times each core (k_round_step); the last core takes the remaining
+// factor.  One workgroup per step; each step's rank is read back to size the
+// next.  The zero matrix (|A|_F = 0 after the first pass) gives zero rank-1
+// cores.
+hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t* J,
+                     const double* const* cores, double eps, int rmax, RoundedMpo* out,
+                     hipStream_t s) {
+  DevArena A;
+  hipError_t e = hipSuccess;
+  std::vector<double*> res(d, nullptr);
+  out->ranks.assign(d + 1, 1);
+  out->cores.assign(d, nullptr);
+  auto finish = [&]() {
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < d; ++k) {
+      A.release(res[k]);
+      out->cores[k] = res[k];
+    }
+    return hipSuccess;
+  };
+  auto read_back = [&](void* host, const void* dev, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  };
+  std::vector<int64_t> n(d), rr(rank, rank + d + 1);
+  for (int k = 0; k < d; ++k) n[k] = I[k] * J[k];
+  // working copies: W[k] is (rr[k], n[k], rr[k+1]) row-major
+  std::vector<const double*> W(cores, cores + d);
+  for (int k = d - 1; k >= 1 && e == hipSuccess; --k) {
+    const int64_t r = rr[k], m = n[k] * rr[k + 1], rk = m < r ? m : r, pn = rr[k - 1] * n[k - 1];
+    double* X = A.get<double>(m * r);
+    double* tau = A.get<double>(r);
+    double* ws = A.get<double>(qr_ws_doubles(m, r));
+    double* Rt = A.get<double>(r * rk);
+    double* Q = A.get<double>(rk * m);
+    double* Gpo = A.get<double>(pn * rk);
+    if ((e = A.e) != hipSuccess) break;
+    k_lq_absorb<<<1, NT, 0, s>>>(W[k], (int)r, (int)m, W[k - 1], (int)pn, X, tau, ws, Rt, Q, Gpo);
+    e = hipGetLastError();
+    W[k] = Q;
+    W[k - 1] = Gpo;
+    rr[k] = rk;
+  }
+  double* dl = A.get<double>(2);
+  if (e == hipSuccess) e = A.e;
+  if (e == hipSuccess) {
+    k_norm_delta<<<1, NT, 0, s>>>(W[0], n[0] * rr[1], eps, d - 1, dl);
+    e = hipGetLastError();
+  }
+  double hd[2] = {0.0, 0.0};
+  read_back(hd, dl, sizeof(hd));
+  if (e != hipSuccess) return e;
+  if (hd[1] == 0.0) {   // the zero matrix
+    for (int k = 0; k < d && e == hipSuccess; ++k) {
+      res[k] = A.get<double>(n[k]);
+      if ((e = A.e) == hipSuccess) e = hipMemsetAsync(res[k], 0, sizeof(double) * n[k], s);
+    }
+    return finish();
+  }
+  if (d == 1) {   // a single core is the matrix itself
+    res[0] = A.get<double>(n[0]);
+    if ((e = A.e) == hipSuccess)
+      e = hipMemcpyAsync(res[0], W[0], sizeof(double) * n[0], hipMemcpyDeviceToDevice, s);
+    return finish();
+  }
+  double* one = A.get<double>(1);
+  int* flag = A.get<int>(4);
+  int* rho_d = A.get<int>(d + 1);
+  if ((e = A.e) != hipSuccess) return e;
+  const double h_one = 1.0;
+  e = hipMemcpyAsync(one, &h_one, sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 4 * sizeof(int), s);
+  const double* T = one;
+  int64_t sr = 1;   // rows of T (the kept rank so far)
+  for (int k = 0; k < d - 1 && e == hipSuccess; ++k) {
+    const int64_t r = rr[k], q = rr[k + 1], nv = sr * n[k];
+    const int64_t mn = nv < q ? nv : q;
+    const int64_t cap = (rmax > 0 && rmax < mn) ? rmax : mn;
+    double* Mr = A.get<double>(nv * q);
+    double* M = A.get<double>(nv * q);
+    double* ws = A.get<double>(qr_ws_doubles(nv, q));
+    double* tau = A.get<double>(q);
+    double* B = A.get<double>(nv * q);
+    double* U = A.get<double>(mn * mn);
+    double* nrm = A.get<double>(mn);
+    double* sig = A.get<double>(mn);
+    int* perm = A.get<int>(mn);
+    double* sgn = A.get<double>(cap);
+    double* Y = A.get<double>(nv * cap);
+    res[k] = A.get<double>(nv * cap);
+    double* Tn = A.get<double>(cap * q);
+    if ((e = A.e) != hipSuccess) break;
+    k_round_step<<<1, NT, 0, s>>>(T, (int)sr, (int)r, W[k], (int)n[k], (int)q, dl, rmax, Mr, M, ws,
+                                  tau, B, U, nrm, sig, perm, sgn, flag, Y, res[k], Tn,
+                                  rho_d + k + 1);
+    e = hipGetLastError();
+    int rk = 0;
+    read_back(&rk, rho_d + k + 1, sizeof(int));
+    if (e != hipSuccess) break;
+    out->ranks[k + 1] = rk;
+    T = Tn;
+    sr = rk;
+  }
+  if (e == hipSuccess) {
+    res[d - 1] = A.get<double>(sr * n[d - 1]);
+    if ((e = A.e) == hipSuccess) {
+      k_absorb_last<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[d - 1], W[d - 1], (int)n[d - 1],
+                                     res[d - 1]);
+      e = hipGetLastError();
+    }
+  }
+  return finish();
 }
 
 }  // namespace tnr

@@ -555,28 +555,6 @@ hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
 
 namespace {
 
-// Device allocations of one call, freed together except those released.
-struct DevArena {
-  std::vector<void*> ptrs;
-  hipError_t e = hipSuccess;
-  template <typename P>
-  P* get(int64_t count) {
-    if (e != hipSuccess) return nullptr;
-    void* p = nullptr;
-    e = hipMalloc(&p, sizeof(P) * (size_t)(count > 0 ? count : 1));
-    if (e != hipSuccess) return nullptr;
-    ptrs.push_back(p);
-    return (P*)p;
-  }
-  void release(const void* p) {
-    for (auto& q : ptrs)
-      if (q == p) q = nullptr;
-  }
-  ~DevArena() {
-    for (void* p : ptrs)
-      if (p) (void)hipFree(p);
-  }
-};
 
 // Prefix sums of the popcounts of the nw bitmap words into ws; *count = total.
 hipError_t scan_words(DevArena& A, const unsigned* bm, int* ws, int64_t nw, int* count,

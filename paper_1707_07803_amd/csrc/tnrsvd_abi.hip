@@ -1513,6 +1513,74 @@ tnrsvd_status tnrsvd_sparse_round(int d, const int64_t* rows, const int64_t* col
   return TNRSVD_OK;
 }
 
+tnrsvd_status tnrsvd_round_mpo(const tnrsvd_mpo* a, double round_tol, int max_rank, void* stream,
+                               tnrsvd_rounded_t* out) {
+  g_err.clear();
+  if (!out) return fail(TNRSVD_E_INVALID, "null out");
+  *out = nullptr;
+  if (!a) return fail(TNRSVD_E_INVALID, "null MPO");
+  if (a->d < 1) return fail(TNRSVD_E_SHAPE, "d must be >= 1");
+  if (!a->rank || !a->rows || !a->cols || !a->core)
+    return fail(TNRSVD_E_INVALID, "null rank/rows/cols/core array");
+  if (a->dtype != TNRSVD_F64 && a->dtype != TNRSVD_F32)
+    return fail(TNRSVD_E_INVALID, "core dtype must be F64 or F32");
+  if (!(round_tol >= 0.0) || std::isinf(round_tol))
+    return fail(TNRSVD_E_INVALID, "round_tol must be finite and >= 0");
+  if (max_rank < 0) return fail(TNRSVD_E_INVALID, "max_rank must be >= 0");
+  const int d = a->d;
+  if (a->rank[0] != 1 || a->rank[d] != 1) return fail(TNRSVD_E_SHAPE, "rank[0] and rank[d] must be 1");
+  for (int k = 0; k < d; ++k) {
+    const int64_t r0 = a->rank[k], n = a->rows[k] * a->cols[k], r1 = a->rank[k + 1];
+    if (r0 < 1 || r1 < 1 || a->rows[k] < 1 || a->cols[k] < 1 || !a->core[k])
+      return fail(TNRSVD_E_SHAPE, "core %d: bad shape or null pointer", k);
+    if (r0 > kRoundRankMax || r1 > kRoundRankMax || a->rows[k] > INT32_MAX ||
+        a->cols[k] > INT32_MAX || n * r1 > INT32_MAX || r0 * n > INT32_MAX)
+      return fail(TNRSVD_E_SHAPE, "core %d: ranks above %d or a panel above 2^31 entries", k,
+                  kRoundRankMax);
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  std::vector<const double*> c64(d);
+  std::vector<void*> conv;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : conv) (void)hipFree(p);
+  };
+  for (int k = 0; k < d; ++k) {
+    if (a->dtype == TNRSVD_F64) {
+      c64[k] = (const double*)a->core[k];
+      continue;
+    }
+    const int64_t len = a->rank[k] * a->rows[k] * a->cols[k] * a->rank[k + 1];
+    void* t = nullptr;
+    if (hipMalloc(&t, sizeof(double) * (size_t)len) != hipSuccess) {
+      (void)hipGetLastError();
+      return release(), fail(TNRSVD_E_NOMEM, "FP64 copy of core %d", k);
+    }
+    conv.push_back(t);
+    const hipError_t e = launch_convert_core(a->core[k], kF32, t, kF64, len, s);
+    if (e != hipSuccess) return release(), dev_check(e, "widen core");
+    c64[k] = (const double*)t;
+  }
+  RoundedMpo res;
+  const hipError_t e =
+      round_mpo(d, a->rank, a->rows, a->cols, c64.data(), round_tol, max_rank, &res, s);
+  release();
+  TRY(dev_check(e, "rounding"));
+  auto* r = new (std::nothrow) tnrsvd_rounded_s;
+  if (!r) {
+    for (double* p : res.cores) (void)hipFree(p);
+    return fail(TNRSVD_E_NOMEM, "host allocation");
+  }
+  r->d = d;
+  r->rows.assign(a->rows, a->rows + d);
+  r->cols.assign(a->cols, a->cols + d);
+  r->ranks = res.ranks;
+  r->cores = res.cores;
+  r->stream = s;
+  *out = r;
+  return TNRSVD_OK;
+}
+
 tnrsvd_status tnrsvd_rounded_ranks(tnrsvd_rounded_t r, int64_t* ranks) {
   if (!r || !ranks) return fail(TNRSVD_E_INVALID, "null argument");
   for (int k = 0; k <= r->d; ++k) ranks[k] = r->ranks[k];

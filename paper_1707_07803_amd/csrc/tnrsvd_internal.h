@@ -101,6 +101,7 @@ using elem_t = std::remove_const_t<std::remove_pointer_t<P>>;
 
 constexpr int kSweepThreads = 512;
 constexpr int kMaxK = 256;
+constexpr int kRoundRankMax = 4096;  // bond ranks taken by the rounding of a general MPO
 constexpr int kSweepArena = 19456;   // doubles of static LDS per sweep workgroup
 constexpr int kSortCap = 990;        // largest panel row count the sweep sorts
 
@@ -190,6 +191,29 @@ hipError_t launch_round_last(const double* T, int rp, int cp, const int* pm, int
 
 // Result of sparse_round: ranks (d + 1) and d device cores (C order (r, I, J, r')),
 // owned by the caller of sparse_round (hipFree each).
+// Device allocations of one call, freed together except those released.
+struct DevArena {
+  std::vector<void*> ptrs;
+  hipError_t e = hipSuccess;
+  template <typename P>
+  P* get(int64_t count) {
+    if (e != hipSuccess) return nullptr;
+    void* p = nullptr;
+    e = hipMalloc(&p, sizeof(P) * (size_t)(count > 0 ? count : 1));
+    if (e != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return (P*)p;
+  }
+  void release(const void* p) {
+    for (auto& q : ptrs)
+      if (q == p) q = nullptr;
+  }
+  ~DevArena() {
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
 struct RoundedMpo {
   std::vector<int64_t> ranks;
   std::vector<double*> cores;
@@ -199,6 +223,11 @@ struct RoundedMpo {
 hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, const int64_t* row,
                         const int64_t* col, const double* val, double eps, int rmax,
                         RoundedMpo* out, int* why, hipStream_t s);
+// SVD-based rounding (Sec. 3) of a general MPO with FP64 device cores
+// (r_k, I_k, J_k, r_{k+1}); the input cores are not modified.
+hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t* J,
+                     const double* const* cores, double eps, int rmax, RoundedMpo* out,
+                     hipStream_t s);
 hipError_t launch_merge_pair_bwd(const double* T, const double* C, const double* dN, double* dT,
                                  double* dC, int a, int I1, int J1, int r, int I2, int J2, int b,
                                  hipStream_t s);

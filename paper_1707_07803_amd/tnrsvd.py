@@ -27,7 +27,7 @@ EXPORTS = [
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
-    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_round", "tnrsvd_rounded_ranks",
+    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_rounded_ranks",
     "tnrsvd_rounded_copy", "tnrsvd_rounded_destroy", "tnrsvd_last_error", "tnrsvd_version",
 ]
 
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_sparse_round.argtypes = [I, P64, P64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, I,
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.tnrsvd_round_mpo.argtypes = [ctypes.POINTER(_Mpo), ctypes.c_double, I, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_void_p)]
     L.tnrsvd_rounded_ranks.argtypes = [ctypes.c_void_p, P64]
     L.tnrsvd_rounded_copy.argtypes = [ctypes.c_void_p, I, ctypes.c_void_p]
     L.tnrsvd_rounded_destroy.argtypes = [ctypes.c_void_p]
@@ -158,30 +160,9 @@ class TNrSVD:
         keep = []
         structs = (_Mpo * self.batch)()
         for b, cores in enumerate(mpos):
-            ds = {c.dtype for c in cores}
-            if len(ds) != 1 or next(iter(ds)) not in (torch.float64, torch.float32):
-                raise TNrSVDError(-1, "cores must all be float64 or all float32")
-            for c in cores:
-                if not c.is_cuda or not c.is_contiguous() or c.dim() != 4:
-                    raise TNrSVDError(-1, "cores must be contiguous 4-way device tensors")
-            d = len(cores)
-            rank = [int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores]
-            for i in range(1, d):
-                if int(cores[i].shape[0]) != rank[i]:
-                    raise TNrSVDError(-2, f"rank mismatch between cores {i - 1} and {i}")
-            rows = [int(c.shape[1]) for c in cores]
-            cols = [int(c.shape[2]) for c in cores]
-            ra = (ctypes.c_int64 * (d + 1))(*rank)
-            ro = (ctypes.c_int64 * d)(*rows)
-            co = (ctypes.c_int64 * d)(*cols)
-            pt = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
-            keep += [ra, ro, co, pt, cores]
-            structs[b].d = d
-            structs[b].rank = ra
-            structs[b].rows = ro
-            structs[b].cols = co
-            structs[b].core = pt
-            structs[b].dtype = F64 if cores[0].dtype == torch.float64 else F32
+            st, held = _mpo_struct(cores)
+            structs[b] = st
+            keep += held
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -432,18 +413,72 @@ def sparse_round(rows, cols, coo_row, coo_col, coo_val, round_tol: float, max_ra
     h = ctypes.c_void_p()
     _check(L.tnrsvd_sparse_round(d, rr, cc, nnz, *ptrs, float(round_tol), int(max_rank), stream,
                                  ctypes.byref(h)))
+    return _take_rounded(L, h, rows, cols, coo_val.device)
+
+
+def _take_rounded(L, h, rows, cols, device):
+    """Copy the cores of a rounded-MPO handle into new device tensors, then free it."""
+    import torch
+    d = len(rows)
     try:
         ranks = (ctypes.c_int64 * (d + 1))()
         _check(L.tnrsvd_rounded_ranks(h, ranks))
         cores = []
         for k in range(d):
             t = torch.empty((ranks[k], rows[k], cols[k], ranks[k + 1]), dtype=torch.float64,
-                            device=coo_val.device)
+                            device=device)
             _check(L.tnrsvd_rounded_copy(h, k, ctypes.c_void_p(t.data_ptr())))
             cores.append(t)
     finally:
         L.tnrsvd_rounded_destroy(h)
     return cores
+
+
+def round_mpo(cores, round_tol: float, max_rank: int = 0):
+    """SVD-based rounding (Sec. 3) of an MPO given as device tensors (r, I, J, r')
+    in float64 or float32, computed by tnrsvd_round_mpo on the current stream.
+
+    Returns float64 device tensors, the first d - 1 cores left-orthonormal.
+    """
+    import torch
+    L = load_library()
+    st, keep = _mpo_struct(cores)
+    h = ctypes.c_void_p()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(L.tnrsvd_round_mpo(ctypes.byref(st), float(round_tol), int(max_rank), stream,
+                              ctypes.byref(h)))
+    del keep
+    return _take_rounded(L, h, [int(c.shape[1]) for c in cores], [int(c.shape[2]) for c in cores],
+                         cores[0].device)
+
+
+def _mpo_struct(cores):
+    """A tnrsvd_mpo describing the device tensors ``cores`` (checked for shape,
+    dtype and layout); returns it with the arrays it points to."""
+    import torch
+    ds = {c.dtype for c in cores}
+    if len(ds) != 1 or next(iter(ds)) not in (torch.float64, torch.float32):
+        raise TNrSVDError(-1, "cores must all be float64 or all float32")
+    for c in cores:
+        if not c.is_cuda or not c.is_contiguous() or c.dim() != 4:
+            raise TNrSVDError(-1, "cores must be contiguous 4-way device tensors")
+    d = len(cores)
+    rank = [int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores]
+    for i in range(1, d):
+        if int(cores[i].shape[0]) != rank[i]:
+            raise TNrSVDError(-2, f"rank mismatch between cores {i - 1} and {i}")
+    ra = (ctypes.c_int64 * (d + 1))(*rank)
+    ro = (ctypes.c_int64 * d)(*[int(c.shape[1]) for c in cores])
+    co = (ctypes.c_int64 * d)(*[int(c.shape[2]) for c in cores])
+    pt = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+    st = _Mpo()
+    st.d = d
+    st.rank = ra
+    st.rows = ro
+    st.cols = co
+    st.core = pt
+    st.dtype = F64 if cores[0].dtype == torch.float64 else F32
+    return st, [ra, ro, co, pt, cores]
 
 
 def _autograd_function():

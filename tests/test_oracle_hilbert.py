@@ -49,7 +49,8 @@ def paper_sigma(P, W):
     om = wl.gaussian_omega(cols[: len(L) - m] + [int(np.prod(cols[len(L) - m:]))], W.K,
                            W.omega_seed)
     A1 = o.reverse_mpo(o.merge_tail(L, m))
-    return m, o.tnrsvd_paper_orientation(A1, W.k, W.p, W.q, om[1], om[0][::-1], eps=W.eps)
+    return m, o.tnrsvd_paper_orientation(A1, W.k, W.p, W.q, om[1], om[0][::-1], eps=W.eps,
+                                            rmax=W.rmax)
 
 
 def test_exponential_sum_matches_the_closed_form_densely():

@@ -317,6 +317,9 @@ HILBERT_MPO_TOL = 1e-12   # rounding of the exponential-sum MPO (the paper's MPO
 def hilbert(N: int) -> Workload:
     """The Hilbert experiment of Sec. 6.3 at size N: rank 16 (K = 32), rounding
     tolerance 1e-9, q by N as in the paper.  ``cores`` is the unrounded
-    exponential-sum MPO; it is rounded at HILBERT_MPO_TOL before the solve."""
+    exponential-sum MPO; it is rounded at HILBERT_MPO_TOL before the solve.
+    The rank cap 64 only bounds the planned capacity: the rounded ranks stay
+    below it (the paper caps nothing)."""
     q = 2 if N <= 30 else (3 if N <= 40 else 4)
-    return Workload(f"hilbert{N}", hilbert_mpo(N), k=16, p=16, q=q, eps=1e-9, omega_seed=70 + N)
+    return Workload(f"hilbert{N}", hilbert_mpo(N), k=16, p=16, q=q, eps=1e-9, rmax=64,
+                    omega_seed=70 + N)
