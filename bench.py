@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--sparse", choices=["on", "off", "only"], default="on",
                     help="time the sparse-to-MPO conversion (Algorithm 4.1) too / not / alone")
     ap.add_argument("--sparse-steps", type=int, default=20)
+    ap.add_argument("--hilbert", choices=["on", "off", "only"], default="on",
+                    help="the Hilbert experiment of Sec. 6.3 (round the MPO, then solve)")
+    ap.add_argument("--hilbert-steps", type=int, default=3)
     ap.add_argument("--batched-full", action="store_true",
                     help="time the whole 512-MPO uneven batch once (minutes) and exit")
     ap.add_argument("--no-configs", action="store_true",
@@ -303,7 +306,7 @@ def sparse_section(steps, cpu_baseline_on):
         o.sparse_to_mpo(w.coo_row, w.coo_col, w.coo_val, w.rows, w.cols)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(1e3 * dt, 1), "unit": "ms per conversion",
-                               "cores": 1, "kind": "oracle",
+                               "cores": 1, "kind": "oracle",   # numpy element work, no LAPACK
                                "sample": "one conversion of power16k (numpy, sum of rank-1 "
                                          "terms by MPO addition)"}
     out["paper_context"] = ("MATLAB on an i7-6700: 0.1396 s for a 16384 x 16384 power-network "
@@ -356,10 +359,77 @@ def rounding_section(steps, cpu_baseline_on):
         o.round_mpo(o.sparse_to_mpo(w.coo_row, w.coo_col, w.coo_val, w.rows, w.cols), 1e-10)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(1e3 * dt, 1), "unit": "ms per conversion + rounding",
-                               "kind": "oracle", "cores": 1,
+                               "kind": "oracle", "cores": blas_threads(),
                                "sample": "power16k_stencil: sparse_to_mpo then round_mpo (numpy)"}
     out["paper_context"] = ("SVD-based rounding of the d = 3 circuit MPO (rank 347 -> 7) took "
                             "about 61 s in MATLAB; the parallel-vector rounding about 5 s")
+    return out
+
+
+def hilbert_section(steps, cpu_baseline_on):
+    """The Hilbert experiment of Sec. 6.3 for N = 10..50: the 2^N x 2^(N-1)
+    submatrix's exponential-sum MPO is rounded on the device (tnrsvd_round_mpo,
+    tolerance 1e-12), then solved for rank 16 (K = 32, q = 2/3/4, rounding 1e-9)
+    in the paper's orientation (first 5 cores merged).  Times are medians of
+    `steps` calls with the MPO resident in HBM."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1707_07803_amd import TNrSVD, round_mpo
+
+    out = {}
+    for N in wl.HILBERT_N:
+        W = wl.hilbert(N)
+        A = [torch.as_tensor(c, device="cuda:0") for c in W.cores]
+        P = round_mpo(A, wl.HILBERT_MPO_TOL)
+        tr = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            R = round_mpo(A, wl.HILBERT_MPO_TOL)
+            torch.cuda.synchronize()
+            tr.append(time.perf_counter() - t0)
+            del R
+        h = TNrSVD(P, W.k, W.p, W.q, seed=N, round_tol=W.eps, max_rank=W.rmax,
+                   orientation="k_first")
+        sig = h.run()[0]
+        ts = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sig = h.run()[0]
+            ts.append(time.perf_counter() - t0)
+        out[f"N={N}"] = {"matrix": f"2^{N} x 2^{N - 1}", "q": W.q,
+                         "mpo_rank_before": int(W.cores[0].shape[3]),
+                         "mpo_ranks_after_max": max(int(c.shape[3]) for c in P[:-1]),
+                         "merged_cores": N - h.d_merged() + 1,
+                         "ms_round": round(1e3 * float(np.median(tr)), 3),
+                         "ms_solve": round(1e3 * float(np.median(ts)), 3),
+                         "basis_ranks_max": max(h.ranks()[1:]),
+                         "sigma_1": float(sig[0]), "sigma_16": float(sig[15])}
+        print(f"[bench] hilbert N={N}: round {out[f'N={N}']['ms_round']} ms, "
+              f"solve {out[f'N={N}']['ms_solve']} ms", file=sys.stderr, flush=True)
+        h.close()
+        del A, P
+        torch.cuda.empty_cache()
+    if cpu_baseline_on:
+        from oracle import tnrsvd_oracle as o
+        N = 30
+        W = wl.hilbert(N)
+        t0 = time.perf_counter()
+        Pn = o.round_mpo(W.cores, wl.HILBERT_MPO_TOL)
+        L = o.reverse_mpo(Pn)
+        m = o.merge_plan([c.shape[1] for c in L], [c.shape[2] for c in L], W.K)
+        cols = [c.shape[2] for c in L]
+        om = wl.gaussian_omega(cols[: len(L) - m] + [int(np.prod(cols[len(L) - m:]))], W.K, N)
+        o.tnrsvd_paper_orientation(o.reverse_mpo(o.merge_tail(L, m)), W.k, W.p, W.q, om[1],
+                                   om[0][::-1], eps=W.eps, rmax=W.rmax)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1e3 * dt, 1), "unit": "ms per round + solve",
+                               "kind": "oracle", "cores": blas_threads(),
+                               "sample": "N = 30: round_mpo then tnrsvd_paper_orientation (numpy)"}
+    out["paper_context"] = ("MATLAB on an i7-6700: a dense rSVD of the same matrix took 0.04 s "
+                            "(N = 10) and 9.79 s (N = 15); TNrSVD timings are plotted only")
     return out
 
 
@@ -414,14 +484,19 @@ def measured_traffic(precision):
     return blob["read_bytes_per_launch"] + blob["write_bytes_per_launch"]
 
 
+def blas_threads():
+    """Threads the oracle's numpy/LAPACK calls may use."""
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(W, eps, budget):
     import numpy as np
     from oracle import tnrsvd_oracle as o
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    threads = blas_threads()
     n = 0
     t0 = time.perf_counter()
     sig = None
@@ -478,6 +553,12 @@ def main():
         sparse = sparse_section(args.sparse_steps, not args.no_cpu_baseline)
         if args.sparse == "only":
             print(json.dumps({"sparse_to_mpo": sparse, "device": device}))
+            return
+    hilbert = None
+    if args.hilbert != "off":
+        hilbert = hilbert_section(args.hilbert_steps, not args.no_cpu_baseline)
+        if args.hilbert == "only":
+            print(json.dumps({"hilbert": hilbert, "device": device}))
             return
     W = wl.spectrum()
     precs = args.precisions.split(",")
@@ -596,6 +677,7 @@ def main():
         "contraction": contraction,
         "batched": batched,
         "sparse_to_mpo": sparse,
+        "hilbert": hilbert,
         "other_configs": configs,
         "kernel_avg_ms": {k: round(v, 5) for k, v in avg_ms.items()},
         "launches_per_solve": launches_per_solve,

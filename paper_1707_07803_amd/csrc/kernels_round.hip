@@ -359,15 +359,57 @@ __global__ __launch_bounds__(NT) void k_round_last(const double* T, int rp, int 
 
 // ------------------------------------------------- rounding of any MPO
 
+// Z (m x s column-major, ld m) <- H_0 H_1 ... H_{k-1} Z for the reflectors
+// stored as by wg_geqr2 in V (ld m), applied in blocks of QBMAX from the last
+// one: a block is I - Vb T Vb^T (compact WY; T by the forward recurrence from
+// Vb^T Vb, as in wg_geqrf), so each block costs three matrix-core GEMMs.
+// ws holds m QBMAX + 2 QBMAX s doubles.
+__device__ void wg_apply_q_blocked(const double* V, const double* tau, int m, int k, double* Z,
+                                   int s, double* ws, double* arena) {
+  const int tid = threadIdx.x;
+  double* Ts = lds_Ts(arena);
+  double* Gs = lds_Gs(arena);
+  for (int j0 = ((k - 1) / QBMAX) * QBMAX; j0 >= 0; j0 -= QBMAX) {
+    const int jb = (k - j0) < QBMAX ? (k - j0) : QBMAX, mp = m - j0;
+    double* Vp = ws;                                   // explicit V (mp x jb, column-major)
+    double* W = ws + (int64_t)mp * QBMAX;              // Vp^T Z (jb x s, row-major)
+    double* W2 = W + (int64_t)QBMAX * s;               // T W
+    for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
+      const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
+      Vp[e] = r > c ? V[(int64_t)(j0 + c) * m + j0 + r] : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QBMAX, 1, arena);
+    if (tid < 64) {
+      for (int i = 0; i < jb; ++i) {
+        const double ti = tau[j0 + i];
+        if (tid < i) {
+          double acc = 0.0;
+          for (int c = tid; c < i; ++c) acc += Ts[tid * QBMAX + c] * Gs[c * QBMAX + i];
+          Ts[tid * QBMAX + i] = -ti * acc;
+        } else if (tid < QBMAX) {
+          Ts[tid * QBMAX + i] = tid == i ? ti : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    wg_gemm<double>(jb, s, mp, 1.0, Vp, mp, 1, Z + j0, 1, m, 0.0, W, s, 1, arena);
+    wg_gemm<double>(jb, s, jb, 1.0, Ts, QBMAX, 1, W, s, 1, 0.0, W2, s, 1, arena);
+    wg_gemm<double>(mp, s, jb, -1.0, Vp, 1, mp, W2, s, 1, 1.0, Z + j0, 1, m, arena);
+  }
+  __syncthreads();
+}
+
 // Right-to-left step at core k >= 1 of the rounding of a general MPO: the LQ
 // of core k (r rows, m = n r' columns, row-major) as the QR with diag(R) >= 0
 // of its transpose X (m x r column-major: the same memory), rk = min(m, r).
-// Q (rk x m row-major) = the first rk columns of the QR's Q, transposed: the
-// new core k, with orthonormal rows.  Gpo (pn x rk) = Gp (pn x r) R^T: the
+// X keeps the reflectors (the new core k is Q^T, rk x m, never formed: the
+// left-to-right pass applies them); Gpo (pn x rk) = Gp (pn x r) R^T is the
 // previous core with L = R^T absorbed.
 __global__ __launch_bounds__(NT) void k_lq_absorb(const double* G, int r, int m, const double* Gp,
                                                   int pn, double* X, double* tau, double* ws,
-                                                  double* Rt, double* Q, double* Gpo) {
+                                                  double* Rt, double* Gpo) {
   __shared__ double arena[AR];
   const int tid = threadIdx.x;
   const int rk = m < r ? m : r;
@@ -379,9 +421,6 @@ __global__ __launch_bounds__(NT) void k_lq_absorb(const double* G, int r, int m,
     const int64_t b = e / rk, c = e % rk;
     Rt[e] = c <= b ? X[b * m + c] : 0.0;
   }
-  for (int64_t e = tid; e < (int64_t)m * rk; e += NT) Q[e] = (e % m) == (e / m) ? 1.0 : 0.0;
-  __syncthreads();
-  wg_apply_q(X, tau, m, rk, Q, rk, m);
   __syncthreads();
   wg_gemm<double>(pn, rk, r, 1.0, Gp, r, 1, Rt, rk, 1, 0.0, Gpo, rk, 1, arena);
 }
@@ -400,33 +439,67 @@ __global__ __launch_bounds__(NT) void k_norm_delta(const double* G, int64_t len,
   }
 }
 
-// Left-to-right step at core k < d - 1: the panel M = T (s x r) times core k
-// (r x n q), reshaped (s n) x q column-major, then its truncated SVD.
-__global__ __launch_bounds__(NT) void k_round_step(const double* T, int s, int r, const double* G,
-                                                   int n, int q, const double* delta_p, int rmax,
-                                                   double* Mr, double* M, double* ws, double* tau,
+// Left-to-right step at core 0: the panel M = core 0 (n x q, as (1 n) x q)
+// times the 1 x 1 carried factor T, column-major, then its truncated SVD.
+__global__ __launch_bounds__(NT) void k_round_first(const double* T, const double* G, int n, int q,
+                                                    const double* delta_p, int rmax, double* M,
+                                                    double* ws, double* tau, double* B, double* U,
+                                                    double* nrm, double* sig, int* perm,
+                                                    double* sgn, int* flag, double* Y,
+                                                    double* core, double* Tn, int* rho_out) {
+  __shared__ double arena[AR];
+  __shared__ int srho;
+  const double t = T[0];
+  for (int64_t e = threadIdx.x; e < (int64_t)n * q; e += NT) {
+    const int64_t i = e / q, c = e % q;
+    M[c * n + i] = t * G[e];
+  }
+  __syncthreads();
+  panel_svd(M, n, q, delta_p[0], rmax, ws, tau, B, U, nrm, sig, perm, sgn, flag, Y, core, Tn,
+            rho_out, arena, &srho);
+}
+
+// Left-to-right step at core 0 < k < d - 1: the carried factor T (s x rk)
+// times the orthogonalised core Q^T (rk x m, m = n q), formed as
+// (Q [T^T; 0])^T with the stored reflectors, reshaped (s n) x q column-major,
+// then its truncated SVD.
+__global__ __launch_bounds__(NT) void k_round_step(const double* T, int s, int rk, const double* X,
+                                                   const double* tq, int m, int n, int q,
+                                                   const double* delta_p, int rmax, double* Z,
+                                                   double* wsq, double* M, double* ws, double* tau,
                                                    double* B, double* U, double* nrm, double* sig,
                                                    int* perm, double* sgn, int* flag, double* Y,
                                                    double* core, double* Tn, int* rho_out) {
   __shared__ double arena[AR];
   __shared__ int srho;
-  const int64_t nq = (int64_t)n * q, nv = (int64_t)s * n;
-  wg_gemm<double>(s, (int)nq, r, 1.0, T, r, 1, G, nq, 1, 0.0, Mr, nq, 1, arena);
+  const int64_t nv = (int64_t)s * n;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * s; e += NT) {
+    const int64_t a = e / m, j = e % m;
+    Z[e] = j < rk ? T[a * rk + j] : 0.0;
+  }
   __syncthreads();
-  for (int64_t e = threadIdx.x; e < nv * q; e += NT) {
-    const int64_t p = e / q, c = e % q;
-    M[c * nv + p] = Mr[e];
+  wg_apply_q_blocked(X, tq, m, rk, Z, s, wsq, arena);
+  for (int64_t e = threadIdx.x; e < nv * q; e += NT) {   // M[(a n + i), c] = Z[(i q + c), a]
+    const int64_t p = e / q, c = e % q, a = p / n, i = p % n;
+    M[c * nv + p] = Z[a * m + i * q + c];
   }
   __syncthreads();
   panel_svd(M, nv, q, delta_p[0], rmax, ws, tau, B, U, nrm, sig, perm, sgn, flag, Y, core, Tn,
             rho_out, arena, &srho);
 }
 
-// The last core takes the carried factor: out (s x n) = T (s x r) G (r x n).
-__global__ __launch_bounds__(NT) void k_absorb_last(const double* T, int s, int r, const double* G,
-                                                    int n, double* out) {
-  __shared__ double arena[GEMM_LDS];
-  wg_gemm<double>(s, n, r, 1.0, T, r, 1, G, n, 1, 0.0, out, n, 1, arena);
+// The last core takes the carried factor: out (s x n) = T (s x rk) Q^T, i.e.
+// the column-major n x s matrix Q [T^T; 0], which has the same memory.
+__global__ __launch_bounds__(NT) void k_round_last_q(const double* T, int s, int rk, const double* X,
+                                                     const double* tq, int n, double* wsq,
+                                                     double* out) {
+  __shared__ double arena[AR];
+  for (int64_t e = threadIdx.x; e < (int64_t)n * s; e += NT) {
+    const int64_t a = e / n, j = e % n;
+    out[e] = j < rk ? T[a * rk + j] : 0.0;
+  }
+  __syncthreads();
+  wg_apply_q_blocked(X, tq, n, rk, out, s, wsq, arena);
 }
 
 }  // namespace
@@ -496,12 +569,13 @@ hipError_t launch_round_last(const double* T, int rp, int cp, const int* pm, int
 }
 
 // SVD-based rounding (Sec. 3) of a general MPO: right-to-left LQ of cores
-// d..2 with each L absorbed into the left neighbour (k_lq_absorb), delta from
-// the first core's norm, then left-to-right truncated SVDs of the carried
-// factor times each core (k_round_step); the last core takes the remaining
-// factor.  One workgroup per step; each step's rank is read back to size the
-// next.  The zero matrix (|A|_F = 0 after the first pass) gives zero rank-1
-// cores.
+// d..2 with each L absorbed into the left neighbour (k_lq_absorb; the
+// orthogonalised cores stay as Householder reflectors), delta from the first
+// core's norm, then left-to-right truncated SVDs of the carried factor times
+// each core (k_round_first, k_round_step); the last core takes the remaining
+// factor (k_round_last_q).  One workgroup per step; each step's rank is read
+// back to size the next.  The zero matrix (|A|_F = 0 after the first pass)
+// gives zero rank-1 cores.
 hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t* J,
                      const double* const* cores, double eps, int rmax, RoundedMpo* out,
                      hipStream_t s) {
@@ -523,29 +597,32 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
     if (e == hipSuccess) e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   };
-  std::vector<int64_t> n(d), rr(rank, rank + d + 1);
+  std::vector<int64_t> n(d), rr(rank, rank + d + 1), mk(d, 0);
   for (int k = 0; k < d; ++k) n[k] = I[k] * J[k];
-  // working copies: W[k] is (rr[k], n[k], rr[k+1]) row-major
-  std::vector<const double*> W(cores, cores + d);
+  // core 0 (absorbed) explicitly; cores k >= 1 as reflectors X[k], tau[k]
+  const double* G0 = cores[0];
+  std::vector<double*> X(d, nullptr), tq(d, nullptr);
+  const double* Gk = d > 1 ? cores[d - 1] : nullptr;
   for (int k = d - 1; k >= 1 && e == hipSuccess; --k) {
     const int64_t r = rr[k], m = n[k] * rr[k + 1], rk = m < r ? m : r, pn = rr[k - 1] * n[k - 1];
-    double* X = A.get<double>(m * r);
-    double* tau = A.get<double>(r);
+    X[k] = A.get<double>(m * r);
+    tq[k] = A.get<double>(r);
     double* ws = A.get<double>(qr_ws_doubles(m, r));
     double* Rt = A.get<double>(r * rk);
-    double* Q = A.get<double>(rk * m);
     double* Gpo = A.get<double>(pn * rk);
     if ((e = A.e) != hipSuccess) break;
-    k_lq_absorb<<<1, NT, 0, s>>>(W[k], (int)r, (int)m, W[k - 1], (int)pn, X, tau, ws, Rt, Q, Gpo);
+    k_lq_absorb<<<1, NT, 0, s>>>(Gk, (int)r, (int)m, cores[k - 1], (int)pn, X[k], tq[k], ws, Rt,
+                                 Gpo);
     e = hipGetLastError();
-    W[k] = Q;
-    W[k - 1] = Gpo;
+    mk[k] = m;
     rr[k] = rk;
+    Gk = Gpo;   // core k - 1 with L absorbed
   }
+  if (d > 1) G0 = Gk;
   double* dl = A.get<double>(2);
   if (e == hipSuccess) e = A.e;
   if (e == hipSuccess) {
-    k_norm_delta<<<1, NT, 0, s>>>(W[0], n[0] * rr[1], eps, d - 1, dl);
+    k_norm_delta<<<1, NT, 0, s>>>(G0, n[0] * rr[1], eps, d - 1, dl);
     e = hipGetLastError();
   }
   double hd[2] = {0.0, 0.0};
@@ -561,7 +638,7 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
   if (d == 1) {   // a single core is the matrix itself
     res[0] = A.get<double>(n[0]);
     if ((e = A.e) == hipSuccess)
-      e = hipMemcpyAsync(res[0], W[0], sizeof(double) * n[0], hipMemcpyDeviceToDevice, s);
+      e = hipMemcpyAsync(res[0], G0, sizeof(double) * n[0], hipMemcpyDeviceToDevice, s);
     return finish();
   }
   double* one = A.get<double>(1);
@@ -574,10 +651,9 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
   const double* T = one;
   int64_t sr = 1;   // rows of T (the kept rank so far)
   for (int k = 0; k < d - 1 && e == hipSuccess; ++k) {
-    const int64_t r = rr[k], q = rr[k + 1], nv = sr * n[k];
+    const int64_t q = rr[k + 1], nv = sr * n[k];
     const int64_t mn = nv < q ? nv : q;
     const int64_t cap = (rmax > 0 && rmax < mn) ? rmax : mn;
-    double* Mr = A.get<double>(nv * q);
     double* M = A.get<double>(nv * q);
     double* ws = A.get<double>(qr_ws_doubles(nv, q));
     double* tau = A.get<double>(q);
@@ -590,10 +666,16 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
     double* Y = A.get<double>(nv * cap);
     res[k] = A.get<double>(nv * cap);
     double* Tn = A.get<double>(cap * q);
+    double* Z = k > 0 ? A.get<double>(nv * q) : nullptr;
+    double* wsq = k > 0 ? A.get<double>(mk[k] * QBMAX + 2 * QBMAX * sr) : nullptr;
     if ((e = A.e) != hipSuccess) break;
-    k_round_step<<<1, NT, 0, s>>>(T, (int)sr, (int)r, W[k], (int)n[k], (int)q, dl, rmax, Mr, M, ws,
-                                  tau, B, U, nrm, sig, perm, sgn, flag, Y, res[k], Tn,
-                                  rho_d + k + 1);
+    if (k == 0)
+      k_round_first<<<1, NT, 0, s>>>(T, G0, (int)n[0], (int)q, dl, rmax, M, ws, tau, B, U, nrm,
+                                     sig, perm, sgn, flag, Y, res[k], Tn, rho_d + 1);
+    else
+      k_round_step<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[k], X[k], tq[k], (int)mk[k], (int)n[k],
+                                    (int)q, dl, rmax, Z, wsq, M, ws, tau, B, U, nrm, sig, perm,
+                                    sgn, flag, Y, res[k], Tn, rho_d + k + 1);
     e = hipGetLastError();
     int rk = 0;
     read_back(&rk, rho_d + k + 1, sizeof(int));
@@ -603,10 +685,11 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
     sr = rk;
   }
   if (e == hipSuccess) {
-    res[d - 1] = A.get<double>(sr * n[d - 1]);
+    const int k = d - 1;
+    res[k] = A.get<double>(sr * n[k]);
+    double* wsq = A.get<double>(mk[k] * QBMAX + 2 * QBMAX * sr);
     if ((e = A.e) == hipSuccess) {
-      k_absorb_last<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[d - 1], W[d - 1], (int)n[d - 1],
-                                     res[d - 1]);
+      k_round_last_q<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[k], X[k], tq[k], (int)n[k], wsq, res[k]);
       e = hipGetLastError();
     }
   }
