@@ -48,6 +48,7 @@ __all__ = [
     "lq_nonneg", "qr_nonneg", "svd_signfix", "choose_rank",
     "round_sweep", "tnrsvd", "TNrSVDResult", "dense_rsvd",
     "tnrsvd_paper_orientation", "reverse_mpo",
+    "gaussian_counter_array", "sketch_counter_base", "sketch_compress",
     "merge_tail_adjoint", "sigma_sum_grad",
     "sparse_to_mpo", "round_mpo",
 ]
@@ -460,6 +461,101 @@ def round_sweep(cores: Sequence[np.ndarray], eps: float, rmax: int,
 
 
 # --------------------------------------------------------------------------
+# Sketched product truncation (not in the paper): an opt-in step before ROUND
+# --------------------------------------------------------------------------
+
+def gaussian_counter_array(seed: int, idx: np.ndarray) -> np.ndarray:
+    """gaussian_counter(seed, n) for every n in idx (uint64 arithmetic wraps
+    mod 2^64 as SplitMix64 requires); numpy's log/cos/sin may differ from the
+    math module's in the last bit, which no consumer of this stream relies on."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    k = idx // np.uint64(2)
+    g = np.uint64(_GOLDEN)
+    sd = np.uint64(seed & _MASK64)
+
+    def mix(c):
+        with np.errstate(over="ignore"):
+            z = sd + (c + np.uint64(1)) * g
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+    u1 = ((mix(np.uint64(2) * k) >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (mix(np.uint64(2) * k + np.uint64(1)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    rad = np.sqrt(-2.0 * np.log(u1))
+    ang = 2.0 * np.pi * u2
+    return rad * np.where(idx % np.uint64(2) == 0, np.cos(ang), np.sin(ang))
+
+
+def sketch_counter_base(t: int) -> int:
+    """First counter of the sketch of the t-th product of a solve (t = 0 for
+    Y = A Omega, then one per product): beyond Omega's counters."""
+    return (t + 1) << 40
+
+
+def sketch_compress(Y: Sequence[np.ndarray], ell: int, seed: int, t: int) -> List[np.ndarray]:
+    """Compress a product chain Y (cores (P_i, n_i, P_{i+1}), the last
+    (P, n, K)) to bond ranks <= ell before ROUND, by the randomize-then-
+    orthogonalize rounding of Al Daas, Ballard et al. (SIAM J. Sci. Comput.
+    2023): a Gaussian chain S with bond ranks l_k = min(ell, P_k) sketches the
+    right parts, W_k = Y_{>=k} S_{>=k}^T (P_k x l_k), right to left; then, left
+    to right, the panel (C Y_k) W_{k+1} ((s n) x l_{k+1}) is orthogonalised by
+    QR with diag(R) >= 0, its Q becomes core k and Q^T (C Y_k) is carried
+    right; the last core takes C Y_{d-1}.  The K leg is never cut.  Y is
+    returned unchanged when no bond rank exceeds ell.
+
+    Sketch entries: gaussian_counter(seed, sketch_counter_base(t) + o_k + j),
+    with core k's block at o_k = sum over 1 <= j < k of ell n_j ell, entry
+    (c, i, c') at j = (c n_k + i) ell + c' (cores 1 .. d-2), and on the last
+    core (c, i, kappa) at j = c n K + i K + kappa (the leading l_k x l_{k+1}
+    block of an ell x n x ell layout is used).
+
+    Not in the paper; parity of the GPU mode is against this function.  Pinned
+    by exactness when ell reaches the chain's true bond ranks, by the skip rule,
+    and by the dense projection it amounts to on tiny inputs.
+    """
+    Y = [np.asarray(y, dtype=np.float64) for y in Y]
+    d = len(Y)
+    P = [Y[0].shape[0]] + [y.shape[2] for y in Y]
+    if d == 1 or max(P[1:d]) <= ell:
+        return [y.copy() for y in Y]
+    n = [y.shape[1] for y in Y]
+    K = P[d]
+    l = [None] + [min(ell, P[k]) for k in range(1, d)]
+    base = sketch_counter_base(t)
+    off = [0] * (d + 1)
+    for k in range(1, d - 1):
+        off[k + 1] = off[k] + ell * n[k] * ell
+
+    def sketch_core(k):
+        if k == d - 1:
+            c, j = np.meshgrid(np.arange(l[k]), np.arange(n[k] * K), indexing="ij")
+            idx = base + off[k] + c * (n[k] * K) + j
+            return gaussian_counter_array(seed, idx.astype(np.uint64))       # (l_k, n K)
+        c, i, c2 = np.meshgrid(np.arange(l[k]), np.arange(n[k]), np.arange(l[k + 1]),
+                               indexing="ij")
+        idx = base + off[k] + (c * n[k] + i) * ell + c2
+        return gaussian_counter_array(seed, idx.astype(np.uint64))           # (l_k, n, l_k+1)
+
+    W = [None] * (d + 1)
+    W[d - 1] = Y[d - 1].reshape(P[d - 1], n[d - 1] * K) @ sketch_core(d - 1).T
+    for k in range(d - 2, 0, -1):
+        Sk = sketch_core(k)
+        W[k] = np.einsum("aib,bc,eic->ae", Y[k], W[k + 1], Sk)
+    out = []
+    C = np.ones((1, 1))
+    for k in range(d - 1):
+        Zt = np.tensordot(C, Y[k], axes=(1, 0))                  # (s, n, P_{k+1})
+        s_ = Zt.shape[0]
+        Zr = Zt.reshape(s_ * n[k], P[k + 1])
+        Q, _ = qr_nonneg(Zr @ W[k + 1])
+        out.append(Q.reshape(s_, n[k], Q.shape[1]))
+        C = Q.T @ Zr
+    out.append(np.tensordot(C, Y[d - 1], axes=(1, 0)))
+    return out
+
+
+# --------------------------------------------------------------------------
 # TNrSVD: Algorithm 5.1 with the subspace iteration of Algorithm 5.4
 # --------------------------------------------------------------------------
 
@@ -479,7 +575,7 @@ class TNrSVDResult:
 def tnrsvd(A_cores: Sequence[np.ndarray], k: int, p: int, q: int,
            omega: Optional[Tuple[Sequence[np.ndarray], np.ndarray]] = None,
            seed: Optional[int] = None, eps: float = 0.0, rmax: int = 0,
-           merge: bool = True) -> TNrSVDResult:
+           merge: bool = True, sketch_rank: int = 0, sketch_seed: int = 0) -> TNrSVDResult:
     """TNrSVD of an MPO matrix A (Algorithm 5.1 in MPO form, Sec. 5).
 
     1. merge the last cores so that the K-core has I, J >= K (Sec. 6.3);
@@ -491,6 +587,10 @@ def tnrsvd(A_cores: Sequence[np.ndarray], k: int, p: int, q: int,
     5. B^T = A^T Q; ROUND and sweep it; SVD of the last core gives sigma, V
        and W (Algorithm 5.3 mirrored); U = Q W on the last core (Sec. 5.4);
     6. keep the first k = K - p values and vectors (oversampling, Sec. 5.1).
+
+    sketch_rank > 0 (not in the paper): every product t = 0, 1, ... (Y = A
+    Omega first, B^T last) goes through sketch_compress(., sketch_rank,
+    sketch_seed, t) before its ROUND.
     """
     K = k + p
     A = [np.asarray(c, dtype=np.float64) for c in A_cores]
@@ -509,21 +609,30 @@ def tnrsvd(A_cores: Sequence[np.ndarray], k: int, p: int, q: int,
         omega = omega_from_seed(cols_m, K, seed)
     Om = omega_as_mps(*omega)
     ranks = []
+    nprod = [0]
+
+    def cut(X):
+        if sketch_rank <= 0:
+            return X
+        t = nprod[0]
+        nprod[0] += 1
+        return sketch_compress(X, sketch_rank, sketch_seed, t)
+
     Y = mpo_times_mps(A, Om)
     Y0 = [y.copy() for y in Y]
-    r = round_sweep(Y, eps, rmax, "qr")
+    r = round_sweep(cut(Y), eps, rmax, "qr")
     ranks.append(r["ranks"])
     Q = r["cores"]
     for _ in range(q):
         Z = mpo_t_times_mps(A, Q)
-        r = round_sweep(Z, eps, rmax, "qr")
+        r = round_sweep(cut(Z), eps, rmax, "qr")
         ranks.append(r["ranks"])
         Y = mpo_times_mps(A, r["cores"])
-        r = round_sweep(Y, eps, rmax, "qr")
+        r = round_sweep(cut(Y), eps, rmax, "qr")
         ranks.append(r["ranks"])
         Q = r["cores"]
     Bt = mpo_t_times_mps(A, Q)
-    r = round_sweep(Bt, eps, rmax, "svd")
+    r = round_sweep(cut(Bt), eps, rmax, "svd")
     ranks.append(r["ranks"])
     sig = r["sigma"]
     W = r["W"]
