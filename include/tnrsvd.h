@@ -83,7 +83,26 @@ typedef struct {
   int check_finite;          /* nonzero: scan input cores for NaN/Inf        */
   void* stream;              /* hipStream_t, borrowed; NULL = null stream    */
   int orientation;           /* tnrsvd_orientation                           */
+  int sketch_rank;           /* 0: off; ell in [1, 256]: sketched product    */
+                             /* truncation before each ROUND (see below)     */
 } tnrsvd_opts;
+
+/*
+ * Sketched product truncation (opts.sketch_rank = ell > 0; not in the paper,
+ * a cheaper alternative to rounding the full product).  After every product
+ * (Y = A Omega, A^T Q, A Q, the projection) whose bond ranks P_k = R_k r_k
+ * exceed ell somewhere, the product is compressed to bond ranks <= ell by
+ * randomize-then-orthogonalize (Al Daas, Ballard et al., SIAM J. Sci.
+ * Comput. 2023): a Gaussian chain with bond ranks min(ell, P_k) sketches the
+ * right parts, then a left-to-right pass keeps the Householder Q of each
+ * sketched panel.  The SVD-based ROUND then runs on the compressed product,
+ * whose panels are ell / r times narrower.  The sketch of the t-th product of
+ * a solve (t = 0 for A Omega) for MPO b uses the Omega stream of seed + b at
+ * counters from (t + 1) 2^40 on.  Exact when ell reaches the product's true
+ * ranks; otherwise the error is the sketch's (small when ell exceeds the
+ * ranks ROUND keeps by a margin).  Workspace: about (d - 1) P ell + 4 ell n
+ * max(P, ell) doubles per MPO, allocated by tnrsvd_create.
+ */
 
 /*
  * Orientation of the K leg (the paper's Sec. 5: Omega, Y and Q carry their K
@@ -306,7 +325,8 @@ tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merg
  * tnrsvd_profile_read -- synchronise the stream and return, for one kernel
  * kind, the summed event time (ms) and the launch count since enabling.
  * Kernel kinds: 0 contraction (Sec. 5.2 products), 1 right-to-left LQ sweep,
- * 2 left-to-right truncation/QR/SVD sweep, 3 U = Q W, 4 Omega load, 5 Y copy.
+ * 2 left-to-right truncation/QR/SVD sweep, 3 U = Q W, 4 Omega load, 5 Y copy,
+ * 6 sketched product truncation (opts.sketch_rank > 0).
  * tnrsvd_get_product_ranks -- product ranks P_0..P_d (P_d = K) of the last
  * product and the ranks rho_0..rho_d left by its right-to-left sweep (valid
  * after the sweep); synchronises the stream.  Either pointer may be NULL.

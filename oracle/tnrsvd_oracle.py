@@ -541,7 +541,8 @@ def sketch_compress(Y: Sequence[np.ndarray], ell: int, seed: int, t: int) -> Lis
     W[d - 1] = Y[d - 1].reshape(P[d - 1], n[d - 1] * K) @ sketch_core(d - 1).T
     for k in range(d - 2, 0, -1):
         Sk = sketch_core(k)
-        W[k] = np.einsum("aib,bc,eic->ae", Y[k], W[k + 1], Sk)
+        T1 = np.tensordot(Y[k], W[k + 1], axes=(2, 0))          # (P_k, n, l_k+1)
+        W[k] = np.tensordot(T1, Sk, axes=([1, 2], [1, 2]))       # (P_k, l_k)
     out = []
     C = np.ones((1, 1))
     for k in range(d - 1):

@@ -16,24 +16,6 @@ struct Acc { using type = float; };
 template <>
 struct Acc<double> { using type = double; };
 
-__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
-  // SplitMix64 (Steele, Lea, Flood 2014) in counter form: state seed + (n+1) * golden gamma.
-  uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-__device__ inline double gaussian_at(uint64_t seed, uint64_t n) {
-  // Box-Muller on the pair (2k, 2k+1): u1 in (0,1], u2 in [0,1).
-  const uint64_t k = n >> 1;
-  const double u1 = (double)((splitmix64_at(seed, 2 * k) >> 11) + 1ull) * 0x1.0p-53;
-  const double u2 = (double)(splitmix64_at(seed, 2 * k + 1) >> 11) * 0x1.0p-53;
-  const double rad = sqrt(-2.0 * log(u1));
-  const double ang = 2.0 * 3.14159265358979311600 * u2;
-  return (n & 1ull) ? rad * sin(ang) : rad * cos(ang);
-}
-
 __global__ void k_merge_pair(const double* __restrict__ T, const double* __restrict__ C,
                              double* __restrict__ out, int a, int I1, int J1, int b, int I2,
                              int J2, int b2) {

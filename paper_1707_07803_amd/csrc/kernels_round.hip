@@ -502,6 +502,130 @@ __global__ __launch_bounds__(NT) void k_round_last_q(const double* T, int s, int
   wg_apply_q_blocked(X, tq, n, rk, out, s, wsq, arena);
 }
 
+// ------------------------------------------- sketched product truncation
+
+// Randomize-then-orthogonalize (Al Daas, Ballard et al., SIAM J. Sci. Comput.
+// 2023) applied to the pending product of MPO b (one workgroup): with a
+// Gaussian chain S of bond ranks l_k = min(ell, P_k) drawn from the counter
+// stream, the sketch environments W_k = Y_{>=k} S_{>=k}^T (P_k x l_k) are
+// formed right to left; then, left to right, the panel (C Y_k) W_{k+1}
+// ((s n) x l_{k+1}) is orthogonalised by Householder QR (diag(R) >= 0), its Q
+// overwrites core k and Q^T (C Y_k) is carried; the last core takes C Y_{d-1}.
+// The product ranks pr are lowered to the new ones.  Nothing is done when no
+// bond rank exceeds ell.  Sketch entry (c, i, c') of core k (1 <= k <= d-2)
+// is the normal number at counter cbase + o_k + (c n_k + i) ell + c', with
+// o_k = sum over 1 <= j < k of ell n_j ell; on the last core (c, i, kappa)
+// at cbase + o_{d-1} + c n K + i K + kappa.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_sketch_pass(const MpoDesc* mpos, const CoreDesc* cores,
+                                                    int op, int* pr, T* Z, int ell, uint64_t seed,
+                                                    uint64_t cbase, const int* nm_d,
+                                                    const int64_t* ws_off, double* wsb, int* err) {
+  __shared__ double arena[AR];
+  __shared__ int Pold[kSketchMaxD + 1];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const MpoDesc md = mpos[b];
+  const int d = md.d, K = md.K, pc = md.pcap, nm = nm_d[b];
+  if (d < 2) return;
+  if (d > kSketchMaxD) {
+    if (tid == 0) atomicOr(err, 4);
+    return;
+  }
+  for (int k = tid; k <= d; k += NT) Pold[k] = pr[md.r0 + k];
+  __syncthreads();
+  int pmax = 0;
+  for (int k = 1; k < d; ++k) pmax = Pold[k] > pmax ? Pold[k] : pmax;
+  if (pmax <= ell) return;
+  if (pmax > pc) {   // the plan's capacity bounds every product rank
+    if (tid == 0) atomicOr(err, 4);
+    return;
+  }
+  const uint64_t s_seed = seed + (uint64_t)b;
+  double* Wb = wsb + ws_off[b];
+  double* S = Wb + (int64_t)(d - 1) * pc * ell;
+  double* U2 = S + (int64_t)ell * nm * (ell > K ? ell : K);
+  double* Zt = U2 + (int64_t)nm * pc * ell;
+  double* M = Zt + (int64_t)ell * nm * (pc > K ? pc : K);
+  double* Qm = M + (int64_t)ell * nm * ell;
+  double* tau = Qm + (int64_t)ell * nm * ell;
+  double* C = tau + ell;
+  double* C2 = C + (int64_t)ell * pc;
+  double* qws = C2 + (int64_t)ell * pc;
+  auto Wk = [&](int k) { return Wb + (int64_t)(k - 1) * pc * ell; };
+  auto nmode = [&](int k) {
+    const CoreDesc& cd = cores[md.c0 + k];
+    return op == 0 ? cd.I : cd.J;
+  };
+  auto counter_off = [&](int k) {   // o_k
+    uint64_t o = 0;
+    for (int j = 1; j < k; ++j) o += (uint64_t)ell * nmode(j) * ell;
+    return o;
+  };
+  auto lr = [&](int k) { return Pold[k] < ell ? Pold[k] : ell; };
+
+  // right to left: W_{d-1}, then W_k from W_{k+1}
+  {
+    const int k = d - 1, n = nmode(k), P = Pold[k], lk = lr(k);
+    const int64_t nK = (int64_t)n * K;
+    const uint64_t o = cbase + counter_off(k);
+    for (int64_t e = tid; e < lk * nK; e += NT) S[e] = gaussian_at(s_seed, o + (uint64_t)e);
+    __syncthreads();
+    const T* Y = Z + cores[md.c0 + k].z_off;
+    wg_gemm<T>(lk, P, (int)nK, 1.0, S, nK, 1, Y, 1, nK, 0.0, Wk(k), 1, lk, arena);
+  }
+  for (int k = d - 2; k >= 1; --k) {
+    const int n = nmode(k), P = Pold[k], P2 = Pold[k + 1], lk = lr(k), lk2 = lr(k + 1);
+    const uint64_t o = cbase + counter_off(k);
+    for (int64_t e = tid; e < (int64_t)lk * n * lk2; e += NT) {
+      const int64_t c2 = e % lk2, ci = e / lk2;
+      S[e] = gaussian_at(s_seed, o + (uint64_t)(ci * ell + c2));
+    }
+    __syncthreads();
+    for (int i = 0; i < n; ++i)   // U2[(i P2 + q) lk + c] = sum_c' W_{k+1}[q, c'] S[c, i, c']
+      wg_gemm<double>(P2, lk, lk2, 1.0, Wk(k + 1), lk2, 1, S + (int64_t)i * lk2, 1,
+                      (int64_t)n * lk2, 0.0, U2 + (int64_t)i * P2 * lk, lk, 1, arena);
+    const T* Y = Z + cores[md.c0 + k].z_off;
+    wg_gemm<T>(lk, P, n * P2, 1.0, U2, 1, lk, Y, 1, (int64_t)n * P2, 0.0, Wk(k), 1, lk, arena);
+  }
+
+  // left to right
+  if (tid == 0) C[0] = 1.0;
+  __syncthreads();
+  int s = 1;
+  for (int k = 0; k < d - 1; ++k) {
+    const int n = nmode(k), P = Pold[k], P2 = Pold[k + 1], lk2 = lr(k + 1), sn = s * n;
+    const int rho = sn < lk2 ? sn : lk2;
+    T* Y = Z + cores[md.c0 + k].z_off;
+    wg_gemm<T>(s, n * P2, P, 1.0, C, P, 1, Y, (int64_t)n * P2, 1, 0.0, Zt, (int64_t)n * P2, 1,
+               arena);
+    wg_gemm<double>(sn, lk2, P2, 1.0, Zt, P2, 1, Wk(k + 1), lk2, 1, 0.0, M, 1, sn, arena);
+    wg_qr(M, sn, lk2, sn, tau, qws, arena);
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)sn * rho; e += NT) Qm[e] = (e % sn) == (e / sn) ? 1.0 : 0.0;
+    __syncthreads();
+    wg_apply_q(M, tau, sn, rho, Qm, rho, sn);
+    __syncthreads();
+    wg_gemm<double>(rho, P2, sn, 1.0, Qm, sn, 1, Zt, P2, 1, 0.0, C2, P2, 1, arena);
+    for (int64_t e = tid; e < (int64_t)sn * rho; e += NT) {
+      const int64_t row = e / rho, r = e % rho;
+      Y[e] = T(Qm[r * sn + row]);
+    }
+    double* t = C;
+    C = C2;
+    C2 = t;
+    s = rho;
+    if (tid == 0) pr[md.r0 + k + 1] = rho;
+    __syncthreads();
+  }
+  {
+    const int k = d - 1, n = nmode(k), P = Pold[k];
+    const int64_t nK = (int64_t)n * K;
+    T* Y = Z + cores[md.c0 + k].z_off;
+    wg_gemm<T>(s, (int)nK, P, 1.0, C, P, 1, Y, nK, 1, 0.0, Zt, nK, 1, arena);
+    for (int64_t e = tid; e < s * nK; e += NT) Y[e] = T(Zt[e]);
+  }
+}
+
 }  // namespace
 
 int64_t qr_ws_doubles(int64_t m, int64_t n) { return m * pick_qb(m) + 2 * (int64_t)pick_qb(m) * n + m; }
@@ -694,6 +818,17 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
     }
   }
   return finish();
+}
+
+hipError_t launch_sketch(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op, int* pr,
+                         void* Z, int dtype, int ell, uint64_t seed, uint64_t cbase,
+                         const int* nm, const int64_t* off, double* ws, int* err, hipStream_t s) {
+  by_dtype(dtype, [&](auto* t) {
+    using T = elem_t<decltype(t)>;
+    k_sketch_pass<T><<<batch, NT, 0, s>>>(mpos, cores, op, pr, (T*)Z, ell, seed, cbase, nm, off,
+                                          ws, err);
+  });
+  return hipGetLastError();
 }
 
 }  // namespace tnr

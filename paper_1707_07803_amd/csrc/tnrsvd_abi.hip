@@ -46,7 +46,7 @@ inline int64_t sat_mul(int64_t a, int64_t b) {
 
 enum Space { kNone = 0, kRow = 1, kCol = 2 };
 
-constexpr int kKinds = 6;  // contract, rl, lr, form_u, load_omega, copy_y0
+constexpr int kKinds = 7;  // contract, rl, lr, form_u, load_omega, copy_y0, sketch
 
 }  // namespace
 
@@ -108,6 +108,11 @@ struct tnrsvd_s {
   std::vector<std::vector<int64_t>> tail_off;
   std::vector<std::vector<std::array<int, 4>>> tail_shape;
   double* tail = nullptr;
+  // sketched product truncation (opts.sketch_rank > 0): per-MPO FP64 workspace
+  double* sk = nullptr;
+  int64_t* sk_off_d = nullptr;
+  int* sk_nm_d = nullptr;
+  int prod_t = 0;   // products since the first of the solve (the sketch's stream index)
   bool grad_ready = false;
   GradMpo* gm_d = nullptr;
   int64_t* eoff_d = nullptr;
@@ -224,6 +229,8 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   if (!(o->round_tol >= 0.0) || !std::isfinite(o->round_tol))
     return fail(TNRSVD_E_INVALID, "round_tol must be finite and >= 0");
   if (o->max_rank < 0) return fail(TNRSVD_E_INVALID, "max_rank must be >= 0");
+  if (o->sketch_rank < 0 || o->sketch_rank > 256)
+    return fail(TNRSVD_E_INVALID, "sketch_rank must be in [0, 256]");
 
   std::vector<int> merge(batch);
   for (int b = 0; b < batch; ++b) TRY(plan_mpo(mpos[b], K, &merge[b]));
@@ -261,6 +268,7 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   // ---- capacity plan -----------------------------------------------------
   int64_t a_tot = 0, x_tot = 0, z_tot = 0, w_tot = 0, l_tot = 0, t_tot = 0, y_tot = 0,
           u_tot = 0, om_tot = 0, s_tot = 0, out_tot = 0;
+  std::vector<int> sk_nm;
   int r_tot = 0;
   int64_t tcap = 1, mcap_s = 1, ucap = 1, qcap = 1;
   int vcap = 64, scap = K;
@@ -329,7 +337,7 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
     omn += J[dm - 1] * K;
     om_tot += omn;
     h->max_om = std::max(h->max_om, omn);
-    int64_t mpo_t = 1, mpo_m = 1, mpo_u = 1, mpo_q = 1;
+    int64_t mpo_t = 1, mpo_m = 1, mpo_u = 1, mpo_q = 1, mpo_pc = 1, mpo_nm = 1;
     int mpo_v = 64;
     for (int i = 0; i < dm; ++i) {
       CoreDesc cd{};
@@ -341,6 +349,8 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
       cd.xcap2 = (int)xc[i + 1];
       const int64_t nmax = std::max(I[i], J[i]);
       const int64_t P = R[i] * xc[i], P2 = R[i + 1] * xc[i + 1];
+      mpo_pc = std::max(mpo_pc, P);
+      mpo_nm = std::max(mpo_nm, nmax);
       // register panels pad each y block of rows to a power of two (>= 16)
       int64_t P2pad = 16;
       while (P2pad < P2) P2pad *= 2;
@@ -393,7 +403,8 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
     md.out_off = out_tot;
     out_tot += K + 2 * (int64_t)K * K;
     md.mcap = mpo_v;
-    md.pcap = 0;
+    md.pcap = (int)mpo_pc;
+    sk_nm.push_back((int)mpo_nm);
     tcap = std::max(tcap, mpo_t);
     mcap_s = std::max(mcap_s, mpo_m);
     ucap = std::max(ucap, mpo_u);
@@ -463,6 +474,18 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   ALLOC(h->U, sizeof(double) * x_tot);
   ALLOC(h->V, sizeof(double) * x_tot);
   ALLOC(h->tail, sizeof(double) * tail_tot);
+  std::vector<int64_t> sk_off;
+  if (o->sketch_rank > 0) {
+    int64_t sk_tot = 0;
+    for (int b = 0; b < batch; ++b) {
+      sk_off.push_back(sk_tot);
+      sk_tot += sketch_ws_doubles(h->mh[b].d, h->mh[b].pcap, sk_nm[b], h->mh[b].K,
+                                  o->sketch_rank);
+    }
+    ALLOC(h->sk, sizeof(double) * sk_tot);
+    ALLOC(h->sk_off_d, sizeof(int64_t) * batch);
+    ALLOC(h->sk_nm_d, sizeof(int) * batch);
+  }
   h->a_elems = a_tot;
 #undef ALLOC
   hipStream_t s = h->stream;
@@ -476,6 +499,13 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   if ((e = hipMemcpyAsync(h->mpos_d, h->mh.data(), sizeof(MpoDesc) * batch,
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail_dev(e, "upload MPO descriptors");
+  if (o->sketch_rank > 0) {
+    if ((e = hipMemcpyAsync(h->sk_off_d, sk_off.data(), sizeof(int64_t) * batch,
+                            hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->sk_nm_d, sk_nm.data(), sizeof(int) * batch,
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+      return fail_dev(e, "upload sketch plan");
+  }
   if ((e = hipMemcpyAsync(h->cores_d, h->ch.data(), sizeof(CoreDesc) * h->ncores,
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail_dev(e, "upload core descriptors");
@@ -718,6 +748,7 @@ tnrsvd_status load_omega(tnrsvd_t h) {
 
 tnrsvd_status do_mult(tnrsvd_t h, int op) {
   hipError_t e;
+  if (h->first_product) h->prod_t = 0;
   {
     Timed tm(h, 0);
     e = launch_contract(h->mpos_d, h->cores_d, h->core_mpo_d, h->ncores, h->xr, h->pr,
@@ -733,6 +764,15 @@ tnrsvd_status do_mult(tnrsvd_t h, int op) {
     h->y0_valid = true;
   }
   h->first_product = false;
+  if (h->opts.sketch_rank > 0) {
+    // stream index t of this product: counters from (t + 1) 2^40 on, past Omega's
+    Timed tm(h, 6);
+    e = launch_sketch(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->Z, h->dtype,
+                      h->opts.sketch_rank, h->opts.seed, (uint64_t)(h->prod_t + 1) << 40,
+                      h->sk_nm_d, h->sk_off_d, h->sk, h->err, h->stream);
+    TRY(dev_check(e, "sketch the product"));
+    ++h->prod_t;
+  }
   return TNRSVD_OK;
 }
 

@@ -115,6 +115,26 @@ struct GradMpo {
 
 // Launchers implemented in the .hip sources, called from the ABI layer.
 namespace tnr {
+
+// Counter-based Gaussian stream shared by Omega and the product sketches.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
+  // SplitMix64 (Steele, Lea, Flood 2014) in counter form: state seed + (n+1) * golden gamma.
+  uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ inline double gaussian_at(uint64_t seed, uint64_t n) {
+  // Box-Muller on the pair (2k, 2k+1): u1 in (0,1], u2 in [0,1).
+  const uint64_t k = n >> 1;
+  const double u1 = (double)((splitmix64_at(seed, 2 * k) >> 11) + 1ull) * 0x1.0p-53;
+  const double u2 = (double)(splitmix64_at(seed, 2 * k + 1) >> 11) * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 2.0 * 3.14159265358979311600 * u2;
+  return (n & 1ull) ? rad * sin(ang) : rad * cos(ang);
+}
+
 hipError_t launch_merge_pair(const double* Tin, const double* C, double* out, int a, int I1, int J1,
                              int b, int I2, int J2, int b2, hipStream_t s);
 hipError_t launch_convert_core(const void* in, int in_dtype, void* out, int out_dtype, int64_t n,
@@ -130,6 +150,22 @@ struct Radices {
 };
 hipError_t launch_reverse_core(const void* in, int dtype, void* out, int64_t R0, int64_t n,
                                int64_t R1, const Radices& rad, hipStream_t s);
+// Sketched product truncation (opt-in): per-MPO FP64 workspace and launch.
+__host__ __device__ inline int64_t sketch_ws_doubles(int d, int64_t pc, int64_t nm, int64_t K,
+                                                     int64_t ell) {
+  const int64_t m = ell * nm;
+  return (int64_t)(d - 1) * pc * ell        // W at bonds 1 .. d-1
+         + ell * nm * (ell > K ? ell : K)   // one sketch core
+         + nm * pc * ell                    // U2
+         + ell * nm * (pc > K ? pc : K)     // Zt
+         + 2 * m * ell                      // M and Q
+         + ell + 2 * ell * pc               // tau, C, C2
+         + m * 33 + 64 * ell;               // QR workspace (block width <= 32)
+}
+constexpr int kSketchMaxD = 256;
+hipError_t launch_sketch(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op, int* pr,
+                         void* Z, int dtype, int ell, uint64_t seed, uint64_t cbase,
+                         const int* nm, const int64_t* off, double* ws, int* err, hipStream_t s);
 hipError_t launch_swap_legs(const void* in, int dtype, void* out, int64_t R0, int64_t I, int64_t J,
                             int64_t R1, hipStream_t s);
 hipError_t launch_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch, uint64_t seed,

@@ -33,7 +33,7 @@ EXPORTS = [
 
 # kernel kinds reported by tnrsvd_profile_read
 KERNELS = {"contract": 0, "rl_sweep": 1, "lr_sweep": 2, "form_u": 3, "load_omega": 4,
-           "copy_y0": 5}
+           "copy_y0": 5, "sketch": 6}
 
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_STATE", -4: "E_NOMEM",
           -5: "E_DEVICE", -6: "E_NONFINITE"}
@@ -59,7 +59,7 @@ class _Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int),
                 ("round_tol", ctypes.c_double), ("max_rank", ctypes.c_int64),
                 ("check_finite", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("orientation", ctypes.c_int)]
+                ("orientation", ctypes.c_int), ("sketch_rank", ctypes.c_int)]
 
 # where the K leg of Omega, Y, Q, U and V sits: "k_last" is the library's own
 # layout, "k_first" the paper's (Sec. 5), reached by reading the MPO reversed
@@ -148,7 +148,8 @@ class TNrSVD:
 
     def __init__(self, mpos, k: int, p: int = 0, q: int = 0, seed: int = 0,
                  precision: str = "f64", round_tol: float = 0.0, max_rank: int = 0,
-                 check_finite: bool = False, stream=None, orientation: str = "k_last"):
+                 check_finite: bool = False, stream=None, orientation: str = "k_last",
+                 sketch_rank: int = 0):
         import torch
         L = load_library()
         if isinstance(mpos[0], torch.Tensor):
@@ -170,7 +171,7 @@ class TNrSVD:
                      round_tol=float(round_tol), max_rank=int(max_rank),
                      check_finite=1 if check_finite else 0,
                      stream=ctypes.c_void_p(stream.cuda_stream),
-                     orientation=ORIENTATIONS[orientation])
+                     orientation=ORIENTATIONS[orientation], sketch_rank=int(sketch_rank))
         self.orientation = orientation
         h = ctypes.c_void_p()
         _check(L.tnrsvd_create(ctypes.byref(h), self.batch, structs, ctypes.byref(opts)))
