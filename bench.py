@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--hilbert", choices=["on", "off", "only"], default="on",
                     help="the Hilbert experiment of Sec. 6.3 (round the MPO, then solve)")
     ap.add_argument("--hilbert-steps", type=int, default=3)
+    ap.add_argument("--sketch", type=int, default=16,
+                    help="also time the opt-in sketched product truncation at this rank (0: no)")
     ap.add_argument("--batched-full", action="store_true",
                     help="time the whole 512-MPO uneven batch once (minutes) and exit")
     ap.add_argument("--no-configs", action="store_true",
@@ -138,7 +140,7 @@ def instrumented_counts(h, R, I, J, K, q, esz):
 # ---------------------------------------------------------------------------
 
 def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol=None,
-              autotune=False):
+              autotune=False, sketch=0):
     import numpy as np
     import torch
     from paper_1707_07803_amd import TNrSVD
@@ -147,7 +149,7 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol
     cores = [torch.as_tensor(c, dtype=td).cuda() for c in W.cores]
     mpos = [cores] * batch      # MPO b draws its random MPO from seed + b
     h = TNrSVD(mpos, W.k, W.p, W.q, seed=W.omega_seed, precision=precision, round_tol=eps,
-               max_rank=W.rmax)
+               max_rank=W.rmax, sketch_rank=sketch)
     del cores
     tuned = h.autotune(3) if autotune else None
     if refine_tol is None:
@@ -172,7 +174,7 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol
         h.run(want_sigma=False)
     torch.cuda.synchronize()
     kern = {k: h.profile_read(k) for k in ("contract", "rl_sweep", "lr_sweep", "form_u",
-                                           "load_omega", "copy_y0")}
+                                           "load_omega", "copy_y0", "sketch")}
     h.profile(False)
     sig_all = h.run()
     sigma = sig_all[0]
@@ -576,6 +578,15 @@ def main():
                   f"{res['bf16+refine']['steps'] / res['bf16+refine']['seconds']:.1f} solves/s",
                   file=sys.stderr, flush=True)
     paths = precs + (["bf16+refine"] if "bf16" in precs else [])
+    if args.sketch > 0:
+        # not the paper's rounding: an opt-in alternative, reported beside it
+        ps = precs[0]
+        key = f"{ps}+sketch{args.sketch}"
+        res[key] = time_path(W, ps, W.eps_by_precision[ps], args.steps, args.warmup,
+                             sketch=args.sketch)
+        paths.append(key)
+        print(f"[bench] {key}: {res[key]['steps'] / res[key]['seconds']:.1f} solves/s",
+              file=sys.stderr, flush=True)
 
     batched = None
     if args.batch > 0:

@@ -37,6 +37,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum over the 16 lanes of each DPP row, returned to every lane of the row:
+// shift-adds within the row leave the total in its lane 15 (src), which is
+// then read back by the row's lanes.
+__device__ __forceinline__ double row16_sum(double v, int src) {
+  v += dpp_d<0x111>(v);          // row_shr:1
+  v += dpp_d<0x112>(v);          // row_shr:2
+  v += dpp_d<0x114>(v);          // row_shr:4
+  v += dpp_d<0x118>(v);          // row_shr:8
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Workgroup barrier that orders LDS only: global stores still in flight are
@@ -432,10 +445,69 @@ __device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* fl
   // never rotated again and the sweep count stays small.
   const double tol = 2.220446049250313e-16 * (double)(len > 16 ? len : 16);
   const int nn = nv + (nv & 1);
+  // More pairs per round than waves and short vectors: one 16-lane row of a
+  // wave per pair (32 pairs at once), row sums by DPP shifts within the row.
+  const bool rows16 = nn / 2 > NW && len <= 256;
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();
+    if (rows16) {
+      const int g = tid >> 4, r16 = tid & 15, src = (lane & ~15) | 15;
+      for (int rnd = 0; rnd < nn - 1; ++rnd) {
+        for (int t = g; t < nn / 2; t += NT / 16) {
+          int p, q;
+          if (t == 0) {
+            p = nn - 1;
+            q = rnd;
+          } else {
+            p = (rnd + t) % (nn - 1);
+            q = (rnd - t + nn - 1) % (nn - 1);
+          }
+          if (p > q) {
+            const int tmp = p;
+            p = q;
+            q = tmp;
+          }
+          if (q >= nv) continue;
+          double* bp = B + (int64_t)p * ldb;
+          double* bq = B + (int64_t)q * ldb;
+          double a = 0.0, b = 0.0, c = 0.0;
+          for (int e = r16; e < len; e += 16) {
+            const double x = bp[e], y = bq[e];
+            a += x * x;
+            b += y * y;
+            c += x * y;
+          }
+          a = row16_sum(a, src);
+          b = row16_sum(b, src);
+          c = row16_sum(c, src);
+          if (a <= tiny || b <= tiny || a + b <= skip2 || fabs(c) <= tol * sqrt(a) * sqrt(b))
+            continue;
+          const double zeta = (b - a) / (2.0 * c);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int e = r16; e < len; e += 16) {
+            const double x = bp[e], y = bq[e];
+            bp[e] = cs * x - sn * y;
+            bq[e] = sn * x + cs * y;
+          }
+          double* up = U + (int64_t)p * nv;
+          double* uq = U + (int64_t)q * nv;
+          for (int e = r16; e < nv; e += 16) {
+            const double x = up[e], y = uq[e];
+            up[e] = cs * x - sn * y;
+            uq[e] = sn * x + cs * y;
+          }
+          if (r16 == 0) *flag = 1;
+        }
+        __syncthreads();
+      }
+      const int any = *flag;
+      __syncthreads();
+      if (!any) break;
+      continue;
+    }
     for (int rnd = 0; rnd < nn - 1; ++rnd) {
       for (int t = w; t < nn / 2; t += NW) {
         int p, q;
