@@ -227,10 +227,19 @@ def other_configs():
         dt = timed(h, lambda: h.run(False), 1)
         res[p] = (dt, h.run()[0])
         h.close()
+    # the opt-in sketched product truncation (not the paper's rounding) at ell = 48
+    h = TNrSVD(dev(W.cores, "f32"), W.k, W.p, W.q, seed=W.omega_seed, precision="f32",
+               round_tol=W.eps, max_rank=W.rmax, sketch_rank=48)
+    dt = timed(h, lambda: h.run(False), 1)
+    res["f32+sketch48"] = (dt, h.run()[0])
+    h.close()
     out["large"] = {"workload": "d=50, 2x2 cores, ranks 10, k=10 p=10 q=2, r_max=32 (2^50 x 2^50)",
                     "solves_per_s": {p: round(1.0 / res[p][0], 4) for p in res},
                     "sigma_rel_diff_f32_vs_f64": float(np.linalg.norm(res["f32"][1] - res["f64"][1])
-                                                       / np.linalg.norm(res["f64"][1]))}
+                                                       / np.linalg.norm(res["f64"][1])),
+                    "sigma_rel_diff_sketch48_vs_f64": float(
+                        np.linalg.norm(res["f32+sketch48"][1] - res["f64"][1])
+                        / np.linalg.norm(res["f64"][1]))}
     Ws = wl.batched(512)
     cost = [len(w.cores) * w.cores[0].shape[1] ** 2 * w.cores[1].shape[0] ** 3 for w in Ws]
     sel = sorted(range(len(Ws)), key=lambda b: cost[b])[:128]
@@ -249,9 +258,14 @@ def other_configs():
     tf = timed(h, lambda: h.run(False), 1)
     grads = [torch.empty_like(c) for c in cores]
     tb = timed(h, lambda: h.backward(None, grads), 1)
+    h.close()
+    h = TNrSVD(cores, W.k, W.p, W.q, seed=W.omega_seed, precision="f32", max_rank=W.rmax,
+               sketch_rank=64)
+    ts = timed(h, lambda: h.run(False), 1)
     out["grad"] = {"workload": "d=30, 4x4 cores, ranks 16, k=16 p=8 q=1, FP32; gradient of the "
                                "sum of the top 16 sigma at fixed singular vectors",
-                   "forward_s": round(tf, 4), "backward_s": round(tb, 4)}
+                   "forward_s": round(tf, 4), "backward_s": round(tb, 4),
+                   "forward_sketch64_s": round(ts, 4)}
     h.close()
     return out
 
@@ -401,6 +415,16 @@ def hilbert_section(steps, cpu_baseline_on):
             t0 = time.perf_counter()
             sig = h.run()[0]
             ts.append(time.perf_counter() - t0)
+        hs = TNrSVD(P, W.k, W.p, W.q, seed=N, round_tol=W.eps, max_rank=W.rmax,
+                    orientation="k_first", sketch_rank=64)
+        sig_s = hs.run()[0]
+        tk = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sig_s = hs.run()[0]
+            tk.append(time.perf_counter() - t0)
+        hs.close()
         out[f"N={N}"] = {"matrix": f"2^{N} x 2^{N - 1}", "q": W.q,
                          "mpo_rank_before": int(W.cores[0].shape[3]),
                          "mpo_ranks_after_max": max(int(c.shape[3]) for c in P[:-1]),
@@ -408,9 +432,13 @@ def hilbert_section(steps, cpu_baseline_on):
                          "ms_round": round(1e3 * float(np.median(tr)), 3),
                          "ms_solve": round(1e3 * float(np.median(ts)), 3),
                          "basis_ranks_max": max(h.ranks()[1:]),
+                         "ms_solve_sketch64": round(1e3 * float(np.median(tk)), 3),
+                         "sigma_rel_diff_sketch64": float(np.linalg.norm(sig_s - sig)
+                                                          / np.linalg.norm(sig)),
                          "sigma_1": float(sig[0]), "sigma_16": float(sig[15])}
         print(f"[bench] hilbert N={N}: round {out[f'N={N}']['ms_round']} ms, "
-              f"solve {out[f'N={N}']['ms_solve']} ms", file=sys.stderr, flush=True)
+              f"solve {out[f'N={N}']['ms_solve']} ms, sketched "
+              f"{out[f'N={N}']['ms_solve_sketch64']} ms", file=sys.stderr, flush=True)
         h.close()
         del A, P
         torch.cuda.empty_cache()
