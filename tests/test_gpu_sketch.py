@@ -110,3 +110,41 @@ def test_invalid_sketch_rank():
     with pytest.raises(TNrSVDError) as ei:
         TNrSVD(to_device(W.cores), W.k, W.p, 0, sketch_rank=257)
     assert ei.value.status == -1
+
+
+def test_graph_replay_and_batch_match_eager():
+    """The sketch kernel under hipGraph capture (replayed several times, with
+    eager work between) and in a batch of uneven MPOs gives the eager,
+    one-MPO singular values: every launch reads its product index and the
+    MPO's seed offset from its own arguments."""
+    import torch
+    from paper_1707_07803_amd import TNrSVD
+    W = wl.small()
+    V = wl.random_mpo(7, 2, 3, 4, 0.5, 17)
+    dev = [to_device(W.cores), to_device(V)]
+    eager = []
+    for b, cores in enumerate(dev):
+        h = TNrSVD(cores, 6, 4, 1, seed=30 + b, sketch_rank=6)
+        eager.append(h.run()[0])
+        h.close()
+    hb = TNrSVD(dev, 6, 4, 1, seed=30, sketch_rank=6)
+    for rep in range(3):
+        s = hb.run_graph()
+        for b in range(2):
+            np.testing.assert_allclose(s[b], eager[b], rtol=1e-12)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()    # eager work between replays
+    np.testing.assert_allclose(hb.run()[1], eager[1], rtol=1e-12)
+    hb.close()
+
+
+def test_paper_orientation_with_sketch_matches_mirror():
+    from paper_1707_07803_amd import TNrSVD, omega_flat
+    W = wl.small()
+    om = omega_flat(*omega_for(W.cores, W.K, 3))
+    hl = TNrSVD(to_device(W.cores), W.k, W.p, 1, seed=2, sketch_rank=8)
+    hf = TNrSVD(to_device(o.reverse_mpo(W.cores)), W.k, W.p, 1, seed=2, sketch_rank=8,
+                orientation="k_first")
+    hl.set_omega(om)
+    hf.set_omega(om)
+    np.testing.assert_array_equal(hf.run()[0], hl.run()[0])
