@@ -641,6 +641,19 @@ def main():
                    "kernel_avg_ms": {k: round(v[0] / v[1], 4) for k, v in kb.items()}}
         print(f"[bench] batched {args.batch}: {batched['solves_per_s']} solves/s", file=sys.stderr,
               flush=True)
+        # the same batch with FP64 contractions, and with the opt-in sketched truncation
+        variants = {}
+        for name, pv, skv in (("f64", "f64", 0), (f"{pb}+sketch{args.sketch}", pb, args.sketch)):
+            if skv == 0 and name != "f64":
+                continue
+            rv = time_path(W, pv, W.eps_by_precision[pv], args.batch_steps, 1, batch=args.batch,
+                           graph=True, autotune=True, sketch=skv)
+            ev = [float(np.linalg.norm(sv - exact) / np.linalg.norm(exact)) for sv in rv["sigma_all"]]
+            variants[name] = {"solves_per_s": round(args.batch * rv["steps"] / rv["seconds"], 2),
+                              "max_sigma_err_vs_prescribed": max(ev)}
+            print(f"[bench] batched {args.batch} {name}: {variants[name]['solves_per_s']} solves/s",
+                  file=sys.stderr, flush=True)
+        batched["variants"] = variants
 
     configs = None
     if not args.no_configs:
