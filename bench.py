@@ -463,10 +463,11 @@ def hilbert_section(steps, cpu_baseline_on):
     return out
 
 
-def batched_full(precisions):
+def batched_full(precisions, sketch=0):
     """The whole uneven batch (512 MPOs, d in [10,40], I=J in {2,4}, ranks in [4,32],
     k=8 p=8 q=1, r_max=32) as one handle: one warm-up solve and one timed solve per
-    precision, with per-kernel event times.  The largest members bound the batch."""
+    precision, with per-kernel event times.  The largest members bound the batch.
+    sketch > 0 adds the first precision with the opt-in sketched truncation."""
     import numpy as np
     import torch
     import workloads as wl
@@ -475,10 +476,14 @@ def batched_full(precisions):
     Ws = wl.batched(512)
     out = {"workload": "512 uneven MPOs (d in [10,40], I=J in {2,4}, ranks in [4,32], N(0,1/R)), "
                        "k=8 p=8 q=1, r_max=32, one handle, persistent launches"}
-    for p in precisions:
+    runs = [(p, p, 0) for p in precisions]
+    if sketch > 0:
+        runs.append((f"{precisions[0]}+sketch{sketch}", precisions[0], sketch))
+    sig = {}
+    for key, p, sk in runs:
         td = torch.float64 if p == "f64" else torch.float32
         mpos = [[torch.as_tensor(c, dtype=td).cuda() for c in w.cores] for w in Ws]
-        h = TNrSVD(mpos, 8, 8, 1, seed=9, precision=p, max_rank=32)
+        h = TNrSVD(mpos, 8, 8, 1, seed=9, precision=p, max_rank=32, sketch_rank=sk)
         del mpos
         h.run(False)
         torch.cuda.synchronize()
@@ -488,12 +493,18 @@ def batched_full(precisions):
         h.run(False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        kern = {k: round(h.profile_read(k)[0], 1) for k in ("contract", "rl_sweep", "lr_sweep")}
+        kern = {k: round(h.profile_read(k)[0], 1) for k in ("contract", "rl_sweep", "lr_sweep",
+                                                              "sketch")}
         h.profile(False)
+        sig[key] = h.run()
         h.close()
-        out[p] = {"seconds_per_batch": round(dt, 3), "solves_per_s": round(512 / dt, 3),
-                  "kernel_ms": kern}
-        print(f"[bench] full batch {p}: {dt:.2f} s", file=sys.stderr, flush=True)
+        out[key] = {"seconds_per_batch": round(dt, 3), "solves_per_s": round(512 / dt, 3),
+                    "kernel_ms": kern}
+        if key != runs[0][0]:
+            ref = sig[runs[0][0]]
+            out[key]["max_sigma_rel_diff_vs_" + runs[0][0]] = float(max(
+                np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(sig[key], ref)))
+        print(f"[bench] full batch {key}: {dt:.2f} s", file=sys.stderr, flush=True)
     return out
 
 
@@ -565,7 +576,8 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.batched_full:
-        print(json.dumps({"batched_full": batched_full(args.precisions.split(",")[:2])}))
+        print(json.dumps({"batched_full": batched_full(args.precisions.split(",")[:2],
+                                                       args.sketch)}))
         return
     import numpy as np
     import torch
