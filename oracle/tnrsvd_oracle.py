@@ -49,6 +49,7 @@ __all__ = [
     "round_sweep", "tnrsvd", "TNrSVDResult", "dense_rsvd",
     "tnrsvd_paper_orientation", "reverse_mpo",
     "gaussian_counter_array", "sketch_counter_base", "sketch_compress",
+    "complex_to_real_mpo", "tnrsvd_complex",
     "merge_tail_adjoint", "sigma_sum_grad",
     "sparse_to_mpo", "round_mpo",
 ]
@@ -747,6 +748,56 @@ def tnrsvd_paper_orientation(A_cores: Sequence[np.ndarray], k: int, p: int,
         Q, _ = _paper_round_orth(times(Qz, False), eps, rmax, "qr")
     _, S = _paper_round_orth(times(Q, True), eps, rmax, "svd")
     return S[:k]
+
+
+# --------------------------------------------------------------------------
+# Complex-valued MPOs through the real embedding (the paper allows complex
+# tensors; the embedding is a standard identity, not the paper's)
+# --------------------------------------------------------------------------
+
+def complex_to_real_mpo(cores: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Real MPO of the real form B of a complex MPO A: every complex number z on
+    a bond becomes the 2 x 2 block phi(z) = [[Re z, -Im z], [Im z, Re z]]
+    (phi(xy) = phi(x) phi(y), so bond products carry over).  Inner ranks double;
+    the first core's new left component becomes the most significant digit of
+    its row mode (I_1 -> 2 I_1) and the last core's new right component the most
+    significant digit of its column mode (J_d -> 2 J_d).  B(i', j') with those
+    digits s, t is phi(A(i, j))[s, t]: a row and column permutation of
+    [[Re A, -Im A], [Im A, Re A]], whose singular values are A's, each twice.
+    Pinned by LAPACK's complex SVD of the dense A.
+    """
+    d = len(cores)
+    out = []
+    for k, G in enumerate(cores):
+        G = np.asarray(G, dtype=np.complex128)
+        R0, I, J, R1 = G.shape
+        E = np.zeros((R0, 2, I, J, R1, 2))
+        E[:, 0, :, :, :, 0] = G.real
+        E[:, 0, :, :, :, 1] = -G.imag
+        E[:, 1, :, :, :, 0] = G.imag
+        E[:, 1, :, :, :, 1] = G.real
+        # bond index (a, s) -> 2 a + s
+        E = E.transpose(0, 1, 2, 3, 4, 5)                     # (a, s, i, j, b, t)
+        if k == 0:
+            # s joins the row mode as its most significant digit: i' = s I + i
+            E = E.reshape(1, 2, I, J, R1, 2).reshape(1, 2 * I, J, R1, 2)
+        else:
+            E = E.reshape(2 * R0, I, J, R1, 2)
+        a0, Ii, Jj = E.shape[0], E.shape[1], E.shape[2]
+        if k == d - 1:
+            # t joins the column mode: j' = t J + j
+            E = E.reshape(a0, Ii, Jj, 1, 2).transpose(0, 1, 4, 2, 3).reshape(a0, Ii, 2 * Jj, 1)
+        else:
+            E = E.reshape(a0, Ii, Jj, 2 * R1)
+        out.append(np.ascontiguousarray(E))
+    return out
+
+
+def tnrsvd_complex(A_cores: Sequence[np.ndarray], k: int, p: int, q: int, **kw) -> np.ndarray:
+    """Top-k singular values of a complex MPO: TNrSVD of its real form with
+    k' = 2k, p' = 2p, then every other value (each appears twice)."""
+    res = tnrsvd(complex_to_real_mpo(A_cores), 2 * k, 2 * p, q, **kw)
+    return res.sigma[0::2].copy()
 
 
 # --------------------------------------------------------------------------
