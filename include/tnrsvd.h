@@ -429,6 +429,24 @@ tnrsvd_status tnrsvd_sparse_round(int d, const int64_t* rows, const int64_t* col
  */
 tnrsvd_status tnrsvd_round_mpo(const tnrsvd_mpo* a, double round_tol, int max_rank, void* stream,
                                tnrsvd_rounded_t* out);
+/*
+ * tnrsvd_complex_embed -- real form of a complex MPO (the paper allows real
+ * or complex cores, Sec. 2; the embedding is a standard identity, not the
+ * paper's).  a's cores are complex, stored as interleaved (re, im) pairs of
+ * a->dtype (F64 or F32) in C order (R, I, J, R'); a->rank/rows/cols are
+ * the complex MPO's.  Every bond entry z becomes the 2 x 2 block
+ * phi(z) = [[Re z, -Im z], [Im z, Re z]] (phi(xy) = phi(x) phi(y)), bond index
+ * (a, s) -> 2 a + s, so the inner ranks double; the first core's left
+ * component becomes the most significant digit of its row mode (I_1 -> 2 I_1)
+ * and the last core's right component that of its column mode (J_d -> 2 J_d).
+ * The result B is a row and column permutation of [[Re A, -Im A], [Im A,
+ * Re A]]: its singular values are A's, each twice, so TNrSVD of B with k' = 2k
+ * and p' = 2p, every other value taken, solves A.  out[k]: caller-allocated
+ * DEVICE buffers of the real core k, (2R or 1) x (2I or I) x (2J or J) x
+ * (2R' or 1) elements of a->dtype.  Synchronises `stream`.
+ * Errors: E_INVALID (null argument, dtype), E_SHAPE (ranks, shapes), E_DEVICE.
+ */
+tnrsvd_status tnrsvd_complex_embed(const tnrsvd_mpo* a, void* const* out, void* stream);
 tnrsvd_status tnrsvd_rounded_ranks(tnrsvd_rounded_t r, int64_t* ranks);
 tnrsvd_status tnrsvd_rounded_copy(tnrsvd_rounded_t r, int k, double* dst);
 tnrsvd_status tnrsvd_rounded_destroy(tnrsvd_rounded_t r);

@@ -285,6 +285,44 @@ hipError_t launch_reverse_core(const void* in, int dtype, void* out, int64_t R0,
   return hipGetLastError();
 }
 
+// Real form of one core of a complex MPO (interleaved re/im of T, shape
+// (R0, I, J, R1)): every bond entry z becomes phi(z) = [[Re z, -Im z],
+// [Im z, Re z]], bond index (a, s) -> 2 a + s.  On the first core (first != 0)
+// the left component s instead becomes the most significant digit of the row
+// mode (i' = s I + i, left rank 1); on the last core the right component t
+// becomes the most significant digit of the column mode (j' = t J + j).
+template <typename T>
+__global__ void k_complex_embed(const T* __restrict__ in, T* __restrict__ out, int64_t R0,
+                                int64_t I, int64_t J, int64_t R1, int first, int last) {
+  const int64_t Io = first ? 2 * I : I, Jo = last ? 2 * J : J, R1o = last ? 1 : 2 * R1;
+  const int64_t n = R0 * I * J * R1 * 4;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int st = (int)(e & 3), s = st >> 1, t = st & 1;
+    const int64_t src = e >> 2;
+    const int64_t b = src % R1, j = (src / R1) % J, i = (src / (R1 * J)) % I, a = src / (R1 * J * I);
+    const T re = in[2 * src], im = in[2 * src + 1];
+    const T v = s == t ? re : (s == 0 ? T(-(double)im) : im);
+    const int64_t ao = first ? 0 : 2 * a + s, io = first ? s * I + i : i;
+    const int64_t jo = last ? t * J + j : j, bo = last ? 0 : 2 * b + t;
+    out[((ao * Io + io) * Jo + jo) * R1o + bo] = v;
+  }
+}
+
+hipError_t launch_complex_embed(const void* in, int dtype, void* out, int64_t R0, int64_t I,
+                                int64_t J, int64_t R1, int first, int last, hipStream_t s) {
+  const int64_t n = R0 * I * J * R1 * 4;
+  if (n <= 0) return hipSuccess;
+  const int g = grid_for(n, 256, 4096);
+  if (dtype == kF64)
+    k_complex_embed<double><<<g, 256, 0, s>>>((const double*)in, (double*)out, R0, I, J, R1,
+                                              first, last);
+  else
+    k_complex_embed<float><<<g, 256, 0, s>>>((const float*)in, (float*)out, R0, I, J, R1, first,
+                                             last);
+  return hipGetLastError();
+}
+
 hipError_t launch_check_finite(const void* in, int dtype, int64_t n, int* flag, hipStream_t s) {
   const int g = grid_for(n, 256, 4096);
   if (dtype == 0)

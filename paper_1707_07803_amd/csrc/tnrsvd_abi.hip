@@ -1621,6 +1621,32 @@ tnrsvd_status tnrsvd_round_mpo(const tnrsvd_mpo* a, double round_tol, int max_ra
   return TNRSVD_OK;
 }
 
+tnrsvd_status tnrsvd_complex_embed(const tnrsvd_mpo* a, void* const* out, void* stream) {
+  g_err.clear();
+  if (!a || !out) return fail(TNRSVD_E_INVALID, "null argument");
+  if (a->d < 1) return fail(TNRSVD_E_SHAPE, "d must be >= 1");
+  if (!a->rank || !a->rows || !a->cols || !a->core)
+    return fail(TNRSVD_E_INVALID, "null rank/rows/cols/core array");
+  if (a->dtype != TNRSVD_F64 && a->dtype != TNRSVD_F32)
+    return fail(TNRSVD_E_INVALID, "core dtype must be F64 or F32 (interleaved complex)");
+  const int d = a->d;
+  if (a->rank[0] != 1 || a->rank[d] != 1) return fail(TNRSVD_E_SHAPE, "rank[0] and rank[d] must be 1");
+  for (int k = 0; k < d; ++k) {
+    if (a->rank[k] < 1 || a->rank[k + 1] < 1 || a->rows[k] < 1 || a->cols[k] < 1 || !a->core[k] ||
+        !out[k])
+      return fail(TNRSVD_E_SHAPE, "core %d: bad shape or null pointer", k);
+    if (a->rank[k] * a->rows[k] * a->cols[k] * a->rank[k + 1] > ((int64_t)1 << 40))
+      return fail(TNRSVD_E_SHAPE, "core %d too large", k);
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  for (int k = 0; k < d; ++k)
+    TRY(dev_check(launch_complex_embed(a->core[k], a->dtype == TNRSVD_F64 ? kF64 : kF32, out[k],
+                                       a->rank[k], a->rows[k], a->cols[k], a->rank[k + 1], k == 0,
+                                       k == d - 1, s),
+                  "complex embedding"));
+  return dev_check(hipStreamSynchronize(s), "synchronise");
+}
+
 tnrsvd_status tnrsvd_rounded_ranks(tnrsvd_rounded_t r, int64_t* ranks) {
   if (!r || !ranks) return fail(TNRSVD_E_INVALID, "null argument");
   for (int k = 0; k <= r->d; ++k) ranks[k] = r->ranks[k];

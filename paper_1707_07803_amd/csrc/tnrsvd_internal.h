@@ -166,6 +166,8 @@ constexpr int kSketchMaxD = 256;
 hipError_t launch_sketch(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op, int* pr,
                          void* Z, int dtype, int ell, uint64_t seed, uint64_t cbase,
                          const int* nm, const int64_t* off, double* ws, int* err, hipStream_t s);
+hipError_t launch_complex_embed(const void* in, int dtype, void* out, int64_t R0, int64_t I,
+                                int64_t J, int64_t R1, int first, int last, hipStream_t s);
 hipError_t launch_swap_legs(const void* in, int dtype, void* out, int64_t R0, int64_t I, int64_t J,
                             int64_t R1, hipStream_t s);
 hipError_t launch_omega(const MpoDesc* mpos, const CoreDesc* cores, int batch, uint64_t seed,

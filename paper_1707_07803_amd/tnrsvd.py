@@ -27,7 +27,7 @@ EXPORTS = [
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
-    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_rounded_ranks",
+    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_complex_embed", "tnrsvd_rounded_ranks",
     "tnrsvd_rounded_copy", "tnrsvd_rounded_destroy", "tnrsvd_last_error", "tnrsvd_version",
 ]
 
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
     L.tnrsvd_round_mpo.argtypes = [ctypes.POINTER(_Mpo), ctypes.c_double, I, ctypes.c_void_p,
                                    ctypes.POINTER(ctypes.c_void_p)]
+    L.tnrsvd_complex_embed.argtypes = [ctypes.POINTER(_Mpo), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.c_void_p]
     L.tnrsvd_rounded_ranks.argtypes = [ctypes.c_void_p, P64]
     L.tnrsvd_rounded_copy.argtypes = [ctypes.c_void_p, I, ctypes.c_void_p]
     L.tnrsvd_rounded_destroy.argtypes = [ctypes.c_void_p]
@@ -451,6 +453,50 @@ def round_mpo(cores, round_tol: float, max_rank: int = 0):
     del keep
     return _take_rounded(L, h, [int(c.shape[1]) for c in cores], [int(c.shape[2]) for c in cores],
                          cores[0].device)
+
+
+def complex_embed(cores):
+    """Real form of a complex MPO (device tensors (R, I, J, R') of complex128 or
+    complex64), computed by tnrsvd_complex_embed: float64 / float32 device
+    tensors with the inner ranks doubled, 2 I on the first core and 2 J on the
+    last.  Its singular values are the complex matrix's, each twice."""
+    import torch
+    L = load_library()
+    if cores[0].dtype not in (torch.complex128, torch.complex64):
+        raise TNrSVDError(-1, "cores must be complex128 or complex64")
+    real = [torch.view_as_real(c.contiguous()) for c in cores]      # (..., 2) interleaved
+    rdt = torch.float64 if cores[0].dtype == torch.complex128 else torch.float32
+    d = len(cores)
+    rank = [int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores]
+    rows = [int(c.shape[1]) for c in cores]
+    cols = [int(c.shape[2]) for c in cores]
+    st = _Mpo()
+    ra = (ctypes.c_int64 * (d + 1))(*rank)
+    ro = (ctypes.c_int64 * d)(*rows)
+    co = (ctypes.c_int64 * d)(*cols)
+    pt = (ctypes.c_void_p * d)(*[c.data_ptr() for c in real])
+    st.d, st.rank, st.rows, st.cols, st.core = d, ra, ro, co, pt
+    st.dtype = F64 if rdt == torch.float64 else F32
+    outs = []
+    for k in range(d):
+        shape = (1 if k == 0 else 2 * rank[k], (2 if k == 0 else 1) * rows[k],
+                 (2 if k == d - 1 else 1) * cols[k], 1 if k == d - 1 else 2 * rank[k + 1])
+        outs.append(torch.empty(shape, dtype=rdt, device=cores[0].device))
+    op = (ctypes.c_void_p * d)(*[t.data_ptr() for t in outs])
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(L.tnrsvd_complex_embed(ctypes.byref(st), op, stream))
+    return outs
+
+
+def solve_complex(cores, k: int, p: int = 0, q: int = 0, seed: int = 0, precision: str = "f64",
+                  round_tol: float = 0.0, max_rank: int = 0, sketch_rank: int = 0):
+    """Top-k singular values of a complex MPO: TNrSVD of its real form with
+    k' = 2k and p' = 2p (each value appears twice), every other value taken."""
+    real = complex_embed(cores)
+    with TNrSVD(real, 2 * k, 2 * p, q, seed, precision, round_tol, max_rank,
+                sketch_rank=sketch_rank) as h:
+        sig = h.run()[0]
+    return sig[0::2].copy()
 
 
 def _mpo_struct(cores):
