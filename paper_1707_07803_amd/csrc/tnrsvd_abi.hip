@@ -214,16 +214,11 @@ tnrsvd_status tnrsvd_destroy(tnrsvd_t h) {
   return TNRSVD_OK;
 }
 
-static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
-                                const tnrsvd_opts* o) {
-  g_err.clear();
-  if (!out || !mpos || !o) return fail(TNRSVD_E_INVALID, "null argument");
-  *out = nullptr;
-  if (batch < 1) return fail(TNRSVD_E_INVALID, "batch must be >= 1");
+// Checks of the scalar options (no device call).
+static tnrsvd_status check_opts(const tnrsvd_opts* o) {
   if (o->k < 1 || o->p < 0 || o->q < 0)
     return fail(TNRSVD_E_INVALID, "need k >= 1, p >= 0, q >= 0");
-  const int K = o->k + o->p;
-  if (K > kMaxK) return fail(TNRSVD_E_INVALID, "K = k + p must be <= %d", kMaxK);
+  if (o->k + o->p > kMaxK) return fail(TNRSVD_E_INVALID, "K = k + p must be <= %d", kMaxK);
   if (o->precision != TNRSVD_F64 && o->precision != TNRSVD_F32 && o->precision != TNRSVD_BF16)
     return fail(TNRSVD_E_INVALID, "unknown precision %d", o->precision);
   if (!(o->round_tol >= 0.0) || !std::isfinite(o->round_tol))
@@ -231,6 +226,19 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   if (o->max_rank < 0) return fail(TNRSVD_E_INVALID, "max_rank must be >= 0");
   if (o->sketch_rank < 0 || o->sketch_rank > 256)
     return fail(TNRSVD_E_INVALID, "sketch_rank must be in [0, 256]");
+  if (o->orientation != TNRSVD_K_LAST && o->orientation != TNRSVD_K_FIRST)
+    return fail(TNRSVD_E_INVALID, "unknown orientation %d", o->orientation);
+  return TNRSVD_OK;
+}
+
+static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
+                                const tnrsvd_opts* o) {
+  g_err.clear();
+  if (!out || !mpos || !o) return fail(TNRSVD_E_INVALID, "null argument");
+  *out = nullptr;
+  if (batch < 1) return fail(TNRSVD_E_INVALID, "batch must be >= 1");
+  TRY(check_opts(o));
+  const int K = o->k + o->p;
 
   std::vector<int> merge(batch);
   for (int b = 0; b < batch; ++b) TRY(plan_mpo(mpos[b], K, &merge[b]));
@@ -620,8 +628,7 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
                             const tnrsvd_opts* o) {
   g_err.clear();
   if (!out || !mpos || !o) return fail(TNRSVD_E_INVALID, "null argument");
-  if (o->orientation != TNRSVD_K_LAST && o->orientation != TNRSVD_K_FIRST)
-    return fail(TNRSVD_E_INVALID, "unknown orientation %d", o->orientation);
+  TRY(check_opts(o));   // before any staging
   if (o->orientation == TNRSVD_K_LAST) return create_lib(out, batch, mpos, o);
   *out = nullptr;
   if (batch < 1) return fail(TNRSVD_E_INVALID, "batch must be >= 1");

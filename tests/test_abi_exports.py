@@ -109,3 +109,68 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py)
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
+    """tnrsvd_create (orientation, sketch_rank), tnrsvd_round_mpo and
+    tnrsvd_complex_embed check their arguments before any device call."""
+    from paper_1707_07803_amd import tnrsvd as binding
+    P64 = ctypes.c_int64
+    Mpo, Opts = binding._Mpo, binding._Opts
+    core = ctypes.c_void_p(8)        # never dereferenced: every case fails first
+
+    def mpo(rank, rows, cols, dtype=0, cores=None):
+        d = len(rows)
+        st = Mpo()
+        st.d = d
+        st.rank = (P64 * (d + 1))(*rank)
+        st.rows = (P64 * d)(*rows)
+        st.cols = (P64 * d)(*cols)
+        st.core = (ctypes.c_void_p * d)(*([core] * d if cores is None else cores))
+        st.dtype = dtype
+        return st
+
+    create = lib.tnrsvd_create
+    create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(Mpo),
+                       ctypes.POINTER(Opts)]
+    h = ctypes.c_void_p()
+    good = mpo([1, 2, 1], [2, 2], [2, 2])
+    for kw, want in [(dict(orientation=5), -1), (dict(sketch_rank=-1), -1),
+                     (dict(sketch_rank=257), -1), (dict(orientation=1, sketch_rank=300), -1)]:
+        o = Opts(k=2, p=2, q=0, seed=1, precision=0, round_tol=0.0, max_rank=0, check_finite=0,
+                 stream=None, **kw)
+        assert create(ctypes.byref(h), 1, ctypes.byref(good), ctypes.byref(o)) == want, kw
+    bad = mpo([1, 2, 1], [2, 2], [2, 2])
+    bad.d = 0
+    o = Opts(k=2, p=2, q=0, seed=1, precision=0, round_tol=0.0, max_rank=0, check_finite=0,
+             stream=None, orientation=1)
+    assert create(ctypes.byref(h), 1, ctypes.byref(bad), ctypes.byref(o)) == -2
+
+    rnd = lib.tnrsvd_round_mpo
+    rnd.argtypes = [ctypes.POINTER(Mpo), ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
+                    ctypes.POINTER(ctypes.c_void_p)]
+    cases = [
+        ((ctypes.byref(good), 1e-3, 0, None, None), -1),                       # null out
+        ((None, 1e-3, 0, None, ctypes.byref(h)), -1),                          # null MPO
+        ((ctypes.byref(good), -1.0, 0, None, ctypes.byref(h)), -1),            # round_tol < 0
+        ((ctypes.byref(good), float("inf"), 0, None, ctypes.byref(h)), -1),
+        ((ctypes.byref(good), 1e-3, -1, None, ctypes.byref(h)), -1),           # max_rank < 0
+        ((ctypes.byref(mpo([2, 2, 1], [2, 2], [2, 2])), 1e-3, 0, None, ctypes.byref(h)), -2),
+        ((ctypes.byref(mpo([1, 0, 1], [2, 2], [2, 2])), 1e-3, 0, None, ctypes.byref(h)), -2),
+        ((ctypes.byref(mpo([1, 5000, 1], [2, 2], [2, 2])), 1e-3, 0, None, ctypes.byref(h)), -2),
+        ((ctypes.byref(mpo([1, 2, 1], [2, 2], [2, 2], dtype=2)), 1e-3, 0, None,
+          ctypes.byref(h)), -1),                                               # BF16 input
+        ((ctypes.byref(mpo([1, 2, 1], [2, 2], [2, 2], cores=[core, None])), 1e-3, 0, None,
+          ctypes.byref(h)), -2),                                               # null core
+    ]
+    for args, want in cases:
+        assert rnd(*args) == want, args
+
+    emb = lib.tnrsvd_complex_embed
+    emb.argtypes = [ctypes.POINTER(Mpo), ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
+    outs = (ctypes.c_void_p * 2)(8, 8)
+    assert emb(None, outs, None) == -1
+    assert emb(ctypes.byref(good), None, None) == -1
+    assert emb(ctypes.byref(mpo([1, 2, 2], [2, 2], [2, 2])), outs, None) == -2
+    assert emb(ctypes.byref(mpo([1, 2, 1], [2, 2], [2, 2], dtype=2)), outs, None) == -1
+    assert emb(ctypes.byref(good), (ctypes.c_void_p * 2)(8, None), None) == -2
