@@ -650,6 +650,8 @@ tnrsvd_status tnrsvd_create(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos,
     if (a.dtype != TNRSVD_F64 && a.dtype != TNRSVD_F32)
       return cleanup(), fail(TNRSVD_E_INVALID, "core dtype must be F64 or F32");
     const int d = a.d;
+    if (a.rank[0] != 1 || a.rank[d] != 1)
+      return cleanup(), fail(TNRSVD_E_SHAPE, "MPO %d: rank[0] and rank[d] must be 1", b);
     const int dt = a.dtype == TNRSVD_F64 ? kF64 : kF32;
     rk[b].resize(d + 1);
     rw[b].resize(d);

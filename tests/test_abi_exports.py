@@ -145,6 +145,8 @@ def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
     o = Opts(k=2, p=2, q=0, seed=1, precision=0, round_tol=0.0, max_rank=0, check_finite=0,
              stream=None, orientation=1)
     assert create(ctypes.byref(h), 1, ctypes.byref(bad), ctypes.byref(o)) == -2
+    edge = mpo([2, 2, 1], [2, 2], [2, 2])        # rank[0] != 1, refused before staging
+    assert create(ctypes.byref(h), 1, ctypes.byref(edge), ctypes.byref(o)) == -2
 
     rnd = lib.tnrsvd_round_mpo
     rnd.argtypes = [ctypes.POINTER(Mpo), ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
