@@ -699,7 +699,9 @@ hipError_t launch_round_last(const double* T, int rp, int cp, const int* pm, int
 // each core (k_round_first, k_round_step); the last core takes the remaining
 // factor (k_round_last_q).  One workgroup per step; each step's rank is read
 // back to size the next.  The zero matrix (|A|_F = 0 after the first pass)
-// gives zero rank-1 cores.
+// gives zero rank-1 cores.  Every buffer but the result cores is carved from
+// one allocation sized on the host from the ranks of the first pass (exact)
+// and the caps of the second (each kept rank is at most the first pass's).
 hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t* J,
                      const double* const* cores, double eps, int rmax, RoundedMpo* out,
                      hipStream_t s) {
@@ -723,28 +725,72 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
   };
   std::vector<int64_t> n(d), rr(rank, rank + d + 1), mk(d, 0);
   for (int k = 0; k < d; ++k) n[k] = I[k] * J[k];
-  // core 0 (absorbed) explicitly; cores k >= 1 as reflectors X[k], tau[k]
+  for (int k = d - 1; k >= 1; --k) {   // ranks after the right-to-left pass
+    mk[k] = n[k] * rr[k + 1];
+    rr[k] = mk[k] < rank[k] ? mk[k] : rank[k];
+  }
+  // ---- workspace plan (doubles, 256-byte pieces)
+  int64_t tot = 0;
+  auto take = [&](int64_t cnt) {
+    const int64_t o = tot;
+    tot += ((cnt > 0 ? cnt : 1) + 31) / 32 * 32;
+    return o;
+  };
+  std::vector<int64_t> oX(d, 0), oT(d, 0), oG(d, 0);
+  int64_t ws_rl = 1, rt_rl = 1;
+  for (int k = d - 1; k >= 1; --k) {
+    const int64_t r = rank[k], rk = rr[k], pn = rank[k - 1] * n[k - 1];
+    oX[k] = take(mk[k] * r);
+    oT[k] = take(r);
+    oG[k - 1] = take(pn * rk);
+    ws_rl = std::max(ws_rl, qr_ws_doubles(mk[k], r));
+    rt_rl = std::max(rt_rl, r * rk);
+  }
+  int64_t cM = 1, cws = 1, ctau = 1, cU = 1, cmn = 1, ccap = 1, cY = 1, cTn = 1, cwsq = 1;
+  auto sr_cap = [&](int k) {   // rows of the carried factor at step k
+    if (k == 0) return (int64_t)1;
+    return (rmax > 0 && rmax < rr[k]) ? (int64_t)rmax : rr[k];
+  };
+  for (int k = 0; k < d - 1; ++k) {
+    const int64_t nv = sr_cap(k) * n[k], q = rr[k + 1], mn = nv < q ? nv : q;
+    const int64_t cap = (rmax > 0 && rmax < mn) ? rmax : mn;
+    cM = std::max(cM, nv * q);
+    cws = std::max(cws, nv * (QBMAX + 1) + 2 * QBMAX * q);   // qr_ws_doubles at any m <= nv
+    ctau = std::max(ctau, q);
+    cU = std::max(cU, mn * mn);
+    cmn = std::max(cmn, mn);
+    ccap = std::max(ccap, cap);
+    cY = std::max(cY, nv * cap);
+    cTn = std::max(cTn, cap * q);
+    if (k > 0) cwsq = std::max(cwsq, mk[k] * QBMAX + 2 * QBMAX * sr_cap(k));
+  }
+  if (d > 1) cwsq = std::max(cwsq, mk[d - 1] * QBMAX + 2 * QBMAX * sr_cap(d - 1));
+  const int64_t o_wsrl = take(ws_rl), o_rt = take(rt_rl), o_M = take(cM), o_ws = take(cws),
+                o_tau = take(ctau), o_B = take(cM), o_U = take(cU), o_nrm = take(cmn),
+                o_sig = take(cmn), o_perm = take(cmn), o_sgn = take(ccap), o_Y = take(cY),
+                o_Tn0 = take(cTn), o_Tn1 = take(cTn), o_Z = take(cM), o_wsq = take(cwsq),
+                o_dl = take(2), o_one = take(1), o_flag = take(4), o_rho = take(d + 1);
+  double* W = A.get<double>(tot);
+  if ((e = A.e) != hipSuccess) return e;
+  auto at = [&](int64_t o) { return W + o; };
+
   const double* G0 = cores[0];
-  std::vector<double*> X(d, nullptr), tq(d, nullptr);
+  std::vector<const double*> X(d, nullptr), tq(d, nullptr);
   const double* Gk = d > 1 ? cores[d - 1] : nullptr;
   for (int k = d - 1; k >= 1 && e == hipSuccess; --k) {
-    const int64_t r = rr[k], m = n[k] * rr[k + 1], rk = m < r ? m : r, pn = rr[k - 1] * n[k - 1];
-    X[k] = A.get<double>(m * r);
-    tq[k] = A.get<double>(r);
-    double* ws = A.get<double>(qr_ws_doubles(m, r));
-    double* Rt = A.get<double>(r * rk);
-    double* Gpo = A.get<double>(pn * rk);
-    if ((e = A.e) != hipSuccess) break;
-    k_lq_absorb<<<1, NT, 0, s>>>(Gk, (int)r, (int)m, cores[k - 1], (int)pn, X[k], tq[k], ws, Rt,
-                                 Gpo);
+    const int64_t r = rank[k], m = mk[k], pn = rank[k - 1] * n[k - 1];
+    double* Xk = at(oX[k]);
+    double* tk = at(oT[k]);
+    double* Gpo = at(oG[k - 1]);
+    k_lq_absorb<<<1, NT, 0, s>>>(Gk, (int)r, (int)m, cores[k - 1], (int)pn, Xk, tk, at(o_wsrl),
+                                 at(o_rt), Gpo);
     e = hipGetLastError();
-    mk[k] = m;
-    rr[k] = rk;
+    X[k] = Xk;
+    tq[k] = tk;
     Gk = Gpo;   // core k - 1 with L absorbed
   }
   if (d > 1) G0 = Gk;
-  double* dl = A.get<double>(2);
-  if (e == hipSuccess) e = A.e;
+  double* dl = at(o_dl);
   if (e == hipSuccess) {
     k_norm_delta<<<1, NT, 0, s>>>(G0, n[0] * rr[1], eps, d - 1, dl);
     e = hipGetLastError();
@@ -765,10 +811,9 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
       e = hipMemcpyAsync(res[0], G0, sizeof(double) * n[0], hipMemcpyDeviceToDevice, s);
     return finish();
   }
-  double* one = A.get<double>(1);
-  int* flag = A.get<int>(4);
-  int* rho_d = A.get<int>(d + 1);
-  if ((e = A.e) != hipSuccess) return e;
+  double* one = at(o_one);
+  int* flag = (int*)at(o_flag);
+  int* rho_d = (int*)at(o_rho);
   const double h_one = 1.0;
   e = hipMemcpyAsync(one, &h_one, sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 4 * sizeof(int), s);
@@ -778,28 +823,20 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
     const int64_t q = rr[k + 1], nv = sr * n[k];
     const int64_t mn = nv < q ? nv : q;
     const int64_t cap = (rmax > 0 && rmax < mn) ? rmax : mn;
-    double* M = A.get<double>(nv * q);
-    double* ws = A.get<double>(qr_ws_doubles(nv, q));
-    double* tau = A.get<double>(q);
-    double* B = A.get<double>(nv * q);
-    double* U = A.get<double>(mn * mn);
-    double* nrm = A.get<double>(mn);
-    double* sig = A.get<double>(mn);
-    int* perm = A.get<int>(mn);
-    double* sgn = A.get<double>(cap);
-    double* Y = A.get<double>(nv * cap);
     res[k] = A.get<double>(nv * cap);
-    double* Tn = A.get<double>(cap * q);
-    double* Z = k > 0 ? A.get<double>(nv * q) : nullptr;
-    double* wsq = k > 0 ? A.get<double>(mk[k] * QBMAX + 2 * QBMAX * sr) : nullptr;
     if ((e = A.e) != hipSuccess) break;
+    double* Tn = at((k & 1) ? o_Tn1 : o_Tn0);
     if (k == 0)
-      k_round_first<<<1, NT, 0, s>>>(T, G0, (int)n[0], (int)q, dl, rmax, M, ws, tau, B, U, nrm,
-                                     sig, perm, sgn, flag, Y, res[k], Tn, rho_d + 1);
+      k_round_first<<<1, NT, 0, s>>>(T, G0, (int)n[0], (int)q, dl, rmax, at(o_M), at(o_ws),
+                                     at(o_tau), at(o_B), at(o_U), at(o_nrm), at(o_sig),
+                                     (int*)at(o_perm), at(o_sgn), flag, at(o_Y), res[k], Tn,
+                                     rho_d + 1);
     else
       k_round_step<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[k], X[k], tq[k], (int)mk[k], (int)n[k],
-                                    (int)q, dl, rmax, Z, wsq, M, ws, tau, B, U, nrm, sig, perm,
-                                    sgn, flag, Y, res[k], Tn, rho_d + k + 1);
+                                    (int)q, dl, rmax, at(o_Z), at(o_wsq), at(o_M), at(o_ws),
+                                    at(o_tau), at(o_B), at(o_U), at(o_nrm), at(o_sig),
+                                    (int*)at(o_perm), at(o_sgn), flag, at(o_Y), res[k], Tn,
+                                    rho_d + k + 1);
     e = hipGetLastError();
     int rk = 0;
     read_back(&rk, rho_d + k + 1, sizeof(int));
@@ -811,9 +848,9 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
   if (e == hipSuccess) {
     const int k = d - 1;
     res[k] = A.get<double>(sr * n[k]);
-    double* wsq = A.get<double>(mk[k] * QBMAX + 2 * QBMAX * sr);
     if ((e = A.e) == hipSuccess) {
-      k_round_last_q<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[k], X[k], tq[k], (int)n[k], wsq, res[k]);
+      k_round_last_q<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[k], X[k], tq[k], (int)n[k], at(o_wsq),
+                                      res[k]);
       e = hipGetLastError();
     }
   }
