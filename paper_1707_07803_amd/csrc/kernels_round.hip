@@ -459,11 +459,12 @@ __global__ __launch_bounds__(NT) void k_round_first(const double* T, const doubl
             rho_out, arena, &srho);
 }
 
-// Left-to-right step at core 0 < k < d - 1: the carried factor T (s x rk)
+// Left-to-right step at core 0 < k < d - 1: the carried factor T (s x rk, s
+// read from the device, where the previous step left it)
 // times the orthogonalised core Q^T (rk x m, m = n q), formed as
 // (Q [T^T; 0])^T with the stored reflectors, reshaped (s n) x q column-major,
 // then its truncated SVD.
-__global__ __launch_bounds__(NT) void k_round_step(const double* T, int s, int rk, const double* X,
+__global__ __launch_bounds__(NT) void k_round_step(const double* T, const int* s_dev, int rk, const double* X,
                                                    const double* tq, int m, int n, int q,
                                                    const double* delta_p, int rmax, double* Z,
                                                    double* wsq, double* M, double* ws, double* tau,
@@ -472,6 +473,7 @@ __global__ __launch_bounds__(NT) void k_round_step(const double* T, int s, int r
                                                    double* core, double* Tn, int* rho_out) {
   __shared__ double arena[AR];
   __shared__ int srho;
+  const int s = s_dev[0];   // the rank the previous step kept
   const int64_t nv = (int64_t)s * n;
   for (int64_t e = threadIdx.x; e < (int64_t)m * s; e += NT) {
     const int64_t a = e / m, j = e % m;
@@ -490,10 +492,11 @@ __global__ __launch_bounds__(NT) void k_round_step(const double* T, int s, int r
 
 // The last core takes the carried factor: out (s x n) = T (s x rk) Q^T, i.e.
 // the column-major n x s matrix Q [T^T; 0], which has the same memory.
-__global__ __launch_bounds__(NT) void k_round_last_q(const double* T, int s, int rk, const double* X,
-                                                     const double* tq, int n, double* wsq,
-                                                     double* out) {
+__global__ __launch_bounds__(NT) void k_round_last_q(const double* T, const int* s_dev, int rk,
+                                                     const double* X, const double* tq, int n,
+                                                     double* wsq, double* out) {
   __shared__ double arena[AR];
+  const int s = s_dev[0];
   for (int64_t e = threadIdx.x; e < (int64_t)n * s; e += NT) {
     const int64_t a = e / n, j = e % n;
     out[e] = j < rk ? T[a * rk + j] : 0.0;
@@ -697,8 +700,8 @@ hipError_t launch_round_last(const double* T, int rp, int cp, const int* pm, int
 // orthogonalised cores stay as Householder reflectors), delta from the first
 // core's norm, then left-to-right truncated SVDs of the carried factor times
 // each core (k_round_first, k_round_step); the last core takes the remaining
-// factor (k_round_last_q).  One workgroup per step; each step's rank is read
-// back to size the next.  The zero matrix (|A|_F = 0 after the first pass)
+// factor (k_round_last_q).  One workgroup per step; each step reads the rank
+// the previous one kept from the device.  The zero matrix (|A|_F = 0 after the first pass)
 // gives zero rank-1 cores.  Every buffer but the result cores is carved from
 // one allocation sized on the host from the ranks of the first pass (exact)
 // and the caps of the second (each kept rank is at most the first pass's).
@@ -817,10 +820,11 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
   const double h_one = 1.0;
   e = hipMemcpyAsync(one, &h_one, sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 4 * sizeof(int), s);
+  // no host round trip between steps: each kernel reads the rank the previous
+  // one kept from rho_d, and the result cores are sized by the caps
   const double* T = one;
-  int64_t sr = 1;   // rows of T (the kept rank so far)
   for (int k = 0; k < d - 1 && e == hipSuccess; ++k) {
-    const int64_t q = rr[k + 1], nv = sr * n[k];
+    const int64_t q = rr[k + 1], nv = sr_cap(k) * n[k];
     const int64_t mn = nv < q ? nv : q;
     const int64_t cap = (rmax > 0 && rmax < mn) ? rmax : mn;
     res[k] = A.get<double>(nv * cap);
@@ -832,28 +836,26 @@ hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t
                                      (int*)at(o_perm), at(o_sgn), flag, at(o_Y), res[k], Tn,
                                      rho_d + 1);
     else
-      k_round_step<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[k], X[k], tq[k], (int)mk[k], (int)n[k],
+      k_round_step<<<1, NT, 0, s>>>(T, rho_d + k, (int)rr[k], X[k], tq[k], (int)mk[k], (int)n[k],
                                     (int)q, dl, rmax, at(o_Z), at(o_wsq), at(o_M), at(o_ws),
                                     at(o_tau), at(o_B), at(o_U), at(o_nrm), at(o_sig),
                                     (int*)at(o_perm), at(o_sgn), flag, at(o_Y), res[k], Tn,
                                     rho_d + k + 1);
     e = hipGetLastError();
-    int rk = 0;
-    read_back(&rk, rho_d + k + 1, sizeof(int));
-    if (e != hipSuccess) break;
-    out->ranks[k + 1] = rk;
     T = Tn;
-    sr = rk;
   }
   if (e == hipSuccess) {
     const int k = d - 1;
-    res[k] = A.get<double>(sr * n[k]);
+    res[k] = A.get<double>(sr_cap(k) * n[k]);
     if ((e = A.e) == hipSuccess) {
-      k_round_last_q<<<1, NT, 0, s>>>(T, (int)sr, (int)rr[k], X[k], tq[k], (int)n[k], at(o_wsq),
+      k_round_last_q<<<1, NT, 0, s>>>(T, rho_d + k, (int)rr[k], X[k], tq[k], (int)n[k], at(o_wsq),
                                       res[k]);
       e = hipGetLastError();
     }
   }
+  std::vector<int> kept(d + 1, 1);
+  read_back(kept.data() + 1, rho_d + 1, sizeof(int) * (d - 1));
+  for (int k = 1; k < d; ++k) out->ranks[k] = kept[k];
   return finish();
 }
 
