@@ -572,7 +572,7 @@ def main():
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md and not launched",
+                                   "designed but not launched",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.batched_full:
