@@ -571,7 +571,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+        print(json.dumps({"error": "this library runs on one GPU; multi-GPU sharding is "
                                    "designed but not launched",
                           "n_gpus": args.gpus}))
         sys.exit(2)
