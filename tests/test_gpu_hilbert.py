@@ -69,6 +69,8 @@ CASES = {
     "mixed_modes": (chain([3, 1, 4, 2], [2, 5, 1, 3], [6, 9, 5]), 1e-10, 0),
     "wide_bonds": (chain([2, 2, 2, 2], [2, 2, 2, 2], [40, 70, 30]), 1e-10, 0),
     "d2": (chain([7, 5], [3, 4], [9]), 1e-10, 0),
+    # an LQ panel of 16 * 80 = 1280 rows: too tall for the LDS panel path
+    "tall_panel": (chain([4] * 4, [4] * 4, [80, 80, 80]), 1e-10, 0),
 }
 
 
