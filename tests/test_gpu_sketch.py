@@ -148,3 +148,25 @@ def test_paper_orientation_with_sketch_matches_mirror():
     hl.set_omega(om)
     hf.set_omega(om)
     np.testing.assert_array_equal(hf.run()[0], hl.run()[0])
+
+
+def test_known_spectrum_fp64_and_bf16_against_oracle():
+    """The known-spectrum workload (products of rank 125, rounding 1e-12): the
+    sketched FP64 solve follows the oracle's sketched mode; with BF16 storage
+    the compressed cores are written in BF16 and the result stays within the
+    BF16 path's tolerance."""
+    W = wl.spectrum()
+    om = omega_for(W.cores, W.K, W.omega_seed)
+    ref = o.tnrsvd(W.cores, W.k, W.p, W.q, omega=om, eps=W.eps_by_precision["f64"], rmax=W.rmax,
+                   sketch_rank=16, sketch_seed=5).sigma
+    s64, _ = solve(W.cores, W.k, W.p, W.q, om, 16, seed=5, eps=W.eps_by_precision["f64"],
+                   rmax=W.rmax)
+    print("spectrum sketched f64 vs oracle", rel(s64, ref))
+    assert rel(s64, ref) < 1e-10
+    from paper_1707_07803_amd import TNrSVD, omega_flat
+    h = TNrSVD(to_device(W.cores, "f32"), W.k, W.p, W.q, seed=5, precision="bf16",
+               round_tol=W.eps_by_precision["bf16"], max_rank=W.rmax, sketch_rank=16)
+    h.set_omega(omega_flat(*om))
+    sb = h.run()[0]
+    print("spectrum sketched bf16 vs prescribed", rel(sb, W.sigma_exact[: W.k]))
+    assert rel(sb, W.sigma_exact[: W.k]) < 1e-2
