@@ -60,6 +60,8 @@ def parse():
                     help="also time the opt-in sketched product truncation at this rank (0: no)")
     ap.add_argument("--batched-full", action="store_true",
                     help="time the whole 512-MPO uneven batch once (minutes) and exit")
+    ap.add_argument("--only-configs", action="store_true",
+                    help="time only the other workloads (large, batched subset, gradient)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the timings of the other workloads (plain FP64, large, "
                          "batched uneven subset, gradient)")
@@ -590,6 +592,9 @@ def main():
               "gcn_arch": getattr(props, "gcnArchName", ""),
               "total_memory_GiB": round(props.total_memory / 2 ** 30, 1)}
     print(f"[bench] device {device}", file=sys.stderr, flush=True)
+    if args.only_configs:
+        print(json.dumps({"other_configs": other_configs(), "device": device}))
+        return
     sparse = None
     if args.sparse != "off":
         sparse = sparse_section(args.sparse_steps, not args.no_cpu_baseline)
