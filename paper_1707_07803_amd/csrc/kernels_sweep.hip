@@ -315,15 +315,56 @@ __device__ __forceinline__ void reg_absorb_dispatch(int spy, double (&x)[QMR][QN
 }
 
 // Flat-tree TSQR of a tall panel (m rows > 256, n <= 128 columns), run by the
-// right-to-left pass as a sequence of register QR jobs: leaf QRs of consecutive
-// 256-row chunks, each leaf's R merged into the running R by a QR of the two
-// stacked triangles.  Workspace layout (in the core's W slab):
+// right-to-left pass as register QR jobs: leaf QRs of consecutive 256-row
+// chunks (k_rl_leaves, all leaves at once), then each leaf's R merged into the
+// running R by a QR of the two stacked triangles, in leaf order.  Workspace layout (in the core's W slab):
 //   leaf c reflectors   W + c * 256 * n            (column-major, ld = rows of leaf c)
 //   merge c reflectors  W + (nc + c) * 256 * n     (ld = rows of merge c), c >= 1
-//   Racc, Rtmp          W + 2 nc 256 n, + n * n     (row-major)
+//   Racc                W + 2 nc 256 n              (row-major; n * n after it unused)
 //   taus                W + (2 nc 256 + 2 n) n: leaf c at + c n, merge c at + (nc + c) n
+//   R of leaf c >= 1    W + (2 nc 256 + 2 n) n + 2 nc n + (c - 1) n n   (row-major)
 // The final R goes to the L slab; tsqr_apply replays the tree in the
 // left-to-right pass.
+
+// TSQR leaves of the last core's tall panel, one workgroup per (MPO, leaf):
+// leaf c is the register QR of rows [256 c, 256 c + 256) of the panel.  Its
+// reflectors and scalars go where the flat tree keeps them, its R to Racc
+// (leaf 0) or to the slot of leaf c >= 1 after the taus:
+//   W + (2 nc 256 + 2 n) n + 2 nc n + (c - 1) n n   (row-major n x n).
+// The last-core phase of the pass then runs the merges 1 .. nc-1 in order, so
+// the factors are those of the sequential tree.  The test for the TSQR path
+// repeats the pass's own, on the same descriptors; other MPOs exit at once.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rl_leaves(const MpoDesc* mpos, const CoreDesc* cores,
+                                                  int op, const int* pr, const T* __restrict__ Z,
+                                                  double* Wd) {
+  __shared__ double arena[ARENA];
+  const MpoDesc md = mpos[blockIdx.x];
+  const int i = md.d - 1;
+  const CoreDesc cd = cores[md.c0 + i];
+  const int n = op == 0 ? cd.I : cd.J;
+  const int P = pr[md.r0 + i];
+  const int Pn = pr[md.r0 + i + 1];
+  const int m = n * md.K;
+  if (P < 1 || P > cd.RA * cd.xcap || Pn < 1 || Pn > cd.RA2 * cd.xcap2 || md.K > Pn ||
+      m > ARENA - 64 - 2 * QBMAX * QBMAX)
+    return;                                   // the pass reports the shape error
+  if (!(i > 0 && P <= QCOLS && m > QROWS && m <= 16 * QROWS)) return;
+  const int nc = (m + QROWS - 1) / QROWS;
+  const int c = blockIdx.y;
+  if (c >= nc) return;
+  double* Xt = Wd + cd.w_off;
+  double* ws_tau = Xt + (int64_t)(2 * nc * QROWS + 2 * P) * P;
+  double* Rdst = c == 0 ? Xt + (int64_t)2 * nc * QROWS * P
+                        : ws_tau + (int64_t)2 * nc * P + (int64_t)(c - 1) * P * P;
+  const int r0 = c * QROWS;
+  const int mrows = (m - r0) < QROWS ? (m - r0) : QROWS;
+  double x[QMR][QNC];
+  reg_load_plain<T>(x, Z + cd.z_off, m, P, r0, mrows);
+  reg_geqr(x, mrows, P, arena, arena + ARENA - 32, ws_tau + (int64_t)c * P,
+           Xt + (int64_t)c * QROWS * P, mrows, Rdst, arena + 2 * QROWS,
+           arena + 2 * QROWS + QCOLS);
+}
 
 // ---------------------------------------------------------------------------
 // Right-to-left pass: absorb + QR of every core, one workgroup per MPO.
@@ -375,16 +416,16 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
       // and for a tall panel the TSQR leaves and merges (leaf 0, leaf 1,
       // merge 1, leaf 2, merge 2, ...).
       const int nc = tsqr ? (m + QROWS - 1) / QROWS : 1;
-      const int njobs = tsqr ? 2 * nc - 1 : 1;
+      // the TSQR leaves were factorised in parallel by k_rl_leaves: here only
+      // the merges 1 .. nc-1 remain, in order
+      const int njobs = tsqr ? nc - 1 : 1;
       double* ws_tau = Xt + (int64_t)(2 * nc * QROWS + 2 * P) * P;
       double* Racc = Xt + (int64_t)2 * nc * QROWS * P;
-      double* Rtmp = Racc + (int64_t)P * P;
-      int kacc = 0, kleaf = 0;
+      const double* Rleaf = ws_tau + (int64_t)2 * nc * P;
+      int kacc = tsqr ? (QROWS < P ? QROWS : P) : 0;   // leaf 0 has QROWS rows
       for (int job = 0; job < njobs; ++job) {
         double x[QMR][QNC];   // the register panel, dead between jobs
-        // job -> (leaf c) or (merge c): leaf 0 is job 0, then leaf c = job 2c - 1, merge c = job 2c
-        const bool merge = tsqr && job > 0 && (job % 2 == 0);
-        const int c = tsqr ? (job + 1) / 2 : 0;
+        const int c = tsqr ? job + 1 : 0;                 // merge c
         int mrows, ldv;
         double* Vdst;
         double* Rdst;
@@ -402,23 +443,17 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
           Vdst = Xt;
           Rdst = L + cd.l_off;
           taud = tau + cd.tau_off;
-        } else if (!merge) {
-          const int r0 = c * QROWS;
-          mrows = (m - r0) < QROWS ? (m - r0) : QROWS;
-          reg_load_plain<T>(x, Zc, m, P, r0, mrows);
-          ldv = mrows;
-          Vdst = Xt + (int64_t)c * QROWS * P;
-          Rdst = c == 0 ? Racc : Rtmp;
-          taud = ws_tau + (int64_t)c * P;
-          kleaf = mrows < P ? mrows : P;
         } else {
-          // stack [Racc; Rtmp] column-major into this merge's (not yet written)
-          // reflector block, then load it like a plain panel
+          // stack [Racc; R of leaf c] column-major into this merge's (not yet
+          // written) reflector block, then load it like a plain panel
+          const int mc = (m - c * QROWS) < QROWS ? (m - c * QROWS) : QROWS;
+          const int kleaf = mc < P ? mc : P;
+          const double* Rc = Rleaf + (int64_t)(c - 1) * P * P;
           mrows = kacc + kleaf;
           Vdst = Xt + (int64_t)(nc + c) * QROWS * P;
           for (int e = tid; e < mrows * P; e += NT) {
             const int col = e / mrows, r = e % mrows;
-            Vdst[e] = r < kacc ? Racc[r * P + col] : Rtmp[(r - kacc) * P + col];
+            Vdst[e] = r < kacc ? Racc[r * P + col] : Rc[(r - kacc) * P + col];
           }
           __syncthreads();
           reg_load_plain<double>(x, Vdst, mrows, P);
@@ -430,12 +465,7 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
         reg_geqr(x, mrows, P, vb, tb, taud, Vdst, ldv, Rdst, arena + 2 * QROWS,
                  arena + 2 * QROWS + QCOLS);
         __syncthreads();
-        if (tsqr) {
-          if (job == 0)
-            kacc = kleaf;
-          else if (merge)
-            kacc = mrows < P ? mrows : P;
-        }
+        if (tsqr) kacc = mrows < P ? mrows : P;
       }
       const int k = m < P ? m : P;
       if (tid == 0) {
@@ -673,6 +703,8 @@ constexpr int LR_SC = 990;    // sort / sign buffers (6144*2 + 4096 + 3*990 + 80
 
 static_assert(LR_MB + LR_VB + LR_UB + 3 * LR_SC + 16 + 64 <= ARENA, "left-to-right LDS carve");
 static_assert(ARENA == kSweepArena, "arena size shared with the host plan");
+static_assert(QROWS == kRegRows && QCOLS == kRegCols && 16 * QROWS == kTsqrLeavesMax * kRegRows,
+              "register panel shape shared with the host plan");
 static_assert(LR_SC == kSortCap, "sort capacity shared with the host plan");
 
 struct ScratchLayout {
@@ -905,9 +937,11 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
 
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
-                          double* L, double* tau, int* err, hipStream_t s) {
+                          double* L, double* tau, int* err, int leaf_nc, hipStream_t s) {
   by_dtype(dtype, [&](auto* t) {
     using T = elem_t<decltype(t)>;
+    if (leaf_nc > 1)
+      k_rl_leaves<T><<<dim3(batch, leaf_nc), NT, 0, s>>>(mpos, cores, op, pr, (const T*)Z, Wd);
     k_rl_pass<T, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,
                                          err);
     k_rl_pass<T, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,

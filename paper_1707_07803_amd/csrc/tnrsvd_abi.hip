@@ -52,6 +52,7 @@ constexpr int kKinds = 7;  // contract, rl, lr, form_u, load_omega, copy_y0, ske
 
 struct tnrsvd_s {
   int device = 0;
+  int leaf_nc = 0;   // most TSQR leaves of a last-core panel over the batch (grid of k_rl_leaves)
   // TNRSVD_K_FIRST: the caller's MPO b was read reversed (core i of the caller is
   // core d - 1 - i here, rank legs swapped); paper_shape[b] keeps the caller's cores
   int orientation = 0;
@@ -373,9 +374,16 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
       int64_t wneed = nmax * P2pad * P;
       if (i == dm - 1) {
         // a tall last-core panel may be factorised by TSQR: leaf + merge
-        // reflectors (2 nc blocks of 256 x P), two P x P factors, 2 nc taus
-        const int64_t nc = (nmax * K + 255) / 256;
-        wneed = std::max(wneed, (2 * nc * 256 + 2 * P) * P + 2 * nc * P);
+        // reflectors (2 nc blocks of 256 x P), two P x P factors, 2 nc taus,
+        // and the R factors of leaves 1 .. nc-1 (P x P each)
+        // (the rank in force may be below P and the mode below nmax, so the
+        // leaf count and width are bounded by the register panel's limits)
+        const int64_t nc = (nmax * K + kRegRows - 1) / kRegRows;
+        const int64_t ncl = std::min<int64_t>(nc, kTsqrLeavesMax);
+        const int64_t Pl = std::min<int64_t>(P, kRegCols);
+        wneed = std::max(wneed, (2 * nc * kRegRows + 2 * P) * P + 2 * nc * P +
+                                    (ncl > 1 ? (ncl - 1) * Pl * Pl : 0));
+        if (ncl > 1) h->leaf_nc = std::max(h->leaf_nc, (int)ncl);
       }
       // the blocked QR of the global path needs m qb + 2 qb P more (qb <= 32)
       wneed += nmax * P2pad * 32 + 2 * 32 * P;
@@ -790,7 +798,7 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   {
     Timed tm(h, 1);
     e = launch_rl_pass(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->rho, h->ldm, h->Z, h->dtype,
-                       h->W, h->L, h->tau, h->err, h->stream);
+                       h->W, h->L, h->tau, h->err, h->leaf_nc, h->stream);
   }
   TRY(dev_check(e, "right-to-left sweep"));
   Timed tm(h, 2);

@@ -103,6 +103,9 @@ constexpr int kSweepThreads = 512;
 constexpr int kMaxK = 256;
 constexpr int kRoundRankMax = 4096;  // bond ranks taken by the rounding of a general MPO
 constexpr int kSweepArena = 19456;   // doubles of static LDS per sweep workgroup
+// register panels of the sweeps: at most 256 rows x 128 columns; a last-core
+// panel of up to 16 such row blocks is factorised by TSQR
+constexpr int kRegRows = 256, kRegCols = 128, kTsqrLeavesMax = 16;
 constexpr int kSortCap = 990;        // largest panel row count the sweep sorts
 
 }  // namespace tnr
@@ -184,7 +187,7 @@ hipError_t launch_copy_y0(const MpoDesc* mpos, const CoreDesc* cores, const int*
                           int64_t max_out, hipStream_t s);
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
-                          double* L, double* tau, int* err, hipStream_t s);
+                          double* L, double* tau, int* err, int leaf_nc, hipStream_t s);
 hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* rho, const int* ldm, int* xr, const double* Wd,
                           const double* tau, double* scratch, void* Xout, int out_dtype,
