@@ -447,6 +447,25 @@ tnrsvd_status tnrsvd_round_mpo(const tnrsvd_mpo* a, double round_tol, int max_ra
  * Errors: E_INVALID (null argument, dtype), E_SHAPE (ranks, shapes), E_DEVICE.
  */
 tnrsvd_status tnrsvd_complex_embed(const tnrsvd_mpo* a, void* const* out, void* stream);
+/*
+ * tnrsvd_mpo_add -- the MPO of the sum of two matrices given as MPOs with the
+ * same row and column modes (Sec. 3: ranks add).  a and b: device cores
+ * (r, I, J, r') of the same dtype (F64 or F32), rank[0] = rank[d] = 1.  The
+ * sum C has ranks 1, ra_1 + rb_1, ..., ra_{d-1} + rb_{d-1}, 1: its first core
+ * is [A_1 B_1] along the right rank leg, its last core [A_d; B_d] along the
+ * left one, and every inner core is block diagonal, diag(A_k, B_k), with
+ * zeros elsewhere; for d = 1 the single core is A_1 + B_1.  Entries are
+ * copied exactly (d = 1: one correctly rounded addition).  The ranks are not
+ * reduced: tnrsvd_round_mpo rounds the sum.  out[k]: caller-allocated DEVICE
+ * buffer of core k of C, ((k = 0) ? 1 : ra_k + rb_k) x I_k x J_k x
+ * ((k = d-1) ? 1 : ra_{k+1} + rb_{k+1}) elements in C order; a and b are
+ * read only.  Synchronises `stream` (hipStream_t, NULL: null stream).
+ * Errors: E_INVALID (null argument, dtype), E_SHAPE (d or modes differ, end
+ * ranks not 1, a rank below 1, a core of C with more than 2^40 entries or a
+ * rank above 2^20), E_DEVICE.
+ */
+tnrsvd_status tnrsvd_mpo_add(const tnrsvd_mpo* a, const tnrsvd_mpo* b, void* const* out,
+                             void* stream);
 tnrsvd_status tnrsvd_rounded_ranks(tnrsvd_rounded_t r, int64_t* ranks);
 tnrsvd_status tnrsvd_rounded_copy(tnrsvd_rounded_t r, int k, double* dst);
 tnrsvd_status tnrsvd_rounded_destroy(tnrsvd_rounded_t r);

@@ -7,8 +7,8 @@ package holds the build script and a thin ctypes binding.
 """
 
 from .tnrsvd import (TNrSVD, TNrSVDError, TNrSVDFunction, solve, sparse_to_mpo, sparse_round,  # noqa: F401
-                     round_mpo, complex_embed, solve_complex,
+                     round_mpo, complex_embed, solve_complex, mpo_add,
                      load_library, omega_flat, LIB_PATH, EXPORTS, PRECISIONS, ORIENTATIONS)
 
-__all__ = ["TNrSVD", "TNrSVDError", "TNrSVDFunction", "solve", "sparse_to_mpo", "sparse_round", "round_mpo", "complex_embed", "solve_complex", "load_library", "omega_flat", "LIB_PATH",
+__all__ = ["TNrSVD", "TNrSVDError", "TNrSVDFunction", "solve", "sparse_to_mpo", "sparse_round", "round_mpo", "complex_embed", "solve_complex", "mpo_add", "load_library", "omega_flat", "LIB_PATH",
            "EXPORTS", "PRECISIONS", "ORIENTATIONS"]

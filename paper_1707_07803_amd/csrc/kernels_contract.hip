@@ -323,6 +323,51 @@ hipError_t launch_complex_embed(const void* in, int dtype, void* out, int64_t R0
   return hipGetLastError();
 }
 
+// MPO addition (Sec. 3), one core of the sum C = A + B per launch: ranks add,
+// so an inner core is block diagonal, diag(A_k, B_k); the first core stacks A's
+// and B's right rank legs, the last core their left rank legs, and for d = 1 the
+// single core is A_1 + B_1.  Output (a, i, j, b) in C order over
+// (ra0 + rb0 or 1) x I x J x (ra1 + rb1 or 1); a left (right) index belongs to
+// A below ra0 (ra1), to B from there on, and to both on the first (last) core.
+template <typename T>
+__global__ void k_mpo_add(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
+                          int64_t ra0, int64_t rb0, int64_t I, int64_t J, int64_t ra1,
+                          int64_t rb1, int first, int last) {
+  const int64_t L = first ? 1 : ra0 + rb0, Rr = last ? 1 : ra1 + rb1;
+  const int64_t n = L * I * J * Rr;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e % Rr, ij = (e / Rr) % (I * J), a = e / (Rr * I * J);
+    const bool la = first || a < ra0, lb = first || a >= ra0;
+    const bool ka = last || b < ra1, kb = last || b >= ra1;
+    double v = 0.0;
+    if (la && ka) {
+      const int64_t aa = first ? 0 : a, ba = last ? 0 : b;
+      v += (double)A[(aa * I * J + ij) * (last ? 1 : ra1) + ba];
+    }
+    if (lb && kb) {
+      const int64_t ab = first ? 0 : a - ra0, bb = last ? 0 : b - ra1;
+      v += (double)B[(ab * I * J + ij) * (last ? 1 : rb1) + bb];
+    }
+    C[e] = T(v);
+  }
+}
+
+hipError_t launch_mpo_add(const void* A, const void* B, void* C, int dtype, int64_t ra0,
+                          int64_t rb0, int64_t I, int64_t J, int64_t ra1, int64_t rb1, int first,
+                          int last, hipStream_t s) {
+  const int64_t n = (first ? 1 : ra0 + rb0) * I * J * (last ? 1 : ra1 + rb1);
+  if (n <= 0) return hipSuccess;
+  const int g = grid_for(n, 256, 8192);
+  if (dtype == kF64)
+    k_mpo_add<double><<<g, 256, 0, s>>>((const double*)A, (const double*)B, (double*)C, ra0, rb0,
+                                        I, J, ra1, rb1, first, last);
+  else
+    k_mpo_add<float><<<g, 256, 0, s>>>((const float*)A, (const float*)B, (float*)C, ra0, rb0, I, J,
+                                       ra1, rb1, first, last);
+  return hipGetLastError();
+}
+
 hipError_t launch_check_finite(const void* in, int dtype, int64_t n, int* flag, hipStream_t s) {
   const int g = grid_for(n, 256, 4096);
   if (dtype == 0)

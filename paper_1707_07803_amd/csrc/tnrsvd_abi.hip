@@ -1664,6 +1664,41 @@ tnrsvd_status tnrsvd_complex_embed(const tnrsvd_mpo* a, void* const* out, void* 
   return dev_check(hipStreamSynchronize(s), "synchronise");
 }
 
+tnrsvd_status tnrsvd_mpo_add(const tnrsvd_mpo* a, const tnrsvd_mpo* b, void* const* out,
+                             void* stream) {
+  g_err.clear();
+  if (!a || !b || !out) return fail(TNRSVD_E_INVALID, "null argument");
+  if (a->d < 1 || b->d != a->d) return fail(TNRSVD_E_SHAPE, "d must be >= 1 and equal");
+  for (const tnrsvd_mpo* m : {a, b})
+    if (!m->rank || !m->rows || !m->cols || !m->core)
+      return fail(TNRSVD_E_INVALID, "null rank/rows/cols/core array");
+  if ((a->dtype != TNRSVD_F64 && a->dtype != TNRSVD_F32) || b->dtype != a->dtype)
+    return fail(TNRSVD_E_INVALID, "both MPOs must be F64 or both F32");
+  const int d = a->d;
+  for (const tnrsvd_mpo* m : {a, b})
+    if (m->rank[0] != 1 || m->rank[d] != 1)
+      return fail(TNRSVD_E_SHAPE, "rank[0] and rank[d] must be 1");
+  for (int k = 0; k < d; ++k) {
+    if (a->rows[k] < 1 || a->cols[k] < 1 || b->rows[k] != a->rows[k] ||
+        b->cols[k] != a->cols[k] || a->rank[k + 1] < 1 || b->rank[k + 1] < 1 || !a->core[k] ||
+        !b->core[k] || !out[k])
+      return fail(TNRSVD_E_SHAPE, "core %d: modes differ, bad rank or null pointer", k);
+    const int64_t L = k == 0 ? 1 : a->rank[k] + b->rank[k];
+    const int64_t R = k == d - 1 ? 1 : a->rank[k + 1] + b->rank[k + 1];
+    if (L > ((int64_t)1 << 20) || R > ((int64_t)1 << 20) ||
+        L * a->rows[k] * a->cols[k] * R > ((int64_t)1 << 40))
+      return fail(TNRSVD_E_SHAPE, "core %d of the sum too large", k);
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  for (int k = 0; k < d; ++k)
+    TRY(dev_check(launch_mpo_add(a->core[k], b->core[k], out[k],
+                                 a->dtype == TNRSVD_F64 ? kF64 : kF32, a->rank[k], b->rank[k],
+                                 a->rows[k], a->cols[k], a->rank[k + 1], b->rank[k + 1], k == 0,
+                                 k == d - 1, s),
+                  "MPO addition"));
+  return dev_check(hipStreamSynchronize(s), "synchronise");
+}
+
 tnrsvd_status tnrsvd_rounded_ranks(tnrsvd_rounded_t r, int64_t* ranks) {
   if (!r || !ranks) return fail(TNRSVD_E_INVALID, "null argument");
   for (int k = 0; k <= r->d; ++k) ranks[k] = r->ranks[k];

@@ -169,6 +169,9 @@ constexpr int kSketchMaxD = 256;
 hipError_t launch_sketch(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op, int* pr,
                          void* Z, int dtype, int ell, uint64_t seed, uint64_t cbase,
                          const int* nm, const int64_t* off, double* ws, int* err, hipStream_t s);
+hipError_t launch_mpo_add(const void* A, const void* B, void* C, int dtype, int64_t ra0,
+                          int64_t rb0, int64_t I, int64_t J, int64_t ra1, int64_t rb1, int first,
+                          int last, hipStream_t s);
 hipError_t launch_complex_embed(const void* in, int dtype, void* out, int64_t R0, int64_t I,
                                 int64_t J, int64_t R1, int first, int last, hipStream_t s);
 hipError_t launch_swap_legs(const void* in, int dtype, void* out, int64_t R0, int64_t I, int64_t J,

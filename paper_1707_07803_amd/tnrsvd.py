@@ -27,7 +27,7 @@ EXPORTS = [
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
-    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_complex_embed", "tnrsvd_rounded_ranks",
+    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_complex_embed", "tnrsvd_mpo_add", "tnrsvd_rounded_ranks",
     "tnrsvd_rounded_copy", "tnrsvd_rounded_destroy", "tnrsvd_last_error", "tnrsvd_version",
 ]
 
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(ctypes.c_void_p)]
     L.tnrsvd_complex_embed.argtypes = [ctypes.POINTER(_Mpo), ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.c_void_p]
+    L.tnrsvd_mpo_add.argtypes = [ctypes.POINTER(_Mpo), ctypes.POINTER(_Mpo),
+                                 ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
     L.tnrsvd_rounded_ranks.argtypes = [ctypes.c_void_p, P64]
     L.tnrsvd_rounded_copy.argtypes = [ctypes.c_void_p, I, ctypes.c_void_p]
     L.tnrsvd_rounded_destroy.argtypes = [ctypes.c_void_p]
@@ -485,6 +487,48 @@ def complex_embed(cores):
     op = (ctypes.c_void_p * d)(*[t.data_ptr() for t in outs])
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     _check(L.tnrsvd_complex_embed(ctypes.byref(st), op, stream))
+    return outs
+
+
+def _mpo_view(cores, dtype):
+    """A tnrsvd_mpo describing device tensors `cores` (kept alive by the caller)."""
+    d = len(cores)
+    st = _Mpo()
+    keep = ((ctypes.c_int64 * (d + 1))(*([int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores])),
+            (ctypes.c_int64 * d)(*[int(c.shape[1]) for c in cores]),
+            (ctypes.c_int64 * d)(*[int(c.shape[2]) for c in cores]),
+            (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores]))
+    st.d, st.rank, st.rows, st.cols, st.core = d, *keep
+    st.dtype = dtype
+    return st, keep
+
+
+def mpo_add(a, b):
+    """The MPO of A + B (device tensors (r, I, J, r'), both float64 or both
+    float32, equal modes), computed by tnrsvd_mpo_add: ranks add, inner cores
+    block diagonal.  Returns new device tensors; round them with round_mpo."""
+    import torch
+    L = load_library()
+    if len(a) != len(b) or not a:
+        raise TNrSVDError(-2, "both MPOs need the same number of cores")
+    if a[0].dtype not in (torch.float64, torch.float32) or any(
+            c.dtype != a[0].dtype for c in list(a) + list(b)):
+        raise TNrSVDError(-1, "cores must all be float64 or all float32")
+    a = [c.contiguous() for c in a]
+    b = [c.contiguous() for c in b]
+    dt = F64 if a[0].dtype == torch.float64 else F32
+    sa, ka = _mpo_view(a, dt)
+    sb, kb = _mpo_view(b, dt)
+    d = len(a)
+    outs = []
+    for k in range(d):
+        left = 1 if k == 0 else int(a[k].shape[0] + b[k].shape[0])
+        right = 1 if k == d - 1 else int(a[k].shape[3] + b[k].shape[3])
+        outs.append(torch.empty((left, int(a[k].shape[1]), int(a[k].shape[2]), right),
+                                dtype=a[0].dtype, device=a[0].device))
+    op = (ctypes.c_void_p * d)(*[t.data_ptr() for t in outs])
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(L.tnrsvd_mpo_add(ctypes.byref(sa), ctypes.byref(sb), op, stream))
     return outs
 
 

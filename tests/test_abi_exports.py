@@ -112,8 +112,9 @@ def test_binding_structs_match_the_header(tmp_path):
 
 
 def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
-    """tnrsvd_create (orientation, sketch_rank), tnrsvd_round_mpo and
-    tnrsvd_complex_embed check their arguments before any device call."""
+    """tnrsvd_create (orientation, sketch_rank), tnrsvd_round_mpo,
+    tnrsvd_complex_embed and tnrsvd_mpo_add check their arguments before any
+    device call."""
     from paper_1707_07803_amd import tnrsvd as binding
     P64 = ctypes.c_int64
     Mpo, Opts = binding._Mpo, binding._Opts
@@ -176,3 +177,21 @@ def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
     assert emb(ctypes.byref(mpo([1, 2, 2], [2, 2], [2, 2])), outs, None) == -2
     assert emb(ctypes.byref(mpo([1, 2, 1], [2, 2], [2, 2], dtype=2)), outs, None) == -1
     assert emb(ctypes.byref(good), (ctypes.c_void_p * 2)(8, None), None) == -2
+
+    add = lib.tnrsvd_mpo_add
+    add.argtypes = [ctypes.POINTER(Mpo), ctypes.POINTER(Mpo), ctypes.POINTER(ctypes.c_void_p),
+                    ctypes.c_void_p]
+    other = mpo([1, 3, 1], [2, 2], [2, 2])
+    assert add(None, ctypes.byref(other), outs, None) == -1
+    assert add(ctypes.byref(good), ctypes.byref(other), None, None) == -1
+    assert add(ctypes.byref(good), ctypes.byref(mpo([1, 3, 1], [2, 2], [2, 2], dtype=1)), outs,
+               None) == -1                                                     # dtypes differ
+    assert add(ctypes.byref(good), ctypes.byref(mpo([1, 3, 1], [2, 3], [2, 2])), outs,
+               None) == -2                                                     # modes differ
+    assert add(ctypes.byref(good), ctypes.byref(mpo([1, 1], [4], [4])), outs, None) == -2
+    assert add(ctypes.byref(good), ctypes.byref(mpo([1, 3, 2], [2, 2], [2, 2])), outs,
+               None) == -2                                                     # rank[d] != 1
+    assert add(ctypes.byref(good), ctypes.byref(mpo([1, 0, 1], [2, 2], [2, 2])), outs,
+               None) == -2
+    assert add(ctypes.byref(good), ctypes.byref(other), (ctypes.c_void_p * 2)(8, None),
+               None) == -2                                                     # null out core
