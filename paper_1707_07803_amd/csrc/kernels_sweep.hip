@@ -413,8 +413,7 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
     if (reg_abs || reg_plain || tsqr) {
       // Every register path is a sequence of jobs "load panel, QR, store"
       // with a single QR call site: one job for an absorbed or plain panel,
-      // and for a tall panel the TSQR leaves and merges (leaf 0, leaf 1,
-      // merge 1, leaf 2, merge 2, ...).
+      // and for a tall panel the TSQR merges 1, 2, ..., nc-1 in order.
       const int nc = tsqr ? (m + QROWS - 1) / QROWS : 1;
       // the TSQR leaves were factorised in parallel by k_rl_leaves: here only
       // the merges 1 .. nc-1 remain, in order
