@@ -461,7 +461,7 @@ tnrsvd_status tnrsvd_complex_embed(const tnrsvd_mpo* a, void* const* out, void* 
  * ((k = d-1) ? 1 : ra_{k+1} + rb_{k+1}) elements in C order; a and b are
  * read only.  Synchronises `stream` (hipStream_t, NULL: null stream).
  * Errors: E_INVALID (null argument, dtype), E_SHAPE (d or modes differ, end
- * ranks not 1, a rank below 1, a core of C with more than 2^40 entries or a
+ * ranks not 1, a rank below 1, a core of C with 2^40 entries or more or a
  * rank above 2^20), E_DEVICE.
  */
 tnrsvd_status tnrsvd_mpo_add(const tnrsvd_mpo* a, const tnrsvd_mpo* b, void* const* out,

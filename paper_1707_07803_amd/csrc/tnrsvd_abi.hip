@@ -40,8 +40,8 @@ constexpr int64_t kHardCap = 4096;           // largest bond rank a plan may res
 
 inline int64_t sat_mul(int64_t a, int64_t b) {
   if (a >= kSat || b >= kSat) return kSat;
-  const int64_t r = a * b;
-  return r > kSat ? kSat : r;
+  const __int128 r = (__int128)a * b;   // exact: |a|, |b| < 2^63
+  return r > kSat ? kSat : (r < -kSat ? -kSat : (int64_t)r);
 }
 
 enum Space { kNone = 0, kRow = 1, kCol = 2 };
@@ -1587,11 +1587,11 @@ tnrsvd_status tnrsvd_round_mpo(const tnrsvd_mpo* a, double round_tol, int max_ra
   const int d = a->d;
   if (a->rank[0] != 1 || a->rank[d] != 1) return fail(TNRSVD_E_SHAPE, "rank[0] and rank[d] must be 1");
   for (int k = 0; k < d; ++k) {
-    const int64_t r0 = a->rank[k], n = a->rows[k] * a->cols[k], r1 = a->rank[k + 1];
+    const int64_t r0 = a->rank[k], n = sat_mul(a->rows[k], a->cols[k]), r1 = a->rank[k + 1];
     if (r0 < 1 || r1 < 1 || a->rows[k] < 1 || a->cols[k] < 1 || !a->core[k])
       return fail(TNRSVD_E_SHAPE, "core %d: bad shape or null pointer", k);
     if (r0 > kRoundRankMax || r1 > kRoundRankMax || a->rows[k] > INT32_MAX ||
-        a->cols[k] > INT32_MAX || n * r1 > INT32_MAX || r0 * n > INT32_MAX)
+        a->cols[k] > INT32_MAX || sat_mul(n, r1) > INT32_MAX || sat_mul(r0, n) > INT32_MAX)
       return fail(TNRSVD_E_SHAPE, "core %d: ranks above %d or a panel above 2^31 entries", k,
                   kRoundRankMax);
   }
@@ -1652,7 +1652,7 @@ tnrsvd_status tnrsvd_complex_embed(const tnrsvd_mpo* a, void* const* out, void* 
     if (a->rank[k] < 1 || a->rank[k + 1] < 1 || a->rows[k] < 1 || a->cols[k] < 1 || !a->core[k] ||
         !out[k])
       return fail(TNRSVD_E_SHAPE, "core %d: bad shape or null pointer", k);
-    if (a->rank[k] * a->rows[k] * a->cols[k] * a->rank[k + 1] > ((int64_t)1 << 40))
+    if (sat_mul(sat_mul(sat_mul(a->rank[k], a->rows[k]), a->cols[k]), a->rank[k + 1]) >= kSat)
       return fail(TNRSVD_E_SHAPE, "core %d too large", k);
   }
   const hipStream_t s = (hipStream_t)stream;
@@ -1686,7 +1686,7 @@ tnrsvd_status tnrsvd_mpo_add(const tnrsvd_mpo* a, const tnrsvd_mpo* b, void* con
     const int64_t L = k == 0 ? 1 : a->rank[k] + b->rank[k];
     const int64_t R = k == d - 1 ? 1 : a->rank[k + 1] + b->rank[k + 1];
     if (L > ((int64_t)1 << 20) || R > ((int64_t)1 << 20) ||
-        L * a->rows[k] * a->cols[k] * R > ((int64_t)1 << 40))
+        sat_mul(sat_mul(sat_mul(L, a->rows[k]), a->cols[k]), R) >= kSat)
       return fail(TNRSVD_E_SHAPE, "core %d of the sum too large", k);
   }
   const hipStream_t s = (hipStream_t)stream;

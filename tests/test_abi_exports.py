@@ -195,3 +195,12 @@ def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
                None) == -2
     assert add(ctypes.byref(good), ctypes.byref(other), (ctypes.c_void_p * 2)(8, None),
                None) == -2                                                     # null out core
+
+    # sizes whose products overflow 64 bits are refused, not wrapped
+    huge = 2 ** 31 - 1
+    assert rnd(ctypes.byref(mpo([1, 2, 1], [huge, 2], [huge, 2])), 1e-3, 0, None,
+               ctypes.byref(h)) == -2
+    big = mpo([1, 2, 1], [2 ** 40, 2], [2 ** 40, 2])
+    assert add(ctypes.byref(big), ctypes.byref(mpo([1, 2, 1], [2 ** 40, 2], [2 ** 40, 2])),
+               outs, None) == -2
+    assert emb(ctypes.byref(mpo([1, 2, 1], [2 ** 31, 2], [2 ** 31, 2])), outs, None) == -2
