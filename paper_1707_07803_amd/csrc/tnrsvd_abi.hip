@@ -1542,7 +1542,7 @@ tnrsvd_status tnrsvd_sparse_round(int d, const int64_t* rows, const int64_t* col
   if (!(round_tol >= 0.0) || std::isinf(round_tol))
     return fail(TNRSVD_E_INVALID, "round_tol must be finite and >= 0");
   if (max_rank < 0) return fail(TNRSVD_E_INVALID, "max_rank must be >= 0");
-  if (rows[0] * cols[0] > INT32_MAX)
+  if (sat_mul(rows[0], cols[0]) > INT32_MAX)
     return fail(TNRSVD_E_SHAPE, "first core has more than 2^31 rows I_1 J_1");
   RoundedMpo res;
   int why = 0;
