@@ -314,25 +314,25 @@ __device__ __forceinline__ void reg_absorb_dispatch(int spy, double (&x)[QMR][QN
   }
 }
 
-// Flat-tree TSQR of a tall panel (m rows > 256, n <= 128 columns), run by the
+// TSQR of a tall panel (m rows > 256, n <= 128 columns), run by the
 // right-to-left pass as register QR jobs: leaf QRs of consecutive 256-row
-// chunks (k_rl_leaves, all leaves at once), then each leaf's R merged into the
-// running R by a QR of the two stacked triangles, in leaf order.  Workspace layout (in the core's W slab):
+// chunks (k_rl_leaves, all leaves at once), then a binary tree of merges, each
+// the QR of two stacked R factors (k_rl_merge_level per level, the root in the
+// last-core phase).  Workspace layout (in the core's W slab):
 //   leaf c reflectors   W + c * 256 * n            (column-major, ld = rows of leaf c)
-//   merge c reflectors  W + (nc + c) * 256 * n     (ld = rows of merge c), c >= 1
-//   Racc                W + 2 nc 256 n              (row-major; n * n after it unused)
+//   merge c reflectors  W + (nc + c) * 256 * n     (ld = rows of node c), c >= 1
+//   R of the range led by leaf 0   W + 2 nc 256 n   (row-major; n * n after it unused)
 //   taus                W + (2 nc 256 + 2 n) n: leaf c at + c n, merge c at + (nc + c) n
-//   R of leaf c >= 1    W + (2 nc 256 + 2 n) n + 2 nc n + (c - 1) n n   (row-major)
+//   R of the range led by leaf c >= 1   W + (2 nc 256 + 2 n) n + 2 nc n + (c - 1) n n
 // The final R goes to the L slab; tsqr_apply replays the tree in the
 // left-to-right pass.
 
 // TSQR leaves of the last core's tall panel, one workgroup per (MPO, leaf):
 // leaf c is the register QR of rows [256 c, 256 c + 256) of the panel.  Its
-// reflectors and scalars go where the flat tree keeps them, its R to Racc
+// reflectors and scalars go where the tree keeps them, its R to Racc
 // (leaf 0) or to the slot of leaf c >= 1 after the taus:
 //   W + (2 nc 256 + 2 n) n + 2 nc n + (c - 1) n n   (row-major n x n).
-// The last-core phase of the pass then runs the merges 1 .. nc-1 in order, so
-// the factors are those of the sequential tree.  The test for the TSQR path
+// The merge tree then runs level by level.  The test for the TSQR path
 // repeats the pass's own, on the same descriptors; other MPOs exit at once.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_rl_leaves(const MpoDesc* mpos, const CoreDesc* cores,
@@ -363,6 +363,77 @@ __global__ __launch_bounds__(NT) void k_rl_leaves(const MpoDesc* mpos, const Cor
   reg_load_plain<T>(x, Z + cd.z_off, m, P, r0, mrows);
   reg_geqr(x, mrows, P, arena, arena + ARENA - 32, ws_tau + (int64_t)c * P,
            Xt + (int64_t)c * QROWS * P, mrows, Rdst, arena + 2 * QROWS,
+           arena + 2 * QROWS + QCOLS);
+}
+
+// Binary merge tree over the leaves 0 .. nc-1: node c (1 <= c < nc) at level
+// l = ctz(c) merges the ranges [c - 2^l, c) and [c, min(c + 2^l, nc)); its
+// reflectors and scalars sit in merge slot c.  A range's R is kept in the slot
+// of its first leaf (slot 0 = Racc) and has min(P, rows of the range) rows.
+// The root is the node c = 2^floor(log2(nc - 1)); levels are processed bottom
+// up, and the nodes of one level are independent.
+__device__ __forceinline__ int tsqr_rows(int m, int P, int lo, int hi) {
+  const int r = (hi * QROWS < m ? hi * QROWS : m) - lo * QROWS;
+  return r < P ? r : P;
+}
+
+__device__ __forceinline__ int tsqr_root_level(int nc) { return 31 - __clz(nc - 1); }
+
+// Stacks [R of the left range; R of the right range] of node c column-major
+// into merge slot c (not yet written) and loads it into the register panel;
+// returns its row count.  *Rleft receives the left range's R slot.
+__device__ __forceinline__ int tsqr_stack(double (&x)[QMR][QNC], double* Xt, int m, int P,
+                                          int nc, int c, double** Rleft) {
+  const int l = __ffs(c) - 1, a = c - (1 << l);
+  const int hi = (c + (1 << l)) < nc ? (c + (1 << l)) : nc;
+  const int kl = tsqr_rows(m, P, a, c), kr = tsqr_rows(m, P, c, hi);
+  double* ws_tau = Xt + (int64_t)(2 * nc * QROWS + 2 * P) * P;
+  double* Racc = Xt + (int64_t)2 * nc * QROWS * P;
+  double* Rleaf = ws_tau + (int64_t)2 * nc * P;
+  double* Ra = a == 0 ? Racc : Rleaf + (int64_t)(a - 1) * P * P;
+  const double* Rc = Rleaf + (int64_t)(c - 1) * P * P;
+  const int mrows = kl + kr;
+  double* Vdst = Xt + (int64_t)(nc + c) * QROWS * P;
+  for (int e = threadIdx.x; e < mrows * P; e += NT) {
+    const int col = e / mrows, r = e % mrows;
+    Vdst[e] = r < kl ? Ra[r * P + col] : Rc[(r - kl) * P + col];
+  }
+  __syncthreads();
+  reg_load_plain<double>(x, Vdst, mrows, P);
+  __syncthreads();
+  *Rleft = Ra;
+  return mrows;
+}
+
+// One level l below the root of every MPO's merge tree: node j of the level
+// (c = (2 j + 1) 2^l) per workgroup.  MPOs whose root is at level l or below,
+// or whose last core takes another path, exit at once.
+__global__ __launch_bounds__(NT) void k_rl_merge_level(const MpoDesc* mpos, const CoreDesc* cores,
+                                                       int op, const int* pr, double* Wd,
+                                                       int level) {
+  __shared__ double arena[ARENA];
+  const MpoDesc md = mpos[blockIdx.x];
+  const int i = md.d - 1;
+  const CoreDesc cd = cores[md.c0 + i];
+  const int n = op == 0 ? cd.I : cd.J;
+  const int P = pr[md.r0 + i];
+  const int Pn = pr[md.r0 + i + 1];
+  const int m = n * md.K;
+  if (P < 1 || P > cd.RA * cd.xcap || Pn < 1 || Pn > cd.RA2 * cd.xcap2 || md.K > Pn ||
+      m > ARENA - 64 - 2 * QBMAX * QBMAX)
+    return;
+  if (!(i > 0 && P <= QCOLS && m > QROWS && m <= 16 * QROWS)) return;
+  const int nc = (m + QROWS - 1) / QROWS;
+  if (level >= tsqr_root_level(nc)) return;
+  const int c = (2 * (int)blockIdx.y + 1) << level;
+  if (c >= nc) return;
+  double* Xt = Wd + cd.w_off;
+  double* ws_tau = Xt + (int64_t)(2 * nc * QROWS + 2 * P) * P;
+  double x[QMR][QNC];
+  double* Rdst;
+  const int mrows = tsqr_stack(x, Xt, m, P, nc, c, &Rdst);
+  reg_geqr(x, mrows, P, arena, arena + ARENA - 32, ws_tau + (int64_t)(nc + c) * P,
+           Xt + (int64_t)(nc + c) * QROWS * P, mrows, Rdst, arena + 2 * QROWS,
            arena + 2 * QROWS + QCOLS);
 }
 
@@ -411,20 +482,13 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
     const bool reg_plain = PH == 0 && i > 0 && P <= QCOLS && m <= QROWS;
     const bool tsqr = PH == 0 && i > 0 && P <= QCOLS && m > QROWS && m <= 16 * QROWS;
     if (reg_abs || reg_plain || tsqr) {
-      // Every register path is a sequence of jobs "load panel, QR, store"
-      // with a single QR call site: one job for an absorbed or plain panel,
-      // and for a tall panel the TSQR merges 1, 2, ..., nc-1 in order.
+      // One register QR: of the absorbed or plain panel, or for a tall panel
+      // the root of the TSQR merge tree (its leaves were factorised by
+      // k_rl_leaves and the levels below the root by k_rl_merge_level).
       const int nc = tsqr ? (m + QROWS - 1) / QROWS : 1;
-      // the TSQR leaves were factorised in parallel by k_rl_leaves: here only
-      // the merges 1 .. nc-1 remain, in order
-      const int njobs = tsqr ? nc - 1 : 1;
       double* ws_tau = Xt + (int64_t)(2 * nc * QROWS + 2 * P) * P;
-      double* Racc = Xt + (int64_t)2 * nc * QROWS * P;
-      const double* Rleaf = ws_tau + (int64_t)2 * nc * P;
-      int kacc = tsqr ? (QROWS < P ? QROWS : P) : 0;   // leaf 0 has QROWS rows
-      for (int job = 0; job < njobs; ++job) {
-        double x[QMR][QNC];   // the register panel, dead between jobs
-        const int c = tsqr ? job + 1 : 0;                 // merge c
+      {
+        double x[QMR][QNC];   // the register panel
         int mrows, ldv;
         double* Vdst;
         double* Rdst;
@@ -443,28 +507,17 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
           Rdst = L + cd.l_off;
           taud = tau + cd.tau_off;
         } else {
-          // stack [Racc; R of leaf c] column-major into this merge's (not yet
-          // written) reflector block, then load it like a plain panel
-          const int mc = (m - c * QROWS) < QROWS ? (m - c * QROWS) : QROWS;
-          const int kleaf = mc < P ? mc : P;
-          const double* Rc = Rleaf + (int64_t)(c - 1) * P * P;
-          mrows = kacc + kleaf;
-          Vdst = Xt + (int64_t)(nc + c) * QROWS * P;
-          for (int e = tid; e < mrows * P; e += NT) {
-            const int col = e / mrows, r = e % mrows;
-            Vdst[e] = r < kacc ? Racc[r * P + col] : Rc[(r - kacc) * P + col];
-          }
-          __syncthreads();
-          reg_load_plain<double>(x, Vdst, mrows, P);
-          __syncthreads();
+          const int c = 1 << tsqr_root_level(nc);
+          double* unused;
+          mrows = tsqr_stack(x, Xt, m, P, nc, c, &unused);
           ldv = mrows;
-          Rdst = (job == njobs - 1) ? L + cd.l_off : Racc;
+          Vdst = Xt + (int64_t)(nc + c) * QROWS * P;
+          Rdst = L + cd.l_off;
           taud = ws_tau + (int64_t)(nc + c) * P;
         }
         reg_geqr(x, mrows, P, vb, tb, taud, Vdst, ldv, Rdst, arena + 2 * QROWS,
                  arena + 2 * QROWS + QCOLS);
         __syncthreads();
-        if (tsqr) kacc = mrows < P ? mrows : P;
       }
       const int k = m < P ? m : P;
       if (tid == 0) {
@@ -634,54 +687,49 @@ __device__ void wg_apply_q_reg(const double* __restrict__ V, const double* __res
   __syncthreads();
 }
 
-// M^T = Q_thin [T^T; 0] for a panel factorised by tsqr_panel (n columns, m rows,
-// nc chunks): the merges are applied in reverse, each splitting its output
-// between the running top block and the input of one leaf; then every leaf
+// M^T = Q_thin [T^T; 0] for a panel factorised by the right-to-left pass's
+// TSQR (n columns, m rows, nc leaves): the nodes of the merge tree are applied
+// top down, each splitting its output between its two ranges; then every leaf
 // applies its reflectors to its block of rows.  On entry Y (m x s,
 // column-major) holds [T^T; 0]; zbuf holds 2 n s doubles.
 __device__ void tsqr_apply(const double* ws, int m, int n, double* Y, int s, int nc,
                            double* stage, int cap, double* tstage, double* zbuf) {
   const int tid = threadIdx.x;
   const double* ws_tau = ws + (int64_t)(2 * nc * QROWS + 2 * n) * n;
-  // rows of leaf c and of the running factor after merge c, from the shapes
-  auto kleaf = [&](int c) {
-    const int mc = (m - c * QROWS) < QROWS ? (m - c * QROWS) : QROWS;
-    return mc < n ? mc : n;
-  };
-  auto kacc = [&](int c) {
-    int k = kleaf(0);
-    for (int q = 1; q <= c; ++q) k = (k + kleaf(q)) < n ? (k + kleaf(q)) : n;
-    return k;
-  };
-  // the running top block starts as the first kacc(nc-1) rows of Y (= T^T)
-  for (int c = nc - 1; c >= 1; --c) {
-    const int kprev = kacc(c - 1), kc = kacc(c);
-    const int mr = kprev + kleaf(c);
-    // zbuf (mr x s) = [top (kc rows); 0]
-    for (int e = tid; e < mr * s; e += NT) {
-      const int col = e / mr, r = e % mr;
-      zbuf[e] = (r < kc) ? Y[(int64_t)col * m + r] : 0.0;
+  // the merge tree top down: a node's input (its range's rows of the running
+  // factor) sits at the head of its first leaf's row block; the root's is the
+  // head of Y (= T^T)
+  for (int l = tsqr_root_level(nc); l >= 0; --l) {
+    for (int c = 1 << l; c < nc; c += 2 << l) {
+      const int a = c - (1 << l), hi = (c + (1 << l)) < nc ? (c + (1 << l)) : nc;
+      const int kl = tsqr_rows(m, n, a, c), kr = tsqr_rows(m, n, c, hi);
+      const int kc = tsqr_rows(m, n, a, hi), mr = kl + kr;
+      // zbuf (mr x s) = [the node's input (kc rows); 0]
+      for (int e = tid; e < mr * s; e += NT) {
+        const int col = e / mr, r = e % mr;
+        zbuf[e] = (r < kc) ? Y[(int64_t)col * m + a * QROWS + r] : 0.0;
+      }
+      __syncthreads();
+      const int kk = mr < n ? mr : n;
+      wg_apply_q_reg<4>(ws + (int64_t)(nc + c) * QROWS * n, ws_tau + (int64_t)(nc + c) * n, mr,
+                        kk, zbuf, s, stage, cap, tstage);
+      // the left range's rows back to the head of leaf a's block, the right
+      // range's to the head of leaf c's
+      for (int e = tid; e < mr * s; e += NT) {
+        const int col = e / mr, r = e % mr;
+        if (r < kl)
+          Y[(int64_t)col * m + a * QROWS + r] = zbuf[e];
+        else
+          Y[(int64_t)col * m + c * QROWS + (r - kl)] = zbuf[e];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    const int kk = mr < n ? mr : n;
-    wg_apply_q_reg<4>(ws + (int64_t)(nc + c) * QROWS * n, ws_tau + (int64_t)(nc + c) * n, mr, kk,
-                      zbuf, s, stage, cap, tstage);
-    // top kprev rows back to the head of Y; the rest is leaf c's input,
-    // placed at the head of leaf c's row block
-    for (int e = tid; e < mr * s; e += NT) {
-      const int col = e / mr, r = e % mr;
-      if (r < kprev)
-        Y[(int64_t)col * m + r] = zbuf[e];
-      else
-        Y[(int64_t)col * m + c * QROWS + (r - kprev)] = zbuf[e];
-    }
-    __syncthreads();
   }
-  // leaves: rows [c*256, c*256 + mc): [input (kleaf rows); 0] -> Q_c [input; 0]
+  // leaves: rows [c*256, c*256 + mc): [input (kl rows); 0] -> Q_c [input; 0]
   for (int c = 0; c < nc; ++c) {
     const int mc = (m - c * QROWS) < QROWS ? (m - c * QROWS) : QROWS;
     double* Yc = Y + c * QROWS;
-    const int kl = kleaf(c);
+    const int kl = tsqr_rows(m, n, c, c + 1);
     for (int e = tid; e < mc * s; e += NT) {
       const int col = e / mc, r = e % mc;
       if (r >= kl) Yc[(int64_t)col * m + r] = 0.0;
@@ -939,8 +987,15 @@ hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
                           double* L, double* tau, int* err, int leaf_nc, hipStream_t s) {
   by_dtype(dtype, [&](auto* t) {
     using T = elem_t<decltype(t)>;
-    if (leaf_nc > 1)
+    if (leaf_nc > 1) {
       k_rl_leaves<T><<<dim3(batch, leaf_nc), NT, 0, s>>>(mpos, cores, op, pr, (const T*)Z, Wd);
+      // the levels below the root of the largest tree (the root: the last-core phase)
+      const int lroot = 31 - __builtin_clz((unsigned)(leaf_nc - 1));
+      for (int l = 0; l < lroot; ++l) {
+        const int nodes = (leaf_nc + (2 << l) - 1) / (2 << l);
+        k_rl_merge_level<<<dim3(batch, nodes), NT, 0, s>>>(mpos, cores, op, pr, Wd, l);
+      }
+    }
     k_rl_pass<T, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,
                                          err);
     k_rl_pass<T, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,

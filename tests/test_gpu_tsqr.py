@@ -1,10 +1,10 @@
 """GPU parity of the tall last-core panel path of the right-to-left sweep.
 
 When the last core's panel has more than 256 and at most 4096 rows (mode
-size n times K) and at most 128 columns, it is factorised by a flat-tree TSQR:
-the 256-row leaves all at once (one workgroup each), then their merges in leaf
-order.  These cases cover the largest leaf count (16), a ragged last leaf
-with fewer rows than the panel has columns, and a batch that mixes leaf
+size n times K) and at most 128 columns, it is factorised by TSQR: the 256-row
+leaves all at once (one workgroup each), then a binary tree of merges, level
+by level.  These cases cover the largest leaf count (16), odd trees (3 and 6
+leaves), a ragged last leaf with fewer rows than the panel has columns, and a batch that mixes leaf
 counts with an MPO whose last core takes the plain register path.  The
 singular values are compared with the FP64 oracle, which factorises the
 panels without any tiling.
@@ -41,6 +41,8 @@ def tall_mpo(n_last, seed, R=3):
     (64, 40, 24, 1),   # 64 * 64 = 4096 rows: 16 leaves, the most the path takes
     (17, 10, 6, 1),    # 17 * 16 = 272 rows: 2 leaves, the second with 16 rows < 32 columns
     (20, 10, 6, 2),    # 320 rows, ragged second leaf, two power steps
+    (40, 10, 6, 1),    # 640 rows: 3 leaves, an odd tree
+    (44, 20, 12, 1),   # 1408 rows: 6 leaves, a partial right subtree
 ])
 def test_tall_last_core_against_oracle(n_last, k, p, q):
     A = tall_mpo(n_last, 40 + n_last)
