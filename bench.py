@@ -651,7 +651,7 @@ def main():
                    "solves_per_s": round(args.batch * rb["steps"] / rb["seconds"], 2),
                    "ms_per_step": round(1e3 * rb["seconds"] / rb["steps"], 3),
                    "max_sigma_err_vs_prescribed": max(errs),
-                   "roofline": {"bound": "alu", "kernel": "k_rl_leaves + k_rl_pass (a workgroup per MPO, and per TSQR leaf of its last core)",
+                   "roofline": {"bound": "alu", "kernel": "k_rl_leaves + k_rl_merge_level + k_rl_pass (a workgroup per MPO, and per TSQR leaf or tree node of its last core)",
                                 "achieved": round(achb, 4), "peak": FP64_PEAK_TFLOPS,
                                 "unit": "TFLOP/s", "frac": round(achb / FP64_PEAK_TFLOPS, 6),
                                 "flops_per_launch": flb, "avg_launch_ms": round(avgb, 4)},
@@ -692,7 +692,7 @@ def main():
         fl = counts["rl_sweep"][1] / counts["rl_sweep"][2]
         ach = fl / (avg_ms[dom] * 1e-3) / 1e12
         roof = {"bound": "alu",
-                "kernel": "k_rl_leaves<T> + k_rl_pass<T,0> + k_rl_pass<T,1> (one FP64 Householder LQ sweep)",
+                "kernel": "k_rl_leaves<T> + k_rl_merge_level + k_rl_pass<T,0> + k_rl_pass<T,1> (one FP64 Householder LQ sweep)",
                 "achieved": round(ach, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / FP64_PEAK_TFLOPS, 6), "traffic": measured_traffic(main_p),
                 # one MPO's sweep runs as one workgroup on one of the 256 CUs
