@@ -51,6 +51,8 @@ __all__ = [
     "gaussian_counter_array", "sketch_counter_base", "sketch_compress",
     "complex_to_real_mpo", "tnrsvd_complex",
     "merge_tail_adjoint", "sigma_sum_grad",
+    "mpo_times_mps_adjoint", "mpo_t_times_mps_adjoint", "round_sweep_gram", "qr_adjoint",
+    "round_sweep_gram_adjoint", "pipeline_grad",
     "sparse_to_mpo", "round_mpo",
 ]
 
@@ -866,6 +868,301 @@ def sigma_sum_grad(A_cores: Sequence[np.ndarray], res: "TNrSVDResult",
         F = np.einsum("rxR,Raxs->ras", U[i], s2)
     m = len(A) - dm + 1
     return gm[:-1] + merge_tail_adjoint(A[dm - 1:], gm[-1]) if m > 1 else gm
+
+
+# --------------------------------------------------------------------------
+# Derivative of the whole pipeline (not in the paper): reverse mode through
+# the products, the rounding sweeps, the last-core factorisations and the
+# merge, with Omega fixed and the truncation ranks frozen at their forward
+# values.
+#
+# Each rounding is differentiated through its Gram (environment) form, which
+# computes the same map as ``round_sweep``:
+#   right Grams  G_d = I_K,  G_i = sum_x Y_i[:, x, :] G_{i+1} Y_i[:, x, :]^T;
+#   left to right, with T_0 = 1 and M_i = (T_i Y_i) reshaped (s_i n_i) x P_{i+1},
+#   the kept left singular vectors of the i-th panel of ``round_sweep`` are the
+#   top rho eigenvectors of H_i = M_i G_{i+1} M_i^T (that panel is M_i L_{i+1}
+#   with L_{i+1} L_{i+1}^T = G_{i+1}); core i is U_rho, T_{i+1} = U_rho^T M_i;
+#   the last core is the QR or SVD of M_{d-1} (s n x K) as in ``round_sweep``.
+# Unlike the LQ factors of the right-to-left pass, this form stays
+# differentiable when a product is rank deficient, which products of
+# structured MPOs often are.
+# --------------------------------------------------------------------------
+
+def mpo_times_mps_adjoint(A, X, dY):
+    """Adjoint of ``mpo_times_mps`` (bilinear): returns (dA, dX) for the
+    cotangent dY of the product cores.
+    dA[a,x,y,b] = sum_{c,e} dY[(a,c),x,(b,e)] X[c,y,e];
+    dX[c,y,e] = sum_{a,x,b} dY[(a,c),x,(b,e)] A[a,x,y,b]."""
+    dA, dX = [], []
+    for a, x, g in zip(A, X, dY):
+        R, I, J, R2 = a.shape
+        r, _, r2 = x.shape
+        g5 = np.asarray(g, dtype=np.float64).reshape(R, r, I, R2, r2)
+        dA.append(np.einsum("acxbe,cye->axyb", g5, x))
+        dX.append(np.einsum("acxbe,axyb->cye", g5, a))
+    return dA, dX
+
+
+def mpo_t_times_mps_adjoint(A, X, dZ):
+    """Adjoint of ``mpo_t_times_mps``: (dA, dX) for the cotangent dZ.
+    dA[a,x,y,b] = sum_{c,e} dZ[(a,c),y,(b,e)] X[c,x,e];
+    dX[c,x,e] = sum_{a,y,b} dZ[(a,c),y,(b,e)] A[a,x,y,b]."""
+    dA, dX = [], []
+    for a, x, g in zip(A, X, dZ):
+        R, I, J, R2 = a.shape
+        r, _, r2 = x.shape
+        g5 = np.asarray(g, dtype=np.float64).reshape(R, r, J, R2, r2)
+        dA.append(np.einsum("acybe,cxe->axyb", g5, x))
+        dX.append(np.einsum("acybe,axyb->cxe", g5, a))
+    return dA, dX
+
+
+def _signfix_cols(U: np.ndarray) -> np.ndarray:
+    """Flip each column so that its entry of largest magnitude (the first on
+    ties) is positive, as ``svd_signfix`` does for left singular vectors."""
+    if U.shape[1] == 0:
+        return U
+    piv = np.argmax(np.abs(U), axis=0)
+    sg = np.sign(U[piv, np.arange(U.shape[1])])
+    sg[sg == 0] = 1.0
+    return U * sg[None, :]
+
+
+def round_sweep_gram(cores: Sequence[np.ndarray], eps: float, rmax: int, last: str = "qr",
+                     ranks: Optional[Sequence[int]] = None):
+    """The map of ``round_sweep`` computed in the Gram form described above,
+    keeping every intermediate for ``round_sweep_gram_adjoint``.
+
+    ranks: the bond ranks [1, rho_1, ..., rho_{d-1}] to keep (frozen, e.g. the
+    ones ``round_sweep`` chose); without them the tail rule runs on the square
+    roots of the eigenvalues, limited to the min(s n, rho') values the
+    factorised panel has (rho' = the economy rank of the right-to-left pass).
+    Same gauges as ``round_sweep`` (largest-magnitude entry of each kept
+    vector positive; diag(R) >= 0), so its cores equal ``round_sweep``'s up to
+    rounding; eigenvalues below ~1e-16 of the largest are not resolved, which
+    only matters for ranks decided without ``ranks``.
+    """
+    Y = [np.asarray(c, dtype=np.float64) for c in cores]
+    d = len(Y)
+    if Y[0].shape[0] != 1:
+        raise ValueError("first rank must be 1")
+    K = Y[-1].shape[2]
+    G = [None] * (d + 1)
+    G[d] = np.eye(K)
+    for i in range(d - 1, -1, -1):
+        P, n, P2 = Y[i].shape
+        T1 = Y[i].reshape(P * n, P2) @ G[i + 1]
+        G[i] = T1.reshape(P, n * P2) @ Y[i].reshape(P, n * P2).T
+    nrm = float(math.sqrt(max(G[0][0, 0], 0.0)))
+    delta = eps * nrm / math.sqrt(d - 1) if d > 1 else 0.0
+    econ = [0] * (d + 1)                       # economy ranks of the right-to-left pass
+    econ[d] = K
+    for i in range(d - 1, 0, -1):
+        econ[i] = min(Y[i].shape[0], Y[i].shape[1] * econ[i + 1])
+    T = np.ones((1, 1))
+    rec = {"G": G, "T": [], "M": [], "U": [], "lam": [], "rho": [1], "Y": Y, "last": last,
+           "K": K}
+    out = []
+    for i in range(d - 1):
+        P, n, P2 = Y[i].shape
+        s_ = T.shape[0]
+        M = (T @ Y[i].reshape(P, n * P2)).reshape(s_ * n, P2)
+        H = M @ G[i + 1] @ M.T
+        H = 0.5 * (H + H.T)
+        lam, U = np.linalg.eigh(H)
+        lam, U = lam[::-1].copy(), U[:, ::-1].copy()
+        if ranks is not None:
+            rho = int(ranks[i + 1])
+        else:
+            nv = min(s_ * n, econ[i + 1])
+            rho = choose_rank(np.sqrt(np.maximum(lam[:nv], 0.0)), delta, rmax)
+        Ur = _signfix_cols(U[:, :rho])
+        U = U.copy()
+        U[:, :rho] = Ur
+        rec["T"].append(T)
+        rec["M"].append(M)
+        rec["U"].append(U)
+        rec["lam"].append(lam)
+        rec["rho"].append(rho)
+        out.append(Ur.reshape(s_, n, rho))
+        T = Ur.T @ M
+    P, n, _ = Y[d - 1].shape
+    s_ = T.shape[0]
+    M = (T @ Y[d - 1].reshape(P, n * K)).reshape(s_ * n, K)
+    rec["T"].append(T)
+    rec["M"].append(M)
+    res = {"norm": nrm, "ranks": rec["rho"][:], "rec": rec}
+    if last == "qr":
+        Q, R = qr_nonneg(M)
+        out.append(Q.reshape(s_, n, Q.shape[1]))
+        res["R"] = R
+        rec["Q"], rec["R"] = Q, R
+    elif last == "svd":
+        X, S, Wt = svd_signfix(M)
+        out.append(X.reshape(s_, n, X.shape[1]))
+        res["sigma"] = S
+        res["W"] = Wt.T
+        rec["X"], rec["S"], rec["Wt"] = X, S, Wt
+    else:
+        raise ValueError("last must be 'qr' or 'svd'")
+    res["cores"] = out
+    return res
+
+
+def qr_adjoint(Q: np.ndarray, R: np.ndarray, dQ: np.ndarray, dR: Optional[np.ndarray] = None
+               ) -> np.ndarray:
+    """Cotangent of M for the economy QR M = Q R (m >= n, R invertible, diag(R) > 0):
+    dM = (dQ + Q copyltu(R dR^T - dQ^T Q)) R^{-T}, copyltu(X) = the symmetric
+    matrix whose lower triangle is X's (the result of differentiating Q^T Q = I
+    and the triangularity of R)."""
+    n = R.shape[0]
+    C = -dQ.T @ Q
+    if dR is not None:
+        C = C + R @ dR.T
+    S = np.tril(C) + np.tril(C, -1).T
+    B = dQ + Q @ S
+    # B R^{-T}: solve R X^T = B^T
+    return np.linalg.solve(R, B.T).T if n else B
+
+
+def round_sweep_gram_adjoint(rec, dcores: Optional[Sequence[np.ndarray]] = None,
+                             dlast: Optional[np.ndarray] = None,
+                             dsigma: Optional[np.ndarray] = None) -> List[np.ndarray]:
+    """Reverse pass of ``round_sweep_gram``: the cotangents of its input cores
+    from those of its outputs.
+
+    dcores: cotangents of the output cores 0..d-2 (shapes (s, n, rho)), or None;
+    dlast: cotangent of the last core's Q (mode 'qr', shape (s, n, K));
+    dsigma: cotangent of sigma (mode 'svd'; the singular vectors are not used).
+    Steps, last core first: the QR (``qr_adjoint``) or sigma_j = x_j^T M w_j
+    (dM = sum_j dsigma_j x_j w_j^T); then for each core i from d-2 down to 0:
+    T_{i+1} = U^T M gives dM += U dT, dU += M dT^T; the kept eigenvectors of
+    H = M G M^T give dH = V (F o (V^T dU)) U^T with V all eigenvectors,
+    F_aj = 1/(lam_j - lam_a) (a != j, zero on the diagonal); then
+    dM += (dH + dH^T) M G, dG_{i+1} += M^T dH M, and M = T_i Y_i gives dT_i and
+    dY_i.  Last, the right Grams in reverse (left to right):
+    dY_i[:, x, :] += (dG_i + dG_i^T) Y_i[:, x, :] G_{i+1},
+    dG_{i+1} += sum_x Y_i[:, x, :]^T dG_i Y_i[:, x, :].  The norm (and so the
+    tolerance) only decides ranks, which are frozen: it has no cotangent.
+    Requires distinct kept eigenvalues, separated from the discarded ones, and
+    a last panel of full column rank (mode 'qr').
+    """
+    Y, G = rec["Y"], rec["G"]
+    d = len(Y)
+    K = rec["K"]
+    dY = [np.zeros_like(y) for y in Y]
+    dG = [np.zeros_like(g) if g is not None else None for g in G]
+    # last core
+    M = rec["M"][d - 1]
+    T = rec["T"][d - 1]
+    if rec["last"] == "qr":
+        dQ = np.zeros_like(rec["Q"]) if dlast is None else np.asarray(dlast).reshape(rec["Q"].shape)
+        dM = qr_adjoint(rec["Q"], rec["R"], dQ)
+    else:
+        ws = np.zeros(len(rec["S"]))
+        if dsigma is not None:
+            ws[:len(dsigma)] = dsigma
+        dM = (rec["X"] * ws[None, :]) @ rec["Wt"]
+    P, n, _ = Y[d - 1].shape
+    s_ = T.shape[0]
+    dMr = dM.reshape(s_, n * K)
+    dT = dMr @ Y[d - 1].reshape(P, n * K).T
+    dY[d - 1] += (T.T @ dMr).reshape(Y[d - 1].shape)
+    for i in range(d - 2, -1, -1):
+        M, T, U, lam = rec["M"][i], rec["T"][i], rec["U"][i], rec["lam"][i]
+        rho = rec["rho"][i + 1]
+        P, n, P2 = Y[i].shape
+        s_ = T.shape[0]
+        Ur = U[:, :rho]
+        dU = np.zeros_like(Ur) if dcores is None else np.asarray(dcores[i]).reshape(Ur.shape).copy()
+        dM = Ur @ dT
+        dU += M @ dT.T
+        diff = lam[None, :rho] - lam[:, None]           # lam_j - lam_a
+        with np.errstate(divide="ignore"):
+            F = np.where(np.arange(len(lam))[:, None] == np.arange(rho)[None, :], 0.0,
+                         1.0 / np.where(diff == 0.0, np.inf, diff))
+        dH = U @ (F * (U.T @ dU)) @ Ur.T
+        dM += (dH + dH.T) @ M @ G[i + 1]
+        dG[i + 1] += M.T @ dH @ M
+        dMr = dM.reshape(s_, n * P2)
+        Yr = Y[i].reshape(P, n * P2)
+        dT = dMr @ Yr.T
+        dY[i] += (T.T @ dMr).reshape(Y[i].shape)
+    for i in range(1, d):
+        P, n, P2 = Y[i].shape
+        Sd = dG[i] + dG[i].T
+        YG = (Y[i].reshape(P * n, P2) @ G[i + 1]).reshape(P, n * P2)
+        dY[i] += (Sd @ YG).reshape(P, n, P2)
+        if i + 1 < d:
+            DY = (dG[i] @ Y[i].reshape(P, n * P2)).reshape(P * n, P2)
+            dG[i + 1] += Y[i].reshape(P * n, P2).T @ DY
+    return dY
+
+
+def pipeline_grad(A_cores: Sequence[np.ndarray], k: int, p: int, q: int,
+                  omega: Tuple[Sequence[np.ndarray], np.ndarray], eps: float = 0.0,
+                  rmax: int = 0, dsigma: Optional[np.ndarray] = None,
+                  ranks: Optional[List[List[int]]] = None) -> List[np.ndarray]:
+    """Gradient of L = sum_{j<k} dsigma_j sigma_j (dsigma = 1 by default) of the
+    TNrSVD pipeline ``tnrsvd`` with respect to the original cores of A, with
+    Omega fixed and every rounding's bond ranks frozen (``ranks``, one list per
+    rounding in the order of ``TNrSVDResult.ranks``; taken from a run of
+    ``tnrsvd`` when not given).
+
+    Forward, recomputed: merge; Y = A Omega; each rounding in its Gram form
+    (``round_sweep_gram``) with the frozen ranks; Algorithm 5.4's products
+    and roundings; B^T = A^T Q and its rounding with the last-core SVD.
+    Backward: the same steps in reverse (``round_sweep_gram_adjoint``, the
+    product adjoints, both contributing to dA), then the merge adjoint.
+    Parity: pinned by central finite differences of ``tnrsvd`` and, where the
+    computed subspace is exact, by the closed form sum_j u_j v_j^T.
+    """
+    K = k + p
+    A0 = [np.asarray(c, dtype=np.float64) for c in A_cores]
+    rows = [c.shape[1] for c in A0]
+    cols = [c.shape[2] for c in A0]
+    m = merge_plan(rows, cols, K)
+    A = merge_tail(A0, m)
+    if ranks is None:
+        ranks = tnrsvd(A0, k, p, q, omega=omega, eps=eps, rmax=rmax).ranks
+    if len(ranks) != 2 * q + 2:
+        raise ValueError("one rank list per rounding is needed")
+    Om = omega_as_mps(*omega)
+    stages = []          # (op, X, rounding record)
+    Y = mpo_times_mps(A, Om)
+    r = round_sweep_gram(Y, eps, rmax, "qr", ranks=ranks[0])
+    stages.append((0, Om, r["rec"]))
+    Q = r["cores"]
+    t = 1
+    for _ in range(q):
+        Z = mpo_t_times_mps(A, Q)
+        r = round_sweep_gram(Z, eps, rmax, "qr", ranks=ranks[t])
+        stages.append((1, Q, r["rec"]))
+        Qz = r["cores"]
+        Y = mpo_times_mps(A, Qz)
+        r = round_sweep_gram(Y, eps, rmax, "qr", ranks=ranks[t + 1])
+        stages.append((0, Qz, r["rec"]))
+        Q = r["cores"]
+        t += 2
+    Bt = mpo_t_times_mps(A, Q)
+    r = round_sweep_gram(Bt, eps, rmax, "svd", ranks=ranks[t])
+    stages.append((1, Q, r["rec"]))
+    w = np.ones(k) if dsigma is None else np.asarray(dsigma, dtype=np.float64)
+    dA = [np.zeros_like(a) for a in A]
+    dX_out = None            # cotangent of the basis produced by the stage below
+    for si in range(len(stages) - 1, -1, -1):
+        op, X, rec = stages[si]
+        if rec["last"] == "svd":
+            dP = round_sweep_gram_adjoint(rec, dsigma=w)
+        else:
+            dP = round_sweep_gram_adjoint(rec, dcores=dX_out[:-1], dlast=dX_out[-1])
+        adj = mpo_times_mps_adjoint if op == 0 else mpo_t_times_mps_adjoint
+        gA, gX = adj(A, X, dP)
+        for j in range(len(A)):
+            dA[j] += gA[j]
+        dX_out = gX
+    return dA[:-1] + merge_tail_adjoint(A0[len(A) - 1:], dA[-1]) if m > 1 else dA
 
 
 # --------------------------------------------------------------------------
