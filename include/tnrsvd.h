@@ -372,6 +372,29 @@ tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* co
                                    void* stream);
 
 /*
+ * tnrsvd_sparse_to_mpo_noalloc -- tnrsvd_sparse_to_mpo for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same two calls, arguments, results
+ * and errors, on the same kernels, but the scratch (block bitmap or sort
+ * keys, prefix sums, counters, the unit-entry table and the prefix-sum /
+ * sort temporaries) lives in a file-scope device array of the library
+ * (32 MiB, kNoAllocScratchBytes; each GPU the library runs on holds its own
+ * copy until the process ends).  No hipMalloc, hipFree or allocating library
+ * routine is called; the caller still passes inputs and cores.
+ * Limits: inputs whose scratch exceeds 32 MiB (about 8.9e7 block positions on
+ *   the bitmap path, 6e5 entries on the sort path) and d > 64 return E_SHAPE
+ *   with the size needed.  Device ordinals 0..63.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ *   behind; the call clears what must start at zero.  Calls are serialised
+ *   within a process (each ends with a stream synchronisation); calls that
+ *   overlap on one GPU from elsewhere would race on the array.
+ */
+tnrsvd_status tnrsvd_sparse_to_mpo_noalloc(int d, const int64_t* rows, const int64_t* cols,
+                                           int64_t nnz, const int64_t* coo_row,
+                                           const int64_t* coo_col, const double* coo_val,
+                                           int64_t* nblocks, double* const* cores, void* stream);
+
+/*
  * tnrsvd_sparse_round -- the SVD-based rounding of Sec. 3 applied to the MPO
  * that Algorithm 4.1 (tnrsvd_sparse_to_mpo) builds from the same COO input,
  * computed without forming that MPO.  The rounding is the one the paper uses

@@ -372,114 +372,102 @@ std::vector<std::pair<char*, size_t>> g_scratch;
 
 }  // namespace
 
-// Counts the nonzero blocks (*nblocks) and, when cores is not null, fills the
-// d caller-allocated FP64 cores if the count equals `expect` (the rank they
-// were sized for).  Shapes are validated by the caller; an index outside the
-// matrix is reported through *bad_index and then no core is written.
-hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
-                         const int64_t* row, const int64_t* col, const double* val,
-                         int64_t expect, int64_t* nblocks, double* const* cores, int* bad_index,
-                         hipStream_t s) {
+namespace {
+
+// Byte layout of one call's scratch (bitmap or sort path), from the shapes
+// alone; the hipcub calls below only report their temporary sizes.
+struct S2MLayout {
+  bool bitmap;
+  int64_t nw;
+  int end_bit;
+  size_t tmp_bytes, o_a, o_b, o_c, o_d, o_e, o_f, o_cnt, o_uc, o_tmp, total;
+};
+
+hipError_t s2m_layout(int64_t nnz, uint64_t none, int nk, S2MLayout* L, hipStream_t s) {
+  L->bitmap = none <= kBitmapMax;
+  const int n = (int)(nnz > 0 ? nnz : 1);
+  L->nw = (int64_t)((none + 31) / 32);
+  L->end_bit = 1;
+  while (L->end_bit < 64 && (none >> L->end_bit) != 0) ++L->end_bit;
+  const size_t uc_bytes = align_up(sizeof(UnitCore) * (size_t)(nk + 1));
+  hipError_t e = hipSuccess;
+  L->tmp_bytes = 0;
+  if (L->bitmap) {
+    // a: bitmap, b: word popcounts, c: their inclusive prefix sum
+    e = hipcub::DeviceScan::InclusiveSum(nullptr, L->tmp_bytes, (int*)nullptr, (int*)nullptr,
+                                         (int)L->nw, s);
+    L->o_a = 0;
+    L->o_b = L->o_a + align_up(4 * (size_t)L->nw);
+    L->o_c = L->o_b + align_up(4 * (size_t)L->nw);
+    L->o_d = L->o_e = L->o_f = L->o_c + align_up(4 * (size_t)L->nw);
+  } else {
+    // a: keys, b: sorted keys, c: block keys, d: positions, e: sorted positions, f: heads + scan
+    size_t t_sort = 0, t_scan = 0;
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, t_sort, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                           (int64_t*)nullptr, (int64_t*)nullptr, n, 0, L->end_bit,
+                                           s);
+    if (e == hipSuccess)
+      e = hipcub::DeviceScan::InclusiveSum(nullptr, t_scan, (int*)nullptr, (int*)nullptr, n, s);
+    L->tmp_bytes = t_sort > t_scan ? t_sort : t_scan;
+    L->o_a = 0;
+    L->o_b = L->o_a + align_up(8 * (size_t)n);
+    L->o_c = L->o_b + align_up(8 * (size_t)n);
+    L->o_d = L->o_c + align_up(8 * (size_t)n);
+    L->o_e = L->o_d + align_up(8 * (size_t)n);
+    L->o_f = L->o_e + align_up(8 * (size_t)n);
+  }
+  L->o_cnt = (L->bitmap ? L->o_d : L->o_f + 2 * align_up(4 * (size_t)n));
+  L->o_uc = L->o_cnt + 256;
+  L->o_tmp = L->o_uc + uc_bytes;
+  L->total = L->o_tmp + align_up(L->tmp_bytes > 0 ? L->tmp_bytes : 1);
+  return e;
+}
+
+// p[0..n) = 0 (a kernel rather than a memset, so a captured stream records no
+// memset node)
+__global__ void k_clear_u32(unsigned* __restrict__ p, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = 0u;
+}
+
+// The conversion proper on a scratch buffer `base` laid out by L: counts the
+// blocks, fills the cores when asked, and synchronises the stream.
+hipError_t s2m_run(char* base, const S2MLayout& L, int d, const int64_t* I, const int64_t* J,
+                   int64_t nnz, const int64_t* row, const int64_t* col, const double* val,
+                   int64_t expect, int64_t* nblocks, double* const* cores, const UnitCore* uc,
+                   int nk, int* bad_index, hipStream_t s) {
   int64_t M = 1, Nc = 1;
   for (int k = 0; k < d; ++k) {
     M *= I[k];
     Nc *= J[k];
   }
   const int64_t nbc = Nc / J[0];
-  const uint64_t none = (uint64_t)(M / I[0]) * (uint64_t)nbc;   // number of block positions
-  const bool bitmap = none <= kBitmapMax;
-  const int n = (int)(nnz > 0 ? nnz : 1);
-  const int64_t nw = (int64_t)((none + 31) / 32);
-  int end_bit = 1;
-  while (end_bit < 64 && (none >> end_bit) != 0) ++end_bit;
+  const uint64_t none = (uint64_t)(M / I[0]) * (uint64_t)nbc;
+  const int64_t nw = L.nw;
+  const size_t tmp_bytes = L.tmp_bytes;
+  int* cnt = (int*)(base + L.o_cnt);   // cnt[0] blocks, cnt[1] index outside the matrix
+  UnitCore* duc = (UnitCore*)(base + L.o_uc);
+  void* tmp = base + L.o_tmp;
 
-  // unit-entry table of cores 2..d
-  std::vector<UnitCore> uc;
-  if (cores) {
-    int64_t rdiv = 1, cdiv = 1;
-    for (int k = 1; k < d; ++k) {
-      uc.push_back(UnitCore{cores[k], I[k], J[k], rdiv, cdiv, k == d - 1 ? 1 : 0});
-      rdiv *= I[k];
-      cdiv *= J[k];
+  k_clear_u32<<<1, 64, 0, s>>>((unsigned*)cnt, 2);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && nk > 0)
+    e = hipMemcpyAsync(duc, uc, sizeof(UnitCore) * nk, hipMemcpyHostToDevice, s);
+  if (L.bitmap) {
+    unsigned* bm = (unsigned*)(base + L.o_a);
+    int* pc = (int*)(base + L.o_b);
+    int* ws = (int*)(base + L.o_c);
+    if (e == hipSuccess) {
+      k_clear_u32<<<grid_n(nw), 256, 0, s>>>(bm, nw);
+      e = hipGetLastError();
     }
-  }
-  const size_t uc_bytes = align_up(sizeof(UnitCore) * (uc.size() + 1));
-
-  hipError_t e = hipSuccess;
-  size_t tmp_bytes = 0;
-  size_t o_a, o_b, o_c, o_d, o_e, o_f, o_cnt, o_uc, o_tmp, total;
-  if (bitmap) {
-    // a: bitmap, b: word popcounts, c: their inclusive prefix sum
-    e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, (int*)nullptr, (int*)nullptr,
-                                         (int)nw, s);
-    o_a = 0;
-    o_b = o_a + align_up(4 * (size_t)nw);
-    o_c = o_b + align_up(4 * (size_t)nw);
-    o_d = o_e = o_f = o_c + align_up(4 * (size_t)nw);
-  } else {
-    // a: keys, b: sorted keys, c: block keys, d: positions, e: sorted positions, f: heads + scan
-    size_t t_sort = 0, t_scan = 0;
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, t_sort, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                           (int64_t*)nullptr, (int64_t*)nullptr, n, 0, end_bit, s);
-    if (e == hipSuccess)
-      e = hipcub::DeviceScan::InclusiveSum(nullptr, t_scan, (int*)nullptr, (int*)nullptr, n, s);
-    tmp_bytes = t_sort > t_scan ? t_sort : t_scan;
-    o_a = 0;
-    o_b = o_a + align_up(8 * (size_t)n);
-    o_c = o_b + align_up(8 * (size_t)n);
-    o_d = o_c + align_up(8 * (size_t)n);
-    o_e = o_d + align_up(8 * (size_t)n);
-    o_f = o_e + align_up(8 * (size_t)n);
-  }
-  if (e != hipSuccess) return e;
-  o_cnt = (bitmap ? o_d : o_f + 2 * align_up(4 * (size_t)n));
-  o_uc = o_cnt + 256;
-  o_tmp = o_uc + uc_bytes;
-  total = o_tmp + align_up(tmp_bytes > 0 ? tmp_bytes : 1);
-
-  std::lock_guard<std::mutex> lock(g_scratch_mu);
-  int dev = 0;
-  e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, {nullptr, 0});
-  char* base = nullptr;
-  bool owned = false;
-  if (total <= kCacheMax) {
-    auto& sc = g_scratch[dev];
-    if (sc.second < total) {
-      if (sc.first) (void)hipFree(sc.first);
-      sc = {nullptr, 0};
-      e = hipMalloc((void**)&sc.first, total);
-      if (e != hipSuccess) {
-        sc.first = nullptr;
-        return e;
-      }
-      sc.second = total;
-    }
-    base = sc.first;
-  } else {
-    e = hipMalloc((void**)&base, total);
-    if (e != hipSuccess) return e;
-    owned = true;
-  }
-  int* cnt = (int*)(base + o_cnt);   // cnt[0] blocks, cnt[1] index outside the matrix
-  UnitCore* duc = (UnitCore*)(base + o_uc);
-  void* tmp = base + o_tmp;
-
-  e = hipMemsetAsync(cnt, 0, 2 * sizeof(int), s);
-  if (e == hipSuccess && !uc.empty())
-    e = hipMemcpyAsync(duc, uc.data(), sizeof(UnitCore) * uc.size(), hipMemcpyHostToDevice, s);
-  const int nk = (int)uc.size();
-  if (bitmap) {
-    unsigned* bm = (unsigned*)(base + o_a);
-    int* pc = (int*)(base + o_b);
-    int* ws = (int*)(base + o_c);
-    if (e == hipSuccess) e = hipMemsetAsync(bm, 0, 4 * (size_t)nw, s);
     if (e == hipSuccess && nnz > 0) {
       k_mark<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, M, Nc, I[0], J[0], nbc, bm, cnt + 1);
       k_popc<<<grid_n(nw), 256, 0, s>>>(bm, nw, pc);
       e = hipGetLastError();
-      if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, pc, ws, (int)nw, s);
+      size_t tb = tmp_bytes;
+      if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(tmp, tb, pc, ws, (int)nw, s);
       if (e == hipSuccess) {
         k_total<<<1, 64, 0, s>>>(ws, nw, cnt);
         e = hipGetLastError();
@@ -499,26 +487,29 @@ hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
       }
     }
   } else {
-    uint64_t* key = (uint64_t*)(base + o_a);
-    uint64_t* skey = (uint64_t*)(base + o_b);
-    uint64_t* bkey = (uint64_t*)(base + o_c);
-    int64_t* idx = (int64_t*)(base + o_d);
-    int64_t* sidx = (int64_t*)(base + o_e);
-    int* flag = (int*)(base + o_f);
-    int* scan = (int*)(base + o_f + align_up(4 * (size_t)n));
+    const int n = (int)(nnz > 0 ? nnz : 1);
+    uint64_t* key = (uint64_t*)(base + L.o_a);
+    uint64_t* skey = (uint64_t*)(base + L.o_b);
+    uint64_t* bkey = (uint64_t*)(base + L.o_c);
+    int64_t* idx = (int64_t*)(base + L.o_d);
+    int64_t* sidx = (int64_t*)(base + L.o_e);
+    int* flag = (int*)(base + L.o_f);
+    int* scan = (int*)(base + L.o_f + align_up(4 * (size_t)n));
     if (e == hipSuccess && nnz > 0) {
       k_block_keys<<<grid_n(nnz), 256, 0, s>>>(row, col, val, nnz, M, Nc, I[0], J[0], nbc, none,
                                                key, idx, cnt + 1);
       e = hipGetLastError();
+      size_t tb = tmp_bytes;
       if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, skey, idx, sidx, (int)nnz, 0,
-                                               end_bit, s);
+        e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, skey, idx, sidx, (int)nnz, 0,
+                                               L.end_bit, s);
       if (e == hipSuccess) {
         k_heads<<<grid_n(nnz), 256, 0, s>>>(skey, nnz, none, flag);
         e = hipGetLastError();
       }
+      tb = tmp_bytes;
       if (e == hipSuccess)
-        e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, flag, scan, (int)nnz, s);
+        e = hipcub::DeviceScan::InclusiveSum(tmp, tb, flag, scan, (int)nnz, s);
       if (e == hipSuccess) {
         k_block_ids<<<grid_n(nnz), 256, 0, s>>>(skey, flag, scan, nnz, bkey, cnt);
         e = hipGetLastError();
@@ -545,11 +536,117 @@ hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
     *bad_index = hc[1];
     *nblocks = hc[0] > 0 ? hc[0] : 1;   // the zero matrix is one zero rank-1 term
   }
+  return e;
+}
+
+// Unit-entry table of cores 2..d (nk = d - 1 entries, or 0 without cores).
+int s2m_units(int d, const int64_t* I, const int64_t* J, double* const* cores, UnitCore* uc) {
+  if (!cores) return 0;
+  int64_t rdiv = 1, cdiv = 1;
+  for (int k = 1; k < d; ++k) {
+    uc[k - 1] = UnitCore{cores[k], I[k], J[k], rdiv, cdiv, k == d - 1 ? 1 : 0};
+    rdiv *= I[k];
+    cdiv *= J[k];
+  }
+  return d - 1;
+}
+
+std::mutex g_noalloc_mu;   // held for a whole call (which ends synchronised)
+char* g_noalloc_ptr[kNoAllocDevices] = {};
+
+}  // namespace
+
+// Scratch of sparse_to_mpo_noalloc: file-scope device memory (each GPU the
+// library runs on holds its own copy until the process ends).  Host code uses
+// it only through the per-device address from hipGetSymbolAddress, never by
+// this name.
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+// Counts the nonzero blocks (*nblocks) and, when cores is not null, fills the
+// d caller-allocated FP64 cores if the count equals `expect` (the rank they
+// were sized for).  Shapes are validated by the caller; an index outside the
+// matrix is reported through *bad_index and then no core is written.
+hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
+                         const int64_t* row, const int64_t* col, const double* val,
+                         int64_t expect, int64_t* nblocks, double* const* cores, int* bad_index,
+                         hipStream_t s) {
+  int64_t M = 1, Nc = 1;
+  for (int k = 0; k < d; ++k) {
+    M *= I[k];
+    Nc *= J[k];
+  }
+  const uint64_t none = (uint64_t)(M / I[0]) * (uint64_t)(Nc / J[0]);
+  std::vector<UnitCore> uc(d > 1 ? d - 1 : 1);
+  const int nk = s2m_units(d, I, J, cores, uc.data());
+  S2MLayout L;
+  hipError_t e = s2m_layout(nnz, none, nk, &L, s);
+  if (e != hipSuccess) return e;
+
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, {nullptr, 0});
+  char* base = nullptr;
+  bool owned = false;
+  if (L.total <= kCacheMax) {
+    auto& sc = g_scratch[dev];
+    if (sc.second < L.total) {
+      if (sc.first) (void)hipFree(sc.first);
+      sc = {nullptr, 0};
+      e = hipMalloc((void**)&sc.first, L.total);
+      if (e != hipSuccess) {
+        sc.first = nullptr;
+        return e;
+      }
+      sc.second = L.total;
+    }
+    base = sc.first;
+  } else {
+    e = hipMalloc((void**)&base, L.total);
+    if (e != hipSuccess) return e;
+    owned = true;
+  }
+  e = s2m_run(base, L, d, I, J, nnz, row, col, val, expect, nblocks, cores, uc.data(), nk,
+              bad_index, s);
   if (owned) {
     const hipError_t ef = hipFree(base);
     if (e == hipSuccess) e = ef;
   }
   return e;
+}
+
+hipError_t sparse_to_mpo_noalloc(int d, const int64_t* I, const int64_t* J, int64_t nnz,
+                                 const int64_t* row, const int64_t* col, const double* val,
+                                 int64_t expect, int64_t* nblocks, double* const* cores,
+                                 int* bad_index, size_t* need, hipStream_t s) {
+  int64_t M = 1, Nc = 1;
+  for (int k = 0; k < d; ++k) {
+    M *= I[k];
+    Nc *= J[k];
+  }
+  const uint64_t none = (uint64_t)(M / I[0]) * (uint64_t)(Nc / J[0]);
+  UnitCore uc[kNoAllocMaxD];
+  const int nk = s2m_units(d, I, J, cores, uc);
+  S2MLayout L;
+  hipError_t e = s2m_layout(nnz, none, nk, &L, s);
+  if (e != hipSuccess) return e;
+  *need = L.total;
+  if (L.total > kNoAllocScratchBytes) return hipSuccess;   // the caller reports the limit
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNoAllocDevices) return hipErrorInvalidDevice;
+  if (!g_noalloc_ptr[dev]) {
+    // once per device, with that device current: its copy's address
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[dev] = (char*)p;
+  }
+  return s2m_run(g_noalloc_ptr[dev], L, d, I, J, nnz, row, col, val, expect, nblocks, cores, uc,
+                 nk, bad_index, s);
 }
 
 

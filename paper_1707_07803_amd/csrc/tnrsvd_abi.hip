@@ -1531,6 +1531,48 @@ tnrsvd_status tnrsvd_sparse_to_mpo(int d, const int64_t* rows, const int64_t* co
   return TNRSVD_OK;
 }
 
+tnrsvd_status tnrsvd_sparse_to_mpo_noalloc(int d, const int64_t* rows, const int64_t* cols,
+                                           int64_t nnz, const int64_t* coo_row,
+                                           const int64_t* coo_col, const double* coo_val,
+                                           int64_t* nblocks, double* const* cores, void* stream) {
+  int64_t M = 0, Nc = 0;
+  TRY(check_coo(d, rows, cols, nnz, coo_row, coo_col, coo_val, &M, &Nc));
+  if (!nblocks) return fail(TNRSVD_E_INVALID, "null nblocks");
+  if (d > kNoAllocMaxD)
+    return fail(TNRSVD_E_SHAPE, "d = %d exceeds the %d cores the no-allocation call takes", d,
+                kNoAllocMaxD);
+  const int64_t expect = cores ? *nblocks : -1;
+  if (cores) {
+    if (expect < 1) return fail(TNRSVD_E_INVALID, "*nblocks must hold the rank of the cores");
+    if (expect > (nnz > 0 ? nnz : 1))
+      return fail(TNRSVD_E_SHAPE, "rank %lld exceeds the number of entries", (long long)expect);
+    for (int k = 0; k < d; ++k) {
+      const int64_t len = sat_mul(sat_mul(k == 0 ? 1 : expect, rows[k]),
+                                  sat_mul(cols[k], k == d - 1 ? 1 : expect));
+      if (len >= kSat) return fail(TNRSVD_E_SHAPE, "core %d would exceed 2^40 entries", k);
+    }
+    for (int k = 0; k < d; ++k)
+      if (!cores[k]) return fail(TNRSVD_E_INVALID, "null core %d", k);
+  }
+  int bad = 0;
+  int64_t nb = 0;
+  size_t need = 0;
+  TRY(dev_check(sparse_to_mpo_noalloc(d, rows, cols, nnz, coo_row, coo_col, coo_val, expect, &nb,
+                                      cores, &bad, &need, (hipStream_t)stream),
+                "sparse to MPO (no allocation)"));
+  if (need > kNoAllocScratchBytes)
+    return fail(TNRSVD_E_SHAPE,
+                "the input needs %zu bytes of scratch; the no-allocation call has %zu", need,
+                kNoAllocScratchBytes);
+  if (bad) return fail(TNRSVD_E_SHAPE, "COO index outside the %lld x %lld matrix", (long long)M,
+                       (long long)Nc);
+  *nblocks = nb;
+  if (cores && nb != expect)
+    return fail(TNRSVD_E_SHAPE, "the matrix has %lld nonzero blocks, cores sized for %lld",
+                (long long)nb, (long long)expect);
+  return TNRSVD_OK;
+}
+
 tnrsvd_status tnrsvd_sparse_round(int d, const int64_t* rows, const int64_t* cols, int64_t nnz,
                                   const int64_t* coo_row, const int64_t* coo_col,
                                   const double* coo_val, double round_tol, int max_rank,

@@ -208,6 +208,16 @@ hipError_t sparse_to_mpo(int d, const int64_t* I, const int64_t* J, int64_t nnz,
                          const int64_t* row, const int64_t* col, const double* val,
                          int64_t expect, int64_t* nblocks, double* const* cores, int* bad_index,
                          hipStream_t s);
+// The same conversion on the library's static device scratch (no allocation):
+// *need receives the scratch bytes the input takes; when that exceeds
+// kNoAllocScratchBytes nothing runs and hipSuccess is returned.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr int kNoAllocDevices = 64;   // device ordinals served
+constexpr int kNoAllocMaxD = 64;      // cores of the converted MPO
+hipError_t sparse_to_mpo_noalloc(int d, const int64_t* I, const int64_t* J, int64_t nnz,
+                                 const int64_t* row, const int64_t* col, const double* val,
+                                 int64_t expect, int64_t* nblocks, double* const* cores,
+                                 int* bad_index, size_t* need, hipStream_t s);
 // Rounding of Algorithm 4.1's MPO (kernels_round.hip; orchestrated in kernels_sparse.hip).
 int64_t qr_ws_doubles(int64_t m, int64_t n);
 int64_t colsign_chunks(int64_t n1);

@@ -27,7 +27,7 @@ EXPORTS = [
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
-    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_complex_embed", "tnrsvd_mpo_add", "tnrsvd_rounded_ranks",
+    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_to_mpo_noalloc", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_complex_embed", "tnrsvd_mpo_add", "tnrsvd_rounded_ranks",
     "tnrsvd_rounded_copy", "tnrsvd_rounded_destroy", "tnrsvd_last_error", "tnrsvd_version",
 ]
 
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_sparse_to_mpo.argtypes = [I, P64, P64, ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, P64,
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
+    L.tnrsvd_sparse_to_mpo_noalloc.argtypes = L.tnrsvd_sparse_to_mpo.argtypes
     L.tnrsvd_sparse_round.argtypes = [I, P64, P64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, I,
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
@@ -350,14 +351,16 @@ def solve(cores, k: int, p: int = 0, q: int = 0, seed: int = 0, precision: str =
     return sig, U, V
 
 
-def sparse_to_mpo(rows, cols, coo_row, coo_col, coo_val):
+def sparse_to_mpo(rows, cols, coo_row, coo_col, coo_val, noalloc=False):
     """Algorithm 4.1: the MPO cores of a sparse matrix given in COO form.
 
     rows, cols: mode sizes I_1..I_d, J_1..J_d (eq. (1) ordering, first core
     fastest).  coo_row, coo_col: int64 device tensors; coo_val: float64 device
     tensor (same length).  Returns d float64 device tensors (R, I_k, J_k, R')
     of rank R = number of nonzero I_1 x J_1 blocks, computed by
-    tnrsvd_sparse_to_mpo on the current stream.
+    tnrsvd_sparse_to_mpo on the current stream (noalloc=True: by
+    tnrsvd_sparse_to_mpo_noalloc, whose scratch is the library's static
+    device array; the cores are still allocated here, by torch).
     """
     import torch
 
@@ -376,13 +379,14 @@ def sparse_to_mpo(rows, cols, coo_row, coo_col, coo_val):
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     args = (ctypes.c_void_p(coo_row.data_ptr()), ctypes.c_void_p(coo_col.data_ptr()),
             ctypes.c_void_p(coo_val.data_ptr()))
+    fn = L.tnrsvd_sparse_to_mpo_noalloc if noalloc else L.tnrsvd_sparse_to_mpo
     nb = ctypes.c_int64(0)
-    _check(L.tnrsvd_sparse_to_mpo(d, rr, cc, nnz, *args, ctypes.byref(nb), None, stream))
+    _check(fn(d, rr, cc, nnz, *args, ctypes.byref(nb), None, stream))
     R = nb.value
     shapes = [(1 if k == 0 else R, rows[k], cols[k], 1 if k == d - 1 else R) for k in range(d)]
     cores = [torch.empty(s, dtype=torch.float64, device=dev) for s in shapes]
     ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
-    _check(L.tnrsvd_sparse_to_mpo(d, rr, cc, nnz, *args, ctypes.byref(nb), ptrs, stream))
+    _check(fn(d, rr, cc, nnz, *args, ctypes.byref(nb), ptrs, stream))
     return cores
 
 
