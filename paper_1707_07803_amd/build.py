@@ -17,8 +17,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtnrsvd.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels_contract.hip", "kernels_sweep.hip", "kernels_grad.hip", "kernels_sparse.hip",
-           "kernels_round.hip", "tnrsvd_abi.hip"]
+SOURCES = ["kernels_contract.hip", "kernels_sweep.hip", "kernels_wide.hip", "kernels_grad.hip",
+           "kernels_sparse.hip", "kernels_round.hip", "tnrsvd_abi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

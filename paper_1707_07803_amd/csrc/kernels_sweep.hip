@@ -337,8 +337,9 @@ __device__ __forceinline__ void reg_absorb_dispatch(int spy, double (&x)[QMR][QN
 template <typename T>
 __global__ __launch_bounds__(NT) void k_rl_leaves(const MpoDesc* mpos, const CoreDesc* cores,
                                                   int op, const int* pr, const T* __restrict__ Z,
-                                                  double* Wd) {
+                                                  double* Wd, const int* wflag) {
   __shared__ double arena[ARENA];
+  if (wflag && wflag[blockIdx.x]) return;   // taken by the multi-workgroup path
   const MpoDesc md = mpos[blockIdx.x];
   const int i = md.d - 1;
   const CoreDesc cd = cores[md.c0 + i];
@@ -410,8 +411,9 @@ __device__ __forceinline__ int tsqr_stack(double (&x)[QMR][QNC], double* Xt, int
 // or whose last core takes another path, exit at once.
 __global__ __launch_bounds__(NT) void k_rl_merge_level(const MpoDesc* mpos, const CoreDesc* cores,
                                                        int op, const int* pr, double* Wd,
-                                                       int level) {
+                                                       int level, const int* wflag) {
   __shared__ double arena[ARENA];
+  if (wflag && wflag[blockIdx.x]) return;
   const MpoDesc md = mpos[blockIdx.x];
   const int i = md.d - 1;
   const CoreDesc cd = cores[md.c0 + i];
@@ -449,12 +451,13 @@ template <typename T, int PH>
 __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int op,
                                                 const int* pr, int* rho, int* ldm,
                                                 const T* __restrict__ Z, double* Wd, double* L,
-                                                double* tau, int* err) {
+                                                double* tau, int* err, const int* wflag) {
   __shared__ double arena[ARENA];
   double* vb = arena;                 // 2 * QROWS (register path) or m (global path)
   double* tb = arena + ARENA - 32;    // 2 doubles
   double* red = arena + ARENA - 16;   // NW doubles
   const int tid = threadIdx.x;
+  if (wflag && wflag[blockIdx.x]) return;   // taken by the multi-workgroup path
   const MpoDesc md = mpos[blockIdx.x];
   const int d = md.d;
   if (PH == 0 && tid == 0) rho[md.r0 + d] = md.K;
@@ -984,22 +987,24 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
 
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
-                          double* L, double* tau, int* err, int leaf_nc, hipStream_t s) {
+                          double* L, double* tau, int* err, int leaf_nc, const int* wflag,
+                          hipStream_t s) {
   by_dtype(dtype, [&](auto* t) {
     using T = elem_t<decltype(t)>;
     if (leaf_nc > 1) {
-      k_rl_leaves<T><<<dim3(batch, leaf_nc), NT, 0, s>>>(mpos, cores, op, pr, (const T*)Z, Wd);
+      k_rl_leaves<T><<<dim3(batch, leaf_nc), NT, 0, s>>>(mpos, cores, op, pr, (const T*)Z, Wd,
+                                                         wflag);
       // the levels below the root of the largest tree (the root: the last-core phase)
       const int lroot = 31 - __builtin_clz((unsigned)(leaf_nc - 1));
       for (int l = 0; l < lroot; ++l) {
         const int nodes = (leaf_nc + (2 << l) - 1) / (2 << l);
-        k_rl_merge_level<<<dim3(batch, nodes), NT, 0, s>>>(mpos, cores, op, pr, Wd, l);
+        k_rl_merge_level<<<dim3(batch, nodes), NT, 0, s>>>(mpos, cores, op, pr, Wd, l, wflag);
       }
     }
     k_rl_pass<T, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,
-                                         err);
+                                         err, wflag);
     k_rl_pass<T, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,
-                                         err);
+                                         err, wflag);
   });
   return hipGetLastError();
 }

@@ -122,6 +122,18 @@ struct tnrsvd_s {
   // launch shape of the contraction per op (threads per block, blocks per core
   // cap), from tnrsvd_autotune
   int ct_threads[2] = {256, 256}, ct_cap[2] = {256, 256};
+  // multi-workgroup right-to-left path (kernels_wide.hip): whether the rank
+  // capacities allow a panel beyond the register path; per MPO flag; the
+  // device-side needs of the current rounding; the capacity plan; the plan of
+  // each rounding of a solve as last measured (used when a solve is captured)
+  bool wide_possible = false;
+  double* WV = nullptr;
+  int *wflag_d = nullptr, *wneed_d = nullptr, *wcap_d = nullptr, *wplan_d = nullptr;
+  std::vector<int> wcap;
+  std::vector<std::vector<int>> wplan;
+  std::vector<int> wscratch;
+  int wslots = 0;
+  int round_idx = 0;
 };
 
 namespace {
@@ -276,7 +288,7 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
 
   // ---- capacity plan -----------------------------------------------------
   int64_t a_tot = 0, x_tot = 0, z_tot = 0, w_tot = 0, l_tot = 0, t_tot = 0, y_tot = 0,
-          u_tot = 0, om_tot = 0, s_tot = 0, out_tot = 0;
+          u_tot = 0, om_tot = 0, s_tot = 0, out_tot = 0, wv_tot = 0;
   std::vector<int> sk_nm;
   int r_tot = 0;
   int64_t tcap = 1, mcap_s = 1, ucap = 1, qcap = 1;
@@ -348,6 +360,21 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
     h->max_om = std::max(h->max_om, omn);
     int64_t mpo_t = 1, mpo_m = 1, mpo_u = 1, mpo_q = 1, mpo_pc = 1, mpo_nm = 1;
     int mpo_v = 64;
+    // multi-workgroup path: possible when some core i >= 1 may have more than
+    // kRegCols product columns, or a last-core panel beyond the TSQR leaves
+    bool mpo_wide = false;
+    int64_t mpo_wm = 0;
+    {
+      int64_t rn = K;
+      for (int i = dm - 1; i >= 0; --i) {
+        const int64_t nmax = std::max(I[i], J[i]);
+        const int64_t P = R[i] * xc[i];
+        const int64_t m = nmax * rn;
+        if (i >= 1 && (P > kRegCols || (i == dm - 1 && m > (int64_t)kTsqrLeavesMax * kRegRows)))
+          mpo_wide = true;
+        rn = std::min(m, P);
+      }
+    }
     for (int i = 0; i < dm; ++i) {
       CoreDesc cd{};
       cd.I = (int)I[i];
@@ -387,6 +414,11 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
       }
       // the blocked QR of the global path needs m qb + 2 qb P more (qb <= 32)
       wneed += nmax * P2pad * 32 + 2 * 32 * P;
+      cd.wt_off = w_tot + wneed;
+      if (mpo_wide) {
+        wneed += (int64_t)kWideNB * kWideNB * ((P + kWideNB - 1) / kWideNB);
+        mpo_wm = std::max(mpo_wm, nmax * P2pad);
+      }
       w_tot += wneed;
       cd.l_off = l_tot;
       l_tot += P * P;
@@ -420,6 +452,28 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
     out_tot += K + 2 * (int64_t)K * K;
     md.mcap = mpo_v;
     md.pcap = (int)mpo_pc;
+    md.wv_off = wv_tot;
+    md.wmcap = (int)mpo_wm;
+    if (mpo_wide) {
+      h->wide_possible = true;
+      wv_tot += 2 * mpo_wm * kWideNB + mpo_wm * 16 + 1024;
+    }
+    // capacity plan of the wide launches at each step t (core dm - 1 - t)
+    if ((int)h->wcap.size() < kWidePlan * dm) h->wcap.resize(kWidePlan * dm, 0);
+    if (mpo_wide) {
+      int64_t rn = K;
+      for (int i = dm - 1; i >= 0; --i) {
+        const int64_t nmax = std::max(I[i], J[i]);
+        const int64_t P = R[i] * xc[i];
+        const int64_t m = nmax * rn;
+        const int64_t k = std::min(m, P);
+        const int64_t v[kWidePlan] = {i >= 1 ? (k + kWideNB - 1) / kWideNB : 0, P, m, rn, nmax};
+        const int t = dm - 1 - i;
+        for (int c = 0; c < kWidePlan; ++c)
+          h->wcap[t * kWidePlan + c] = (int)std::max<int64_t>(h->wcap[t * kWidePlan + c], v[c]);
+        rn = k;
+      }
+    }
     sk_nm.push_back((int)mpo_nm);
     tcap = std::max(tcap, mpo_t);
     mcap_s = std::max(mcap_s, mpo_m);
@@ -490,6 +544,17 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   ALLOC(h->U, sizeof(double) * x_tot);
   ALLOC(h->V, sizeof(double) * x_tot);
   ALLOC(h->tail, sizeof(double) * tail_tot);
+  if (h->wide_possible) {
+    h->wcap.resize((size_t)kWidePlan * h->max_d, 0);
+    // one plan slot per rounding of a solve (2q + 2), three more for tnrsvd_refine
+    h->wslots = 2 * o->q + 5;
+    h->wplan.assign(h->wslots, std::vector<int>());
+    ALLOC(h->WV, sizeof(double) * wv_tot);
+    ALLOC(h->wflag_d, sizeof(int) * batch);
+    ALLOC(h->wneed_d, sizeof(int) * kWidePlan * h->max_d);
+    ALLOC(h->wcap_d, sizeof(int) * kWidePlan * h->max_d);
+    ALLOC(h->wplan_d, sizeof(int) * kWidePlan * h->max_d * h->wslots);
+  }
   std::vector<int64_t> sk_off;
   if (o->sketch_rank > 0) {
     int64_t sk_tot = 0;
@@ -528,6 +593,10 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   if ((e = hipMemcpyAsync(h->core_mpo_d, h->core_mpo.data(), sizeof(int) * h->ncores,
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail_dev(e, "upload core map");
+  if (h->wide_possible &&
+      (e = hipMemcpyAsync(h->wcap_d, h->wcap.data(), sizeof(int) * h->wcap.size(),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return fail_dev(e, "upload wide plan");
   if ((e = hipMemsetAsync(h->err, 0, sizeof(int) * 4, s)) != hipSuccess)
     return fail_dev(e, "clear error flags");
 
@@ -760,6 +829,7 @@ tnrsvd_status load_omega(tnrsvd_t h) {
   h->first_product = true;
   h->projected = false;
   h->solved = false;
+  h->round_idx = 0;
   return TNRSVD_OK;
 }
 
@@ -793,14 +863,76 @@ tnrsvd_status do_mult(tnrsvd_t h, int op) {
   return TNRSVD_OK;
 }
 
-tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
+// Right-to-left pass.  When the capacities allow panels beyond the register
+// path, k_wide_classify first picks the MPOs whose panels are that wide (from
+// the ranks on the device); they take the multi-workgroup launches, the rest
+// the one-workgroup kernels.  Run eagerly, the launches follow the device's
+// needs (read back once per rounding) and that plan is kept for the rounding's
+// index within the solve; under stream capture the kept plan (or, before any
+// eager solve, the capacity plan) is used, and MPOs it does not cover stay on
+// the one-workgroup path.
+tnrsvd_status rl_sweep(tnrsvd_t h, int op) {
   hipError_t e;
+  const int* wflag = nullptr;
+  const int* plan = nullptr;
+  if (h->wide_possible) {
+    const int idx = h->round_idx++;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TRY(dev_check(hipStreamIsCapturing(h->stream, &cs), "query capture"));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    const int nplan = kWidePlan * h->max_d;
+    const int* plan_d = nullptr;
+    if (capturing) {
+      if (idx < h->wslots && (int)h->wplan[idx].size() == nplan) {
+        plan = h->wplan[idx].data();
+        plan_d = h->wplan_d + (int64_t)idx * nplan;
+      } else {
+        plan = h->wcap.data();
+        plan_d = h->wcap_d;
+      }
+    }
+    e = launch_wide_classify(h->mpos_d, h->cores_d, h->batch, op, h->pr, plan_d, h->max_d,
+                             h->wflag_d, h->wneed_d, h->stream);
+    TRY(dev_check(e, "classify panels"));
+    if (!capturing) {
+      std::vector<int> need(nplan);
+      TRY(dev_check(hipMemcpyAsync(need.data(), h->wneed_d, sizeof(int) * nplan,
+                                   hipMemcpyDeviceToHost, h->stream),
+                    "read panel sizes"));
+      TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+      if (idx < h->wslots) {
+        h->wplan[idx] = need;
+        TRY(dev_check(hipMemcpyAsync(h->wplan_d + (int64_t)idx * nplan, h->wplan[idx].data(),
+                                     sizeof(int) * nplan, hipMemcpyHostToDevice, h->stream),
+                      "keep panel plan"));
+        plan = h->wplan[idx].data();
+      } else {
+        h->wscratch = need;
+        plan = h->wscratch.data();
+      }
+    }
+    wflag = h->wflag_d;
+  }
   {
     Timed tm(h, 1);
     e = launch_rl_pass(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->rho, h->ldm, h->Z, h->dtype,
-                       h->W, h->L, h->tau, h->err, h->leaf_nc, h->stream);
+                       h->W, h->L, h->tau, h->err, h->leaf_nc, wflag, h->stream);
+    TRY(dev_check(e, "right-to-left sweep"));
+    if (plan) {
+      for (int t = 0; t < h->max_d; ++t) {
+        e = launch_rl_wide_step(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->rho, h->ldm,
+                                h->wflag_d, h->Z, h->dtype, h->W, h->WV, h->L, h->tau, t,
+                                plan + kWidePlan * t, h->stream);
+        TRY(dev_check(e, "right-to-left sweep (wide panels)"));
+      }
+    }
   }
-  TRY(dev_check(e, "right-to-left sweep"));
+  return TNRSVD_OK;
+}
+
+tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
+  hipError_t e;
+  TRY(rl_sweep(h, op));
   Timed tm(h, 2);
   SweepOpts so;
   so.eps = h->opts.round_tol;
@@ -919,6 +1051,14 @@ tnrsvd_status tnrsvd_run_graph(tnrsvd_t h, double* sigma) {
                     "create capture stream"));
       for (hipEvent_t& e : h->gev)
         TRY(dev_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "create event"));
+    }
+    // the multi-workgroup launches of a captured solve follow the plan of an
+    // eager solve: run one first if none has been kept
+    if (h->wide_possible) {
+      bool kept = true;
+      for (int r = 0; r < 2 * h->opts.q + 2; ++r)
+        kept = kept && (int)h->wplan[r].size() == kWidePlan * h->max_d;
+      if (!kept) TRY(tnrsvd_run(h, nullptr));
     }
     // work already queued on the caller's stream (create, set_omega) must not
     // be reordered behind the capture

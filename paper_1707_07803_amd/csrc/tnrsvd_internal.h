@@ -36,6 +36,8 @@ struct CoreDesc {
   int64_t tau_off;   // TAU slab, capacity RA*xcap
   int64_t y0_off;    // Y0 slab (first product), capacity RA * I * RA2 * (xcap2 == K ? K : 1)
   int64_t u_off;     // U / V output slab (double), capacity xcap * max(I,J) * xcap2
+  int64_t wt_off;    // W slab: compact-WY factor T of every 32-column block of
+                     // the multi-workgroup QR, ceil(RA * xcap / 32) x 32 x 32
 };
 
 // Per MPO static plan.
@@ -50,6 +52,11 @@ struct MpoDesc {
   int64_t out_off;   // small outputs (double): sigma[K], W[K*K], R_K[K*K]
   int mcap;          // max panel rows of this MPO (n * rho' over cores)
   int pcap;          // max product rank of this MPO
+  // multi-workgroup right-to-left path (WV slab): two explicit reflector
+  // blocks of wmcap x 32 (double-buffered) and the nested-QR workspace
+  // (wmcap * 16 + 1024); wmcap bounds the panel rows n * rho' of every core
+  int64_t wv_off;
+  int wmcap;
 };
 
 // Rank arrays (device, int): one slot per bond, MpoDesc::r0 + i, i = 0..d.
@@ -190,7 +197,20 @@ hipError_t launch_copy_y0(const MpoDesc* mpos, const CoreDesc* cores, const int*
                           int64_t max_out, hipStream_t s);
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
-                          double* L, double* tau, int* err, int leaf_nc, hipStream_t s);
+                          double* L, double* tau, int* err, int leaf_nc, const int* wflag,
+                          hipStream_t s);
+// Wide right-to-left pass (kernels_wide.hip).  Per step t (core d-1-t of every
+// MPO) the plan holds kWidePlan ints: column blocks of the QR, and bounds on
+// P, panel rows m, rho' and the mode size n (grid sizes of the launches).
+constexpr int kWidePlan = 5;
+constexpr int kWideNB = 32;   // column block of the multi-workgroup QR
+hipError_t launch_wide_classify(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
+                                const int* pr, const int* plan, int max_d, int* wflag, int* need,
+                                hipStream_t s);
+hipError_t launch_rl_wide_step(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
+                               const int* pr, int* rho, int* ldm, const int* wflag, const void* Z,
+                               int dtype, double* Wd, double* WV, double* L, double* tau, int t,
+                               const int* plan_t, hipStream_t s);
 hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* rho, const int* ldm, int* xr, const double* Wd,
                           const double* tau, double* scratch, void* Xout, int out_dtype,

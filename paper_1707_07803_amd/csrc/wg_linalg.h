@@ -295,6 +295,34 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
   wg_gemm_t<64, 64, TB>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, sci, scj, lds);
 }
 
+constexpr int QB = 16;      // block width of the left-to-right pass
+constexpr int QBMAX = 32;   // widest block; Ts and Gs are QBMAX x QBMAX
+
+// Compact WY factor of jb <= QBMAX reflectors held explicitly in Vp (mp x jb,
+// column-major, unit diagonal, zeros above it): H_0 ... H_{jb-1} = I - V T V^T
+// with T upper triangular (row-major in Ts, ld QBMAX).  G = V^T V goes to Gs,
+// then the forward recurrence T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i].
+// Ends with a barrier.
+__device__ void wg_build_t(const double* Vp, int mp, int jb, const double* tau, double* Ts,
+                           double* Gs, double* lds) {
+  const int tid = threadIdx.x;
+  wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QBMAX, 1, lds);
+  if (tid < 64) {
+    for (int i = 0; i < jb; ++i) {
+      const double ti = tau[i];
+      if (tid < i) {
+        double acc = 0.0;
+        for (int c = tid; c < i; ++c) acc += Ts[tid * QBMAX + c] * Gs[c * QBMAX + i];
+        Ts[tid * QBMAX + i] = -ti * acc;
+      } else if (tid < QBMAX) {
+        Ts[tid * QBMAX + i] = tid == i ? ti : 0.0;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+}
+
 // Blocked Householder QR (same output as wg_geqr2: R on and above the
 // diagonal, reflectors below it, tau) of the m x n column-major X (ld ld,
 // default m), for
@@ -306,8 +334,6 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
 // there; otherwise in place in global memory with v as the LDS vector.
 // qb: block width (<= QBMAX).  ws: m qb + 2 qb n doubles of global workspace;
 // Ts, Gs: QBMAX x QBMAX doubles each in LDS outside lds.
-constexpr int QB = 16;      // block width of the left-to-right pass
-constexpr int QBMAX = 32;   // widest block; Ts and Gs are QBMAX x QBMAX
 // A panel too tall for LDS at width qb is itself factorised in QB-wide blocks
 // in LDS (NEST) when those fit, else column by column in global memory.
 template <bool NEST>
@@ -350,23 +376,7 @@ __device__ void wg_geqrf_impl(double* X, int m, int n, double* tau, double* v, d
       }
       __syncthreads();
     }
-    // G = V^T V (jb x jb, row-major in LDS), then T by the forward recurrence
-    //   T_ii = tau_i,  T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-    wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QBMAX, 1, lds);
-    if (tid < 64) {
-      for (int i = 0; i < jb; ++i) {
-        const double ti = tau[j0 + i];
-        if (tid < i) {
-          double acc = 0.0;
-          for (int c = tid; c < i; ++c) acc += Ts[tid * QBMAX + c] * Gs[c * QBMAX + i];
-          Ts[tid * QBMAX + i] = -ti * acc;
-        } else if (tid < QBMAX) {
-          Ts[tid * QBMAX + i] = tid == i ? ti : 0.0;
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    __syncthreads();
+    wg_build_t(Vp, mp, jb, tau + j0, Ts, Gs, lds);
     double* C = X + (int64_t)(j0 + jb) * ld + j0;  // trailing block (mp x nc), ld ld
     double* Wt = ws + (int64_t)mp * qb;             // W^T = C^T V, nc x jb (ld qb)
     double* Wt2 = Wt + (int64_t)qb * n;             // W^T T, nc x jb (ld qb)
