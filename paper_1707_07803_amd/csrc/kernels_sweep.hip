@@ -743,6 +743,62 @@ __device__ void tsqr_apply(const double* ws, int m, int n, double* Y, int s, int
   }
 }
 
+// Y <- H_0 ... H_{k-1} Y (Y: mp x s, column-major, ld mp, s <= 32) for a panel
+// factorised by the multi-workgroup QR (kernels_wide.hip): reflectors below the
+// diagonal of V (column-major, ld mp), the compact-WY factor T_j of column block
+// j (32 columns) at Tb + 1024 j (row-major 32 x 32).  Blocks from the last to
+// the first: W = V_j^T Y, W = T_j W, Y -= V_j W, where the unit lower triangle
+// of V_j (rows j0 .. j0 + jb) is handled apart from its dense rows below, which
+// go through the matrix-core GEMM straight from V.  lds: 4160 doubles of GEMM
+// staging; Wl, W2, Ts: 1024 doubles each (LDS).
+__device__ void wg_apply_wy(const double* __restrict__ V, const double* __restrict__ Tb, int mp,
+                            int k, double* Y, int s, double* lds, double* Wl, double* W2,
+                            double* Ts) {
+  const int tid = threadIdx.x;
+  const int nb = (k + 31) / 32;
+  for (int j = nb - 1; j >= 0; --j) {
+    const int j0 = 32 * j, jb = k - j0 < 32 ? k - j0 : 32;
+    const int rb = j0 + jb, mb = mp - rb;
+    for (int e = tid; e < 1024; e += NT) Ts[e] = Tb[(int64_t)j * 1024 + e];
+    if (mb > 0) {
+      wg_gemm_t<64, 32, double>(jb, s, mb, 1.0, V + (int64_t)j0 * mp + rb, mp, 1, Y + rb, 1, mp,
+                                0.0, Wl, 32, 1, lds);
+    } else {
+      for (int e = tid; e < 1024; e += NT) Wl[e] = 0.0;
+      __syncthreads();
+    }
+    // W[q][c] += Y[j0 + q][c] + sum_{q < r < jb} V[j0 + r][j0 + q] Y[j0 + r][c]
+    for (int e = tid; e < jb * s; e += NT) {
+      const int q = e / s, c = e - q * s;
+      const double* vq = V + (int64_t)(j0 + q) * mp + j0;
+      const double* yc = Y + (int64_t)c * mp + j0;
+      double acc = yc[q];
+      for (int r = q + 1; r < jb; ++r) acc += vq[r] * yc[r];
+      Wl[q * 32 + c] += acc;
+    }
+    __syncthreads();
+    // W2 = T W (T upper triangular)
+    for (int e = tid; e < jb * s; e += NT) {
+      const int q = e / s, c = e - q * s;
+      double acc = 0.0;
+      for (int r = q; r < jb; ++r) acc += Ts[q * 32 + r] * Wl[r * 32 + c];
+      W2[q * 32 + c] = acc;
+    }
+    __syncthreads();
+    // top rows: Y[j0 + r][c] -= W2[r][c] + sum_{q < r} V[j0 + r][j0 + q] W2[q][c]
+    for (int e = tid; e < jb * s; e += NT) {
+      const int r = e / s, c = e - r * s;
+      double acc = W2[r * 32 + c];
+      for (int q = 0; q < r; ++q) acc += V[(int64_t)(j0 + q) * mp + j0 + r] * W2[q * 32 + c];
+      Y[(int64_t)c * mp + j0 + r] -= acc;
+    }
+    if (mb > 0)
+      wg_gemm<double>(mb, s, jb, -1.0, V + (int64_t)j0 * mp + rb, 1, mp, W2, 32, 1, 1.0, Y + rb, 1,
+                      mp, lds);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Left-to-right pass, one workgroup per MPO.  Panels live in LDS when they fit.
 // ---------------------------------------------------------------------------
@@ -770,7 +826,8 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
                                                 const double* Wd, const double* tau,
                                                 double* scratch, TO* __restrict__ Xout,
                                                 double* outs, SweepOpts so, int64_t tcap,
-                                                int64_t mcap_s, int64_t ucap, int* err) {
+                                                int64_t mcap_s, int64_t ucap, int* err,
+                                                const int* wflag) {
   __shared__ double arena[ARENA];
   __shared__ int iarena[LR_SC + 16];
   double* Mb = arena;
@@ -786,6 +843,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
   const int tid = threadIdx.x;
   const MpoDesc md = mpos[blockIdx.x];
   const int d = md.d, K = md.K;
+  const bool wide = wflag && wflag[blockIdx.x];   // panels factorised by kernels_wide.hip
   ScratchLayout SL;
   SL.T = scratch + md.s_off;
   SL.M = SL.T + tcap;
@@ -842,6 +900,8 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       if (ntree > 0) {
         tsqr_apply(Wd + cd.w_off, mp, ri, M, s, ntree, Vb, LR_VB, tst,
                    ((int64_t)2 * ri * s <= LR_UB) ? Ub : SL.U);
+      } else if (wide && s <= 32) {
+        wg_apply_wy(Wd + cd.w_off, Wd + cd.wt_off, mp, ri, M, s, Vb, Ub, Ub + 1024, Ub + 2048);
       } else if (mp <= 256)
         wg_apply_q_reg<4>(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB, tst);
       else if (mp <= 1024)
@@ -860,20 +920,27 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       // the rows of M and of R^T have the same inner products, so the one-sided
       // Jacobi runs on the nv x nv R^T in LDS with the same rotations, and the
       // carried factor U^T M = (U^T R^T) Q^T is recovered by applying Q.
-      const bool pre = !m_in_lds && nv < rn && nv * nv <= LR_MB && nvg * nvg <= LR_UB &&
-                       (int64_t)rn * (QB + 1) <= LR_VB && 2 * QBMAX * QBMAX <= LR_UB &&
+      // R^T stays in LDS when it fits with U, else it goes to the scratch after
+      // the QR's scalars (the Jacobi then works from L2)
+      const bool pre_lds = nv * nv <= LR_MB && nvg * nvg <= LR_UB &&
+                           (int64_t)rn * (QB + 1) <= LR_VB;
+      const bool pre_glob = !pre_lds && nv <= 256 && rn <= LR_VB &&
+                            (int64_t)rn * QB + 2 * QB * nv + nv + nvg * nvg <= so.qcap;
+      const bool pre = !m_in_lds && nv < rn && (pre_lds || pre_glob) &&
+                       2 * QBMAX * QBMAX <= LR_UB &&
                        (int64_t)rn * QB + 2 * QB * nv + nv <= so.qcap;
       double* B = M;
       int blen = rn, bld = ld;
       double* tauP = SL.Q + (int64_t)rn * QB + 2 * QB * nv;
       if (pre) {
         wg_geqrf(M, rn, nv, tauP, Vb, red, SL.Q, Vb, LR_VB, Ub, Ub + QBMAX * QBMAX, ld, QB);
+        double* Bt = pre_lds ? Mb : tauP + nv;
         for (int e = tid; e < nv * nv; e += NT) {
           const int p = e / nv, c = e - p * nv;
-          Mb[e] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T
+          Bt[e] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T
         }
         __syncthreads();
-        B = Mb;
+        B = Bt;
         blen = nv;
         bld = nv;
       }
@@ -1013,11 +1080,11 @@ hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
                           const int* rho, const int* ldm, int* xr, const double* Wd,
                           const double* tau, double* scratch, void* Xout, int out_dtype,
                           double* outs, SweepOpts o, int64_t tcap, int64_t mcap_s, int64_t ucap,
-                          int* err, hipStream_t s) {
+                          int* err, const int* wflag, hipStream_t s) {
   by_dtype(out_dtype, [&](auto* t) {
     using T = elem_t<decltype(t)>;
     k_lr_pass<T><<<batch, NT, 0, s>>>(mpos, cores, op, rho, ldm, xr, Wd, tau, scratch, (T*)Xout,
-                                      outs, o, tcap, mcap_s, ucap, err);
+                                      outs, o, tcap, mcap_s, ucap, err, wflag);
   });
   return hipGetLastError();
 }

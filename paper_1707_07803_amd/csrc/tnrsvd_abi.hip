@@ -434,7 +434,8 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
       const int64_t nv = xc[i] * nmax;
       // QR-preconditioned Jacobi of the left-to-right pass: blocked QR of the
       // transposed panel (P2 rows, nv columns) and its scalars
-      mpo_q = std::max(mpo_q, P2 * 16 + 2 * 16 * nv + nv);
+      // (and R^T, nv x nv, when it does not fit in LDS)
+      mpo_q = std::max(mpo_q, P2 * 16 + 2 * 16 * nv + nv + (i < dm - 1 ? nv * nv : 0));
       if (i < dm - 1) {
         scap = (int)std::max<int64_t>(scap, nv);
         mpo_u = std::max(mpo_u, nv * nv);
@@ -944,7 +945,7 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   int* rout = mode == 0 ? h->xr : h->vr;
   e = launch_lr_pass(h->mpos_d, h->cores_d, h->batch, op, h->rho, h->ldm, rout, h->W, h->tau,
                      h->scratch, out, odt, h->outs, so, h->tcap, h->mcap_s, h->ucap, h->err,
-                     h->stream);
+                     h->wide_possible ? h->wflag_d : nullptr, h->stream);
   return dev_check(e, "left-to-right sweep");
 }
 

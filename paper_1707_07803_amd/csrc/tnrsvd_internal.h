@@ -215,7 +215,7 @@ hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
                           const int* rho, const int* ldm, int* xr, const double* Wd,
                           const double* tau, double* scratch, void* Xout, int out_dtype,
                           double* outs, SweepOpts o, int64_t tcap, int64_t mcap_s, int64_t ucap,
-                          int* err, hipStream_t s);
+                          int* err, const int* wflag, hipStream_t s);
 hipError_t launch_form_u(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
                          int ncores, const int* xr, const void* X, int dtype, const double* outs,
                          double* U, int64_t max_out, int* err, hipStream_t s);
