@@ -749,8 +749,8 @@ __device__ void tsqr_apply(const double* ws, int m, int n, double* Y, int s, int
 // j (32 columns) at Tb + 1024 j (row-major 32 x 32).  Blocks from the last to
 // the first: W = V_j^T Y, W = T_j W, Y -= V_j W, where the unit lower triangle
 // of V_j (rows j0 .. j0 + jb) is handled apart from its dense rows below, which
-// go through the matrix-core GEMM straight from V.  lds: 4160 doubles of GEMM
-// staging; Wl, W2, Ts: 1024 doubles each (LDS).
+// go through the matrix cores straight from V (split-K for V^T Y, 16-row
+// blocks for Y -= V W).  lds: unused; Wl, W2, Ts: 1024 doubles each (LDS).
 __device__ void wg_apply_wy(const double* __restrict__ V, const double* __restrict__ Tb, int mp,
                             int k, double* Y, int s, double* lds, double* Wl, double* W2,
                             double* Ts) {
@@ -760,13 +760,8 @@ __device__ void wg_apply_wy(const double* __restrict__ V, const double* __restri
     const int j0 = 32 * j, jb = k - j0 < 32 ? k - j0 : 32;
     const int rb = j0 + jb, mb = mp - rb;
     for (int e = tid; e < 1024; e += NT) Ts[e] = Tb[(int64_t)j * 1024 + e];
-    if (mb > 0) {
-      wg_gemm_t<64, 32, double>(jb, s, mb, 1.0, V + (int64_t)j0 * mp + rb, mp, 1, Y + rb, 1, mp,
-                                0.0, Wl, 32, 1, lds);
-    } else {
-      for (int e = tid; e < 1024; e += NT) Wl[e] = 0.0;
-      __syncthreads();
-    }
+    // W = V_bot^T Y_bot (jb x s), split over the mb dense rows
+    wg_atb<2, 2>(jb, s, mb, V + (int64_t)j0 * mp + rb, mp, Y + rb, mp, Wl);
     // W[q][c] += Y[j0 + q][c] + sum_{q < r < jb} V[j0 + r][j0 + q] Y[j0 + r][c]
     for (int e = tid; e < jb * s; e += NT) {
       const int q = e / s, c = e - q * s;
@@ -793,8 +788,7 @@ __device__ void wg_apply_wy(const double* __restrict__ V, const double* __restri
       Y[(int64_t)c * mp + j0 + r] -= acc;
     }
     if (mb > 0)
-      wg_gemm<double>(mb, s, jb, -1.0, V + (int64_t)j0 * mp + rb, 1, mp, W2, 32, 1, 1.0, Y + rb, 1,
-                      mp, lds);
+      wg_ab_rows<2>(mb, s, jb, -1.0, V + (int64_t)j0 * mp + rb, mp, W2, 32, 1, Y + rb, mp);
     __syncthreads();
   }
 }

@@ -11,11 +11,11 @@
 //   k_wide_load     Zt_i^T as tiled FP64 GEMMs on the matrix cores, one 64 x 64
 //                   output tile per workgroup, over all mode indices y at once
 //                   (the last core: a copy of the product core);
-//   k_wide_step(j)  the compact-WY update (I - V T V^T)^T of the trailing
-//                   columns by column block j, one strip of columns per
-//                   workgroup; the workgroup of the first strip then
-//                   factorises block j + 1 (blocked Householder, diag(R) >= 0)
-//                   and writes its explicit reflectors and its T factor;
+//   k_wide_panel(j) the Householder QR (diag(R) >= 0) of 32-column block j,
+//                   its columns held in registers, one workgroup per MPO; its
+//                   explicit reflectors and its compact-WY factor T;
+//   k_wide_update(j) the update (I - V T V^T)^T of the columns right of block
+//                   j, one 64-column strip per workgroup;
 //   k_wide_finish   R (upper trapezoid) to the L slab, the ranks rho and ldm.
 // Cores stay sequential, since each absorbs its neighbour's factor.  What is
 // left behind (reflectors below the diagonal of the panel, tau, R, rho, ldm)
@@ -37,7 +37,227 @@ constexpr int SW = 64;        // columns per update workgroup (strips after the 
 constexpr int WARENA = 19456; // doubles of static LDS per workgroup (152 KiB)
 constexpr int RCAP = WARENA - 64 - 2 * QBMAX * QBMAX;   // LDS for panels and GEMM tiles
 static_assert(NB == QBMAX, "one QR block is one compact-WY block");
-static_assert(2 * SW * NB + NB * NB + GEMM_LDS <= WARENA, "update carve");
+
+// Compile-time loop: f(integral_constant<int, B>), ..., f(<E - 1>).
+template <int B, int E, typename F>
+__device__ __forceinline__ void cfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    cfor<B + 1, E>(f);
+  }
+}
+
+// Sums of NV per-thread values over the workgroup, returned to every thread:
+// DPP sums within each wave, one row of NV per wave in red; for NV = 1 every
+// thread then adds the NW rows (one barrier), otherwise NV threads add them
+// and every thread reads the NV totals (two barriers, far fewer LDS reads).
+// red holds NW NV + NV doubles; callers alternate two such buffers.  The
+// barriers order LDS only, so global loads issued before them (the next
+// reflector) stay in flight.
+template <int NV>
+__device__ __forceinline__ void wg_sums(double (&v)[NV], double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[w * NV + k] = v[k];
+  }
+  lds_barrier();
+  if constexpr (NV == 1) {
+    double t = red[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) t += red[q];
+    v[0] = t;
+  } else {
+    if (tid < NV) {
+      double t = red[tid];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) t += red[q * NV + tid];
+      red[NW * NV + tid] = t;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = red[NW * NV + k];
+  }
+}
+
+// Householder QR with nonnegative diagonal of the mp x jb panel P0 (ld ld,
+// jb <= 32, mp <= 512 U), with the output of wg_geqr2 (R on and above the
+// diagonal, reflectors below it with unit leading entry implicit, tau).  The
+// columns are held in registers CW at a time (a slab; U CW = 64): thread t
+// holds rows t + 512 u of the slab.  A slab first takes the reflectors of the
+// columns before it, one at a time (one workgroup sum of CW inner products
+// each), then is factorised column by column: one workgroup sum for the
+// column's norm below the diagonal, one for its inner products with the
+// slab's later columns.  Each reflector follows wg_geqr2 (Parlett's form of
+// the leading entry, the scaled path for columns near underflow, the identity
+// when the column already lies along e_j), so both give the same factors up to
+// the order of summation.  red: 2 x NW x CW doubles of LDS; bc: 1 double.
+template <int U, int CW>
+__device__ __forceinline__ void wg_panel_qr(double* P0, int mp, int jb, int64_t ld, double* tau, double* red,
+                            double* bc, double* red2) {
+  static_assert(U * CW == 64, "64 panel values per thread");
+  const int tid = threadIdx.x;
+  int ph = 0;
+  double x[U][CW];
+  for (int sb = 0; sb < jb; sb += CW) {
+    const int cw = jb - sb < CW ? jb - sb : CW;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = tid + NT * u;
+#pragma unroll
+      for (int c = 0; c < CW; ++c)
+        x[u][c] = (r < mp && c < cw) ? P0[(int64_t)(sb + c) * ld + r] : 0.0;
+    }
+    // the reflectors of columns 0 .. sb-1, in order (left-looking)
+    double vn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = tid + NT * u;
+      vn[u] = (sb > 0 && r > 0 && r < mp) ? P0[r] : (r == 0 ? 1.0 : 0.0);
+    }
+    for (int j = 0; j < sb; ++j) {
+      double vj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) vj[u] = vn[u];
+      const double tj = tau[j];
+      if (j + 1 < sb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int r = tid + NT * u;
+          vn[u] = (r > j + 1 && r < mp) ? P0[(int64_t)(j + 1) * ld + r] : (r == j + 1 ? 1.0 : 0.0);
+        }
+      }
+      if (tj == 0.0) continue;   // uniform: tau is read by every thread
+      double d[CW];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        double a = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) a += vj[u] * x[u][c];
+        d[c] = a;
+      }
+      wg_sums<CW>(d, red + (ph++ & 1) * (NW + 1) * CW);
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        const double f = tj * d[c];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u][c] -= f * vj[u];
+      }
+    }
+    // the slab's own columns
+    cfor<0, CW>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if (c >= cw) return;
+      const int jg = sb + c;
+      double s2a[1] = {0.0};
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = tid + NT * u;
+        if (r > jg && r < mp) s2a[0] += x[u][c] * x[u][c];
+        if (r == jg) *bc = x[u][c];
+      }
+      wg_sums<1>(s2a, red + (ph++ & 1) * (NW + 1) * CW);
+      double s2 = s2a[0];
+      double alpha = *bc;
+      double scl = 1.0;
+      if (s2 > 0.0 && s2 < 0x1p-900 && !(alpha > 0.0 && s2 <= 0x1p-106 * alpha * alpha)) {
+        double mx = fabs(alpha);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int r = tid + NT * u;
+          if (r > jg && r < mp) mx = fmax(mx, fabs(x[u][c]));
+        }
+        mx = block_max(mx, red2);
+        if (mx < 0x1p-1000) {
+          s2 = 0.0;
+        } else {
+          const double inv = 1.0 / mx;
+          double t2 = 0.0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int r = tid + NT * u;
+            if (r > jg && r < mp) {
+              const double t = x[u][c] * inv;
+              t2 += t * t;
+            }
+          }
+          s2 = block_sum(t2, red2);
+          alpha *= inv;
+          scl = mx;
+        }
+      }
+      double tj, beta, inv_v0;
+      if (s2 == 0.0 || (alpha > 0.0 && s2 <= 0x1p-106 * alpha * alpha)) {
+        inv_v0 = 0.0;
+        if (alpha >= 0.0) {
+          tj = 0.0;
+          beta = alpha;
+        } else {
+          tj = 2.0;
+          beta = -alpha;
+        }
+      } else {
+        const double nrm = sqrt(alpha * alpha + s2);
+        const double v0 = (alpha <= 0.0) ? alpha - nrm : -s2 / (alpha + nrm);
+        tj = 2.0 * v0 * v0 / (s2 + v0 * v0);
+        beta = nrm;
+        inv_v0 = 1.0 / v0;
+      }
+      beta *= scl;
+      inv_v0 /= scl;
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = tid + NT * u;
+        if (r > jg && r < mp) {
+          x[u][c] *= inv_v0;
+          v[u] = x[u][c];
+        } else {
+          v[u] = r == jg ? 1.0 : 0.0;
+          if (r == jg) x[u][c] = beta;
+        }
+      }
+      if (tid == 0) tau[jg] = tj;
+      if constexpr (c + 1 < CW) {
+        if (tj != 0.0 && c + 1 < cw) {
+          double d[CW];
+#pragma unroll
+          for (int q = 0; q < CW; ++q) {
+            double a = 0.0;
+            if (q > c) {
+#pragma unroll
+              for (int u = 0; u < U; ++u) {
+                const int r = tid + NT * u;
+                // row jg of column q enters with v = 1 (x[u][q] there is its value)
+                a += v[u] * x[u][q];
+              }
+            }
+            d[q] = a;
+          }
+          wg_sums<CW>(d, red + (ph++ & 1) * (NW + 1) * CW);
+#pragma unroll
+          for (int q = c + 1; q < CW; ++q) {
+            const double f = tj * d[q];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u][q] -= f * v[u];
+          }
+        }
+      }
+    });
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = tid + NT * u;
+      if (r < mp) {
+#pragma unroll
+        for (int c = 0; c < CW; ++c)
+          if (c < cw) P0[(int64_t)(sb + c) * ld + r] = x[u][c];
+      }
+    }
+    __syncthreads();
+  }
+}
 
 // True when core i's panel is wider than the one-workgroup register path:
 // more than 128 columns, or a last-core panel taller than the TSQR leaves.
@@ -144,76 +364,122 @@ __global__ __launch_bounds__(NT) void k_wide_load(const MpoDesc* mpos, const Cor
                        Xt + (int64_t)y * rnext + f0 + (int64_t)p0 * m, 1, m, lds);
 }
 
-// Step t, column block j of core i = d - 1 - t: strip s of the trailing
-// columns (s = 0: the NB columns of block j + 1; s >= 1: SW columns each
-// after them) takes C <- (I - V T V^T)^T C = C - V (C^T V T)^T with the
-// explicit reflectors V of block j (double buffer j & 1) and its T; then the
-// workgroup of strip 0 factorises block j + 1 (rows from its diagonal down)
-// in place, writes its reflectors explicitly to the other buffer and its T.
-// j = -1 only factorises block 0.
-__global__ __launch_bounds__(NT) void k_wide_step(const MpoDesc* mpos, const CoreDesc* cores,
-                                                  int op, const int* pr, const int* rho,
-                                                  const int* wflag, int t, int j, double* Wd,
-                                                  double* WV, double* tau) {
-  __shared__ double arena[WARENA];
+// Shapes of core i = d - 1 - t of a wide MPO at step t; false when the MPO
+// has no such core with a QR (core 0 is absorbed only).
+struct WideCore {
+  int i, n, P, m, kmax;
+};
+__device__ __forceinline__ bool wide_core_at(const MpoDesc& md, const CoreDesc* cores, int op,
+                                             const int* pr, const int* rho, int t, CoreDesc& cd,
+                                             WideCore& wc) {
+  wc.i = md.d - 1 - t;
+  if (wc.i < 1) return false;
+  cd = cores[md.c0 + wc.i];
+  wc.n = op == 0 ? cd.I : cd.J;
+  wc.P = pr[md.r0 + wc.i];
+  const int rnext = (wc.i == md.d - 1) ? md.K : rho[md.r0 + wc.i + 1];
+  wc.m = wc.n * rnext;
+  wc.kmax = wc.m < wc.P ? wc.m : wc.P;
+  return true;
+}
+
+// Step t, column block j of core i = d - 1 - t: strip s (SW columns) of the
+// trailing columns takes C <- (I - V T V^T)^T C = C - V (C^T V T)^T with the
+// explicit reflectors V of block j (buffer j & 1) and its T.  A small LDS
+// footprint keeps two workgroups per compute unit.
+__global__ __launch_bounds__(NT, 4) void k_wide_update(const MpoDesc* mpos, const CoreDesc* cores,
+                                                    int op, const int* pr, const int* rho,
+                                                    const int* wflag, int t, int j, double* Wd,
+                                                    const double* WV) {
+  __shared__ double sm[2 * SW * NB + NB * NB];
   const int tid = threadIdx.x;
   const int b = blockIdx.y;
   if (!wflag[b]) return;
   const MpoDesc md = mpos[b];
-  const int i = md.d - 1 - t;
-  if (i < 1) return;   // core 0 is absorbed only
-  const CoreDesc cd = cores[md.c0 + i];
-  const int n = op == 0 ? cd.I : cd.J;
-  const int P = pr[md.r0 + i];
-  const int rnext = (i == md.d - 1) ? md.K : rho[md.r0 + i + 1];
-  const int m = n * rnext;
-  const int kmax = m < P ? m : P;
-  double* Xt = Wd + cd.w_off;
-  double* Vbuf = WV + md.wv_off;                           // 2 x wmcap x NB
-  double* qws = Vbuf + 2 * (int64_t)md.wmcap * NB;         // wmcap * 16 + 1024
-  double* Tb = Wd + cd.wt_off;                             // NB x NB per block
-  double* taui = tau + cd.tau_off;
-  const int s = blockIdx.x;
-  if (j >= 0 && NB * j < kmax) {
-    const int j0 = NB * j;
-    const int jb = kmax - j0 < NB ? kmax - j0 : NB;
-    const int mp = m - j0;
-    const int c0 = s == 0 ? j0 + jb : j0 + jb + NB + SW * (s - 1);
-    const int wcap = s == 0 ? NB : SW;
-    const int cs = P - c0 < wcap ? P - c0 : wcap;
-    if (cs > 0) {
-      double* Wt = arena;                  // C^T V, cs x jb (ld NB)
-      double* W2t = arena + SW * NB;       // C^T V T
-      double* Ts = arena + 2 * SW * NB;    // T, row-major NB x NB
-      double* lds = Ts + NB * NB;
-      const double* Vp = Vbuf + (int64_t)(j & 1) * md.wmcap * NB;
-      for (int e = tid; e < NB * NB; e += NT) Ts[e] = Tb[(int64_t)j * NB * NB + e];
-      __syncthreads();
-      double* C = Xt + (int64_t)c0 * m + j0;
-      wg_gemm_t<64, 32, double>(cs, jb, mp, 1.0, C, m, 1, Vp, 1, mp, 0.0, Wt, NB, 1, lds);
-      wg_gemm_t<64, 32, double>(cs, jb, jb, 1.0, Wt, NB, 1, Ts, NB, 1, 0.0, W2t, NB, 1, lds);
-      wg_gemm<double>(mp, cs, jb, -1.0, Vp, 1, mp, W2t, 1, NB, 1.0, C, 1, m, lds);
-    }
-  }
-  if (s != 0) return;
-  const int j1 = j + 1, j10 = NB * j1;
-  if (j10 >= kmax) return;
-  const int jb = kmax - j10 < NB ? kmax - j10 : NB;
-  const int mp = m - j10;
-  double* P0 = Xt + (int64_t)j10 * m + j10;
-  double* Ts = arena + WARENA - 32 - 2 * QBMAX * QBMAX;
-  double* Gs = Ts + QBMAX * QBMAX;
-  double* red = arena + WARENA - 16;
+  CoreDesc cd;
+  WideCore wc;
+  if (!wide_core_at(md, cores, op, pr, rho, t, cd, wc)) return;
+  const int j0 = NB * j;
+  if (j0 >= wc.kmax) return;
+  const int jb = wc.kmax - j0 < NB ? wc.kmax - j0 : NB;
+  const int mp = wc.m - j0;
+  const int c0 = j0 + jb + SW * (int)blockIdx.x;
+  const int cs = wc.P - c0 < SW ? wc.P - c0 : SW;
+  if (cs <= 0) return;
+  double* Wt = sm;                  // C^T V, cs x jb (ld NB)
+  double* W2t = sm + SW * NB;       // C^T V T
+  double* Ts = sm + 2 * SW * NB;    // T, row-major NB x NB
+  const double* Vp = WV + md.wv_off + (int64_t)(j & 1) * md.wmcap * NB;
+  const double* Tb = Wd + cd.wt_off;
+  for (int e = tid; e < NB * NB; e += NT) Ts[e] = Tb[(int64_t)j * NB * NB + e];
   __syncthreads();
-  wg_geqrf_impl<true>(P0, mp, jb, taui + j10, arena, red, qws, arena, RCAP, Ts, Gs, m, QBMAX);
-  double* Vp = Vbuf + (int64_t)(j1 & 1) * md.wmcap * NB;
+  double* C = Wd + cd.w_off + (int64_t)c0 * wc.m + j0;
+  // W^T = C^T V (cs x jb), split over K = mp rows on the matrix cores
+  wg_atb<SW / 16, NB / 16>(cs, jb, mp, C, wc.m, Vp, mp, Wt);
+  // W2^T = W^T T (T upper triangular)
+  for (int e = tid; e < cs * jb; e += NT) {
+    const int i = e / jb, q = e - i * jb;
+    double acc = 0.0;
+    for (int r = 0; r <= q; ++r) acc += Wt[i * NB + r] * Ts[r * NB + q];
+    W2t[i * NB + q] = acc;
+  }
+  __syncthreads();
+  // C -= V W2 (W2 element (q, i) = W2t[i NB + q]), by 16-row blocks
+  wg_ab_rows<SW / 16>(mp, cs, jb, -1.0, Vp, mp, W2t, 1, NB, C, wc.m);
+}
+
+// Step t: the Householder QR of column block j of core i = d - 1 - t (rows from
+// its diagonal down, in place), then its reflectors written explicitly to
+// buffer j & 1 and its T factor.  BIG = false takes panels of at most 4096
+// rows (held in registers, small LDS); BIG = true the taller ones (blocked, in
+// LDS or global memory).
+template <bool BIG>
+__global__ __launch_bounds__(NT) void k_wide_panel(const MpoDesc* mpos, const CoreDesc* cores,
+                                                   int op, const int* pr, const int* rho,
+                                                   const int* wflag, int t, int j, double* Wd,
+                                                   double* WV, double* tau) {
+  constexpr int AR = BIG ? WARENA : 2 * (NW + 1) * 32 + 64 + 2 * QBMAX * QBMAX;
+  __shared__ double arena[AR];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  if (!wflag[b]) return;
+  const MpoDesc md = mpos[b];
+  CoreDesc cd;
+  WideCore wc;
+  if (!wide_core_at(md, cores, op, pr, rho, t, cd, wc)) return;
+  const int j0 = NB * j;
+  if (j0 >= wc.kmax) return;
+  const int jb = wc.kmax - j0 < NB ? wc.kmax - j0 : NB;
+  const int mp = wc.m - j0;
+  if (BIG != (mp > 8 * NT)) return;
+  double* Xt = Wd + cd.w_off;
+  double* P0 = Xt + (int64_t)j0 * wc.m + j0;
+  double* taui = tau + cd.tau_off + j0;
+  double* Ts = arena + AR - 32 - 2 * QBMAX * QBMAX;
+  double* Gs = Ts + QBMAX * QBMAX;
+  double* red = arena + AR - 16;
+  if constexpr (BIG) {
+    double* qws = WV + md.wv_off + 2 * (int64_t)md.wmcap * NB;   // wmcap * 16 + 1024
+    wg_geqrf_impl<true>(P0, mp, jb, taui, arena, red, qws, arena, RCAP, Ts, Gs, wc.m, QBMAX);
+  } else {
+    double* pred = arena;            // 2 (NW + 1) 32 doubles
+    double* pbc = arena + 2 * (NW + 1) * 32;
+    if (mp <= 2 * NT)
+      wg_panel_qr<2, 32>(P0, mp, jb, wc.m, taui, pred, pbc, red);
+    else if (mp <= 4 * NT)
+      wg_panel_qr<4, 16>(P0, mp, jb, wc.m, taui, pred, pbc, red);
+    else
+      wg_panel_qr<8, 8>(P0, mp, jb, wc.m, taui, pred, pbc, red);
+  }
+  double* Vp = WV + md.wv_off + (int64_t)(j & 1) * md.wmcap * NB;
   for (int64_t e = tid; e < (int64_t)mp * jb; e += NT) {
     const int c = (int)(e / mp), r = (int)(e - (int64_t)c * mp);
-    Vp[e] = r > c ? P0[(int64_t)c * m + r] : (r == c ? 1.0 : 0.0);
+    Vp[e] = r > c ? P0[(int64_t)c * wc.m + r] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  wg_build_t(Vp, mp, jb, taui + j10, Ts, Gs, arena);
-  for (int e = tid; e < NB * NB; e += NT) Tb[(int64_t)j1 * NB * NB + e] = Ts[e];
+  wg_build_t(Vp, mp, jb, taui, Ts, Gs, nullptr);
+  double* Tb = Wd + cd.wt_off;
+  for (int e = tid; e < NB * NB; e += NT) Tb[(int64_t)j * NB * NB + e] = Ts[e];
 }
 
 // Step t: ldm, rho and R (rows f < k of the factorised panel, q >= f) to the
@@ -294,11 +560,22 @@ hipError_t launch_rl_wide_step(const MpoDesc* mpos, const CoreDesc* cores, int b
     k_wide_load<T><<<dim3(gx, batch), NT, 0, s>>>(mpos, cores, op, pr, rho, wflag, t, tf_n, tp_n,
                                                   (const T*)Z, Wd, L);
   });
-  for (int j = -1; j < nb; ++j) {
-    const int rest = Pm - NB * (j + 1) - NB;   // columns after strip 0
-    const int ns = j < 0 ? 1 : 1 + (rest > 0 ? (rest + SW - 1) / SW : 0);
-    k_wide_step<<<dim3(ns, batch), NT, 0, s>>>(mpos, cores, op, pr, rho, wflag, t, j, Wd, WV, tau);
+  const bool big = mm > 8 * NT;   // some panel taller than the register path
+  // update(jj) after the panel of block jj: the columns right of it, which
+  // start at NB jj + 1 or later (a last block may be narrower than NB)
+  auto update = [&](int jj) {
+    const int rest = Pm - NB * jj - 1;
+    if (rest > 0)
+      k_wide_update<<<dim3((rest + SW - 1) / SW, batch), NT, 0, s>>>(mpos, cores, op, pr, rho,
+                                                                     wflag, t, jj, Wd, WV);
+  };
+  for (int j = 0; j < nb; ++j) {
+    if (j > 0) update(j - 1);
+    k_wide_panel<false><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, wflag, t, j, Wd, WV, tau);
+    if (big)
+      k_wide_panel<true><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, wflag, t, j, Wd, WV, tau);
   }
+  if (nb > 0) update(nb - 1);
   k_wide_finish<<<dim3(tp_n, batch), NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, wflag, t, Wd, L);
   return hipGetLastError();
 }

@@ -288,6 +288,114 @@ __device__ void wg_gemm_t(int M, int N, int K, double alpha, const double* A, in
   __syncthreads();
 }
 
+// C (M x N) = A^T B for a long reduction dimension K, with A (K x M, element
+// (k, i) at A[i lda + k]) and B (K x N, element (k, j) at B[j ldb + k]),
+// M <= 16 MB, N <= 16 NBK, on the FP64 matrix cores without LDS staging: the
+// waves take interleaved 16-deep slices of K, each loading its MFMA operands
+// straight from memory (four k-steps in flight) and accumulating all of C;
+// the partial results are then added into acc (LDS, row-major, ld 16 NBK) by
+// LDS atomics.  Within a slice, the lanes of one row (or column) group read
+// four consecutive k each, so a slice of a row is one contiguous 128-byte run;
+// A and B use the same k order, so the sum is unchanged.  acc is cleared
+// here; ends with a barrier.
+template <int MB, int NBK>
+__device__ void wg_atb(int M, int N, int K, const double* __restrict__ A, int64_t lda,
+                       const double* __restrict__ B, int64_t ldb, double* acc) {
+  constexpr int LDC = 16 * NBK;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  for (int e = tid; e < 16 * MB * LDC; e += NT) acc[e] = 0.0;
+  dbl4 c[MB][NBK];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NBK; ++j) c[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 16 * w; k0 < K; k0 += 16 * NW) {
+    double a[4][MB], b[4][NBK];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = k0 + 4 * q4 + st;
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        const int row = 16 * i + r16;
+        const bool ok = k < K && row < M;
+        const double v = A[ok ? (int64_t)row * lda + k : 0];
+        a[st][i] = ok ? v : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < NBK; ++j) {
+        const int col = 16 * j + r16;
+        const bool ok = k < K && col < N;
+        const double v = B[ok ? (int64_t)col * ldb + k : 0];
+        b[st][j] = ok ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NBK; ++j)
+          c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], c[i][j], 0, 0, 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NBK; ++j)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int row = 16 * i + 4 * jj + q4, col = 16 * j + r16;
+        if (row < M && col < N) atomicAdd(acc + row * LDC + col, c[i][j][jj]);
+      }
+  __syncthreads();
+}
+
+// C (mp x N, column-major, ld ldc) += alpha A B with A (mp x KK, column-major,
+// ld lda), KK <= 32, and B small (element (k, j) at B[k sbk + j sbj], usually
+// LDS), N <= 16 NBK, on the FP64 matrix cores: each wave takes 16-row blocks
+// of C in turn, with no barrier.  The caller orders B's writes before the call
+// and C's use after it.
+template <int NBK>
+__device__ void wg_ab_rows(int mp, int N, int KK, double alpha, const double* __restrict__ A,
+                           int64_t lda, const double* B, int sbk, int sbj, double* C,
+                           int64_t ldc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  double b[8][NBK];
+#pragma unroll
+  for (int st = 0; st < 8; ++st) {
+    const int k = 4 * st + q4;
+#pragma unroll
+    for (int j = 0; j < NBK; ++j) {
+      const int col = 16 * j + r16;
+      b[st][j] = (k < KK && col < N) ? B[k * sbk + col * sbj] : 0.0;
+    }
+  }
+  for (int r0 = 16 * w; r0 < mp; r0 += 16 * NW) {
+    dbl4 c[NBK];
+#pragma unroll
+    for (int j = 0; j < NBK; ++j) c[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int row = r0 + r16;
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int k = 4 * st + q4;
+      const bool ok = k < KK && row < mp;
+      const double v = A[ok ? (int64_t)k * lda + row : 0];
+      const double a = ok ? v : 0.0;
+#pragma unroll
+      for (int j = 0; j < NBK; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[st][j], c[j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < NBK; ++j)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int rr = r0 + 4 * jj + q4, col = 16 * j + r16;
+        if (rr < mp && col < N) C[(int64_t)col * ldc + rr] += alpha * c[j][jj];
+      }
+  }
+}
+
 template <typename TB>
 __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int64_t sai,
                         int64_t sak, const TB* B, int64_t sbk, int64_t sbj, double beta, double* C,
@@ -300,13 +408,14 @@ constexpr int QBMAX = 32;   // widest block; Ts and Gs are QBMAX x QBMAX
 
 // Compact WY factor of jb <= QBMAX reflectors held explicitly in Vp (mp x jb,
 // column-major, unit diagonal, zeros above it): H_0 ... H_{jb-1} = I - V T V^T
-// with T upper triangular (row-major in Ts, ld QBMAX).  G = V^T V goes to Gs,
-// then the forward recurrence T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i].
-// Ends with a barrier.
+// with T upper triangular (row-major in Ts, ld QBMAX).  G = V^T V goes to Gs
+// (split-K on the matrix cores), then the forward recurrence T_ii = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i].  Ends with a barrier.
 __device__ void wg_build_t(const double* Vp, int mp, int jb, const double* tau, double* Ts,
                            double* Gs, double* lds) {
   const int tid = threadIdx.x;
-  wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QBMAX, 1, lds);
+  (void)lds;
+  wg_atb<2, 2>(jb, jb, mp, Vp, mp, Vp, mp, Gs);
   if (tid < 64) {
     for (int i = 0; i < jb; ++i) {
       const double ti = tau[i];
