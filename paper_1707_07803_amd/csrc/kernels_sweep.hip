@@ -451,14 +451,18 @@ template <typename T, int PH>
 __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int op,
                                                 const int* pr, int* rho, int* ldm,
                                                 const T* __restrict__ Z, double* Wd, double* L,
-                                                double* tau, int* err, const int* wflag) {
+                                                double* tau, int* err, const int* wflag,
+                                                const int* order) {
   __shared__ double arena[ARENA];
   double* vb = arena;                 // 2 * QROWS (register path) or m (global path)
   double* tb = arena + ARENA - 32;    // 2 doubles
   double* red = arena + ARENA - 16;   // NW doubles
   const int tid = threadIdx.x;
-  if (wflag && wflag[blockIdx.x]) return;   // taken by the multi-workgroup path
-  const MpoDesc md = mpos[blockIdx.x];
+  // workgroups take the MPOs costliest first (order), so that the last ones
+  // dispatched are short
+  const int b = order ? order[blockIdx.x] : (int)blockIdx.x;
+  if (wflag && wflag[b]) return;   // taken by the multi-workgroup path
+  const MpoDesc md = mpos[b];
   const int d = md.d;
   if (PH == 0 && tid == 0) rho[md.r0 + d] = md.K;
   int rnext = PH == 0 ? md.K : rho[md.r0 + d - 1];
@@ -821,7 +825,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
                                                 double* scratch, TO* __restrict__ Xout,
                                                 double* outs, SweepOpts so, int64_t tcap,
                                                 int64_t mcap_s, int64_t ucap, int* err,
-                                                const int* wflag) {
+                                                const int* wflag, const int* order) {
   __shared__ double arena[ARENA];
   __shared__ int iarena[LR_SC + 16];
   double* Mb = arena;
@@ -835,9 +839,10 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
   int* perm = iarena;
   int* ibuf = iarena + LR_SC;
   const int tid = threadIdx.x;
-  const MpoDesc md = mpos[blockIdx.x];
+  const int bm = order ? order[blockIdx.x] : (int)blockIdx.x;   // costliest MPOs first
+  const MpoDesc md = mpos[bm];
   const int d = md.d, K = md.K;
-  const bool wide = wflag && wflag[blockIdx.x];   // panels factorised by kernels_wide.hip
+  const bool wide = wflag && wflag[bm];   // panels factorised by kernels_wide.hip
   ScratchLayout SL;
   SL.T = scratch + md.s_off;
   SL.M = SL.T + tcap;
@@ -918,9 +923,13 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       // the QR's scalars (the Jacobi then works from L2)
       const bool pre_lds = nv * nv <= LR_MB && nvg * nvg <= LR_UB &&
                            (int64_t)rn * (QB + 1) <= LR_VB;
-      const bool pre_glob = !pre_lds && nv <= 256 && rn <= LR_VB &&
+      // larger R^T (up to 128 x 128) over the whole M, V and U carve, with U in
+      // the scratch; past that R^T goes to the scratch too
+      const bool pre_wide = !pre_lds && nv * nv <= LR_MB + LR_VB + LR_UB && nvg * nvg > LR_UB &&
+                            rn <= LR_VB;
+      const bool pre_glob = !pre_lds && !pre_wide && nv <= 256 && rn <= LR_VB &&
                             (int64_t)rn * QB + 2 * QB * nv + nv + nvg * nvg <= so.qcap;
-      const bool pre = !m_in_lds && nv < rn && (pre_lds || pre_glob) &&
+      const bool pre = !m_in_lds && nv < rn && (pre_lds || pre_wide || pre_glob) &&
                        2 * QBMAX * QBMAX <= LR_UB &&
                        (int64_t)rn * QB + 2 * QB * nv + nv <= so.qcap;
       double* B = M;
@@ -928,7 +937,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       double* tauP = SL.Q + (int64_t)rn * QB + 2 * QB * nv;
       if (pre) {
         wg_geqrf(M, rn, nv, tauP, Vb, red, SL.Q, Vb, LR_VB, Ub, Ub + QBMAX * QBMAX, ld, QB);
-        double* Bt = pre_lds ? Mb : tauP + nv;
+        double* Bt = (pre_lds || pre_wide) ? Mb : tauP + nv;
         for (int e = tid; e < nv * nv; e += NT) {
           const int p = e / nv, c = e - p * nv;
           Bt[e] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T
@@ -1049,7 +1058,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
                           double* L, double* tau, int* err, int leaf_nc, const int* wflag,
-                          hipStream_t s) {
+                          const int* order, hipStream_t s) {
   by_dtype(dtype, [&](auto* t) {
     using T = elem_t<decltype(t)>;
     if (leaf_nc > 1) {
@@ -1063,9 +1072,9 @@ hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
       }
     }
     k_rl_pass<T, 0><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,
-                                         err, wflag);
+                                         err, wflag, order);
     k_rl_pass<T, 1><<<batch, NT, 0, s>>>(mpos, cores, op, pr, rho, ldm, (const T*)Z, Wd, L, tau,
-                                         err, wflag);
+                                         err, wflag, order);
   });
   return hipGetLastError();
 }
@@ -1074,11 +1083,11 @@ hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
                           const int* rho, const int* ldm, int* xr, const double* Wd,
                           const double* tau, double* scratch, void* Xout, int out_dtype,
                           double* outs, SweepOpts o, int64_t tcap, int64_t mcap_s, int64_t ucap,
-                          int* err, const int* wflag, hipStream_t s) {
+                          int* err, const int* wflag, const int* order, hipStream_t s) {
   by_dtype(out_dtype, [&](auto* t) {
     using T = elem_t<decltype(t)>;
     k_lr_pass<T><<<batch, NT, 0, s>>>(mpos, cores, op, rho, ldm, xr, Wd, tau, scratch, (T*)Xout,
-                                      outs, o, tcap, mcap_s, ucap, err, wflag);
+                                      outs, o, tcap, mcap_s, ucap, err, wflag, order);
   });
   return hipGetLastError();
 }

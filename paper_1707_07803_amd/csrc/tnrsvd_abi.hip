@@ -126,6 +126,10 @@ struct tnrsvd_s {
   // capacities allow a panel beyond the register path; per MPO flag; the
   // device-side needs of the current rounding; the capacity plan; the plan of
   // each rounding of a solve as last measured (used when a solve is captured)
+  // MPOs in decreasing order of a sweep-cost estimate (sum over cores of n P^2),
+  // the order the one-workgroup-per-MPO sweeps dispatch them in
+  int* order_d = nullptr;
+  std::vector<int> order;
   bool wide_possible = false;
   double* WV = nullptr;
   int *wflag_d = nullptr, *wneed_d = nullptr, *wcap_d = nullptr, *wplan_d = nullptr;
@@ -545,6 +549,7 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   ALLOC(h->U, sizeof(double) * x_tot);
   ALLOC(h->V, sizeof(double) * x_tot);
   ALLOC(h->tail, sizeof(double) * tail_tot);
+  ALLOC(h->order_d, sizeof(int) * batch);
   if (h->wide_possible) {
     h->wcap.resize((size_t)kWidePlan * h->max_d, 0);
     // one plan slot per rounding of a solve (2q + 2), three more for tnrsvd_refine
@@ -594,6 +599,22 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   if ((e = hipMemcpyAsync(h->core_mpo_d, h->core_mpo.data(), sizeof(int) * h->ncores,
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail_dev(e, "upload core map");
+  {
+    std::vector<double> cost(batch, 0.0);
+    for (int b = 0; b < batch; ++b)
+      for (int i = 0; i < h->mh[b].d; ++i) {
+        const CoreDesc& cd = h->ch[h->mh[b].c0 + i];
+        const double P = (double)cd.RA * cd.xcap;
+        cost[b] += (double)std::max(cd.I, cd.J) * P * P;
+      }
+    h->order.resize(batch);
+    for (int b = 0; b < batch; ++b) h->order[b] = b;
+    std::stable_sort(h->order.begin(), h->order.end(),
+                     [&](int a, int c) { return cost[a] > cost[c]; });
+    if ((e = hipMemcpyAsync(h->order_d, h->order.data(), sizeof(int) * batch,
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+      return fail_dev(e, "upload MPO order");
+  }
   if (h->wide_possible &&
       (e = hipMemcpyAsync(h->wcap_d, h->wcap.data(), sizeof(int) * h->wcap.size(),
                           hipMemcpyHostToDevice, s)) != hipSuccess)
@@ -917,7 +938,7 @@ tnrsvd_status rl_sweep(tnrsvd_t h, int op) {
   {
     Timed tm(h, 1);
     e = launch_rl_pass(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->rho, h->ldm, h->Z, h->dtype,
-                       h->W, h->L, h->tau, h->err, h->leaf_nc, wflag, h->stream);
+                       h->W, h->L, h->tau, h->err, h->leaf_nc, wflag, h->order_d, h->stream);
     TRY(dev_check(e, "right-to-left sweep"));
     if (plan) {
       for (int t = 0; t < h->max_d; ++t) {
@@ -945,7 +966,7 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   int* rout = mode == 0 ? h->xr : h->vr;
   e = launch_lr_pass(h->mpos_d, h->cores_d, h->batch, op, h->rho, h->ldm, rout, h->W, h->tau,
                      h->scratch, out, odt, h->outs, so, h->tcap, h->mcap_s, h->ucap, h->err,
-                     h->wide_possible ? h->wflag_d : nullptr, h->stream);
+                     h->wide_possible ? h->wflag_d : nullptr, h->order_d, h->stream);
   return dev_check(e, "left-to-right sweep");
 }
 

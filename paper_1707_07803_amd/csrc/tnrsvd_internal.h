@@ -198,7 +198,7 @@ hipError_t launch_copy_y0(const MpoDesc* mpos, const CoreDesc* cores, const int*
 hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                           const int* pr, int* rho, int* ldm, const void* Z, int dtype, double* Wd,
                           double* L, double* tau, int* err, int leaf_nc, const int* wflag,
-                          hipStream_t s);
+                          const int* order, hipStream_t s);
 // Wide right-to-left pass (kernels_wide.hip).  Per step t (core d-1-t of every
 // MPO) the plan holds kWidePlan ints: column blocks of the QR, and bounds on
 // P, panel rows m, rho' and the mode size n (grid sizes of the launches).
@@ -215,7 +215,7 @@ hipError_t launch_lr_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
                           const int* rho, const int* ldm, int* xr, const double* Wd,
                           const double* tau, double* scratch, void* Xout, int out_dtype,
                           double* outs, SweepOpts o, int64_t tcap, int64_t mcap_s, int64_t ucap,
-                          int* err, const int* wflag, hipStream_t s);
+                          int* err, const int* wflag, const int* order, hipStream_t s);
 hipError_t launch_form_u(const MpoDesc* mpos, const CoreDesc* cores, const int* core_mpo,
                          int ncores, const int* xr, const void* X, int dtype, const double* outs,
                          double* U, int64_t max_out, int* err, hipStream_t s);
