@@ -62,6 +62,8 @@ def parse():
                     help="time the whole 512-MPO uneven batch once (minutes) and exit")
     ap.add_argument("--only-configs", action="store_true",
                     help="time only the other workloads (large, batched subset, gradient)")
+    ap.add_argument("--no-batched-uneven", action="store_true",
+                    help="skip the 512-MPO uneven batch (about a minute)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the timings of the other workloads (plain FP64, large, "
                          "batched uneven subset, gradient)")
@@ -242,18 +244,6 @@ def other_configs():
                     "sigma_rel_diff_sketch48_vs_f64": float(
                         np.linalg.norm(res["f32+sketch48"][1] - res["f64"][1])
                         / np.linalg.norm(res["f64"][1]))}
-    Ws = wl.batched(512)
-    cost = [len(w.cores) * w.cores[0].shape[1] ** 2 * w.cores[1].shape[0] ** 3 for w in Ws]
-    sel = sorted(range(len(Ws)), key=lambda b: cost[b])[:128]
-    h = TNrSVD([dev(Ws[b].cores, "f32") for b in sel], 8, 8, 1, seed=9, precision="f32",
-               max_rank=32)
-    dt = timed(h, lambda: h.run_graph(False), 1)
-    out["batched_uneven_subset"] = {
-        "workload": "the 128 cheapest of the 512 uneven MPOs (d in [10,40], I=J in {2,4}, "
-                    "ranks in [4,32]), k=8 p=8 q=1, FP32, one persistent launch per pass, "
-                    "hipGraph replay",
-        "solves_per_s": round(128 / dt, 2), "ms_per_batch": round(1e3 * dt, 2)}
-    h.close()
     W = wl.grad()
     cores = dev(W.cores, "f32")
     h = TNrSVD(cores, W.k, W.p, W.q, seed=W.omega_seed, precision="f32", max_rank=W.rmax)
@@ -270,6 +260,161 @@ def other_configs():
                    "forward_sketch64_s": round(ts, 4)}
     h.close()
     return out
+
+
+def batched_accounted_solve(h, Ws, K, esz):
+    """One eager solve of a batch handle, step by step, adding up the algorithmic
+    work of every product and right-to-left sweep from each MPO's device ranks
+    (contraction bytes and flops; Householder flops of the sweep)."""
+    import numpy as np
+    tot = {"contract_bytes": 0.0, "contract_flops": 0.0, "rl_flops": 0.0}
+    shapes = []
+    for w in Ws:
+        R = [w.cores[0].shape[0]] + [c.shape[3] for c in w.cores]
+        I = [c.shape[1] for c in w.cores]
+        J = [c.shape[2] for c in w.cores]
+        shapes.append((R, I, J))
+
+    def account(op):
+        for b, (R, I, J) in enumerate(shapes):
+            P, rho = h.product_ranks(b)
+            d = len(P) - 1
+            # merged layout: the trailing cores form the last one
+            Im = I[: d - 1] + [int(np.prod(I[d - 1:]))]
+            Jm = J[: d - 1] + [int(np.prod(J[d - 1:]))]
+            Rm = R[:d] + [1]
+            by, fl = contraction_counts(Rm, Im, Jm, P, op, K, esz)
+            tot["contract_bytes"] += by
+            tot["contract_flops"] += fl
+            tot["rl_flops"] += rl_sweep_flops(P, rho, Im if op == 0 else Jm)
+
+    h.mult(0)
+    h.orthogonalize()
+    account(0)
+    h.mult(1)
+    h.orthogonalize()
+    account(1)
+    h.mult(0)
+    h.orthogonalize()
+    account(0)
+    h.project()
+    h.solve(want_sigma=False)
+    account(1)
+    return tot
+
+
+def batched_uneven_full(cpu_budget):
+    """The batched-uneven workload at its stated shape: all 512 MPOs of the draw
+    (d in [10,40], I=J in {2,4}, ranks in [4,32], N(0,1/R) cores; k=8 p=8 q=1,
+    r_max=32) in one handle.  Per precision: one accounted warm-up solve, then one
+    timed solve with per-kernel events.  Beside it, the FP64 oracle on a bounded
+    sample of the same members, as a sequential loop and as a process pool."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1707_07803_amd import TNrSVD
+
+    Ws = wl.batched(512)
+    out = {"workload": "512 uneven MPOs (d in [10,40], I=J in {2,4}, ranks in [4,32], "
+                       "N(0,1/R) cores), k=8 p=8 q=1, r_max=32, one handle",
+           "precisions": {}}
+    sig = {}
+    for p in ("f32", "f64"):
+        td = torch.float64 if p == "f64" else torch.float32
+        mpos = [[torch.as_tensor(c, dtype=td).cuda() for c in w.cores] for w in Ws]
+        h = TNrSVD(mpos, 8, 8, 1, seed=9, precision=p, max_rank=32)
+        del mpos
+        esz = 8 if p == "f64" else 4
+        acc = batched_accounted_solve(h, Ws, 16, esz)
+        torch.cuda.synchronize()
+        h.profile(True)
+        t0 = time.perf_counter()
+        h.run(False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kern = {k: h.profile_read(k) for k in ("contract", "rl_sweep", "lr_sweep", "form_u")}
+        h.profile(False)
+        sig[p] = h.run()
+        h.close()
+        rl_ms = kern["rl_sweep"][0]
+        ct_ms = kern["contract"][0]
+        rl_tf = acc["rl_flops"] / (rl_ms * 1e-3) / 1e12
+        gbs = acc["contract_bytes"] / (ct_ms * 1e-3) / 1e9
+        out["precisions"][p] = {
+            "seconds_per_batch": round(dt, 3), "solves_per_s": round(512 / dt, 3),
+            "kernel_ms_per_batch": {k: round(v[0], 1) for k, v in kern.items()},
+            "sweep_roofline": {"bound": "alu", "kernel": "right-to-left sweeps (one-workgroup "
+                               "kernels and the multi-workgroup wide-panel launches)",
+                               "achieved": round(rl_tf, 3), "peak": FP64_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(rl_tf / FP64_PEAK_TFLOPS, 5),
+                               "algorithmic_flops_per_batch": acc["rl_flops"]},
+            "contraction": {"achieved_GBps": round(gbs, 2),
+                            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 5),
+                            "algorithmic_bytes_per_batch": acc["contract_bytes"]}}
+        print(f"[bench] batched 512 uneven {p}: {dt:.2f} s per batch", file=sys.stderr, flush=True)
+    d = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(sig["f32"], sig["f64"])]
+    out["max_sigma_rel_diff_f32_vs_f64"] = max(d)
+    out["mixed_vs_fp64_speedup"] = round(out["precisions"]["f64"]["seconds_per_batch"] /
+                                         out["precisions"]["f32"]["seconds_per_batch"], 3)
+    if cpu_budget > 0:
+        out["cpu_baseline"] = batched_oracle_sample(Ws, cpu_budget)
+    return out
+
+
+_DRAW = []
+
+
+def _oracle_member(b):
+    """One member of the uneven draw through the oracle (seed 9 + b, as the
+    library's handle seeds its b-th MPO)."""
+    from oracle import tnrsvd_oracle as o
+    import workloads as wl
+    if not _DRAW:
+        _DRAW.extend(wl.batched(512))
+    w = _DRAW[b]
+    o.tnrsvd(w.cores, 8, 8, 1, seed=9 + b, eps=0.0, rmax=32)
+    return b
+
+
+def batched_oracle_sample(Ws, budget):
+    """The FP64 oracle on members of the uneven draw: the cheaper half by a cost
+    estimate (d n^2 R^3), in a fixed shuffled order (seed 0), as a sequential
+    loop until `budget` seconds have passed, then the same members as a process
+    pool over the host's cores (one BLAS thread per process).  A bounded sample,
+    not the whole batch: the costlier half (up to 85 s per member on one host)
+    is left out."""
+    import multiprocessing as mp
+    import numpy as np
+    cost = [len(w.cores) * w.cores[0].shape[1] ** 2 * w.cores[1].shape[0] ** 3 for w in Ws]
+    med = float(np.median(cost))
+    order = [int(b) for b in np.random.default_rng(0).permutation(len(Ws)) if cost[b] <= med]
+    t0 = time.perf_counter()
+    done = []
+    for b in order:
+        _oracle_member(int(b))
+        done.append(int(b))
+        if time.perf_counter() - t0 >= budget:
+            break
+    seq = time.perf_counter() - t0
+    ncpu = os.cpu_count() or 1
+    env = dict(os.environ)
+    os.environ.update({"OMP_NUM_THREADS": "1", "OPENBLAS_NUM_THREADS": "1", "MKL_NUM_THREADS": "1"})
+    try:
+        ctx = mp.get_context("spawn")
+        t1 = time.perf_counter()
+        with ctx.Pool(min(ncpu, 16)) as pool:
+            pool.map(_oracle_member, done)
+        par = time.perf_counter() - t1
+    finally:
+        os.environ.clear()
+        os.environ.update(env)
+    return {"sample": f"{len(done)} members of the cheaper half of the 512 (by d n^2 R^3), "
+                      f"fixed shuffled order (first: {done[:8]})",
+            "sequential": {"value": round(len(done) / seq, 4), "unit": "solves/s",
+                           "cores": blas_threads(), "seconds": round(seq, 2)},
+            "process_pool": {"value": round(len(done) / par, 4), "unit": "solves/s",
+                             "processes": min(ncpu, 16), "seconds": round(par, 2)},
+            "os_cpu_count": ncpu, "kind": "oracle"}
 
 
 def sparse_section(steps, cpu_baseline_on):
@@ -536,6 +681,15 @@ def blas_threads():
         return os.cpu_count() or 1
 
 
+def cpu_baseline_1thread(W, eps, budget):
+    """The same oracle run with BLAS limited to one thread."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        res, _ = cpu_baseline(W, eps, budget)
+    res["cores"] = 1
+    return res
+
+
 def cpu_baseline(W, eps, budget):
     import numpy as np
     from oracle import tnrsvd_oracle as o
@@ -552,7 +706,7 @@ def cpu_baseline(W, eps, budget):
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} full solves of the same workload (FP64 numpy/LAPACK, eps={eps:g})",
-            "seconds": round(dt, 3)}, sig
+            "seconds": round(dt, 3), "os_cpu_count": os.cpu_count()}, sig
 
 
 def copy_calibration(mib):
@@ -672,6 +826,10 @@ def main():
                   file=sys.stderr, flush=True)
         batched["variants"] = variants
 
+    batched_uneven = None
+    if not args.no_batched_uneven:
+        batched_uneven = batched_uneven_full(0 if args.no_cpu_baseline else args.cpu_seconds)
+
     configs = None
     if not args.no_configs:
         configs = other_configs()
@@ -721,6 +879,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu, osig = cpu_baseline(W, W.eps_by_precision["f64"], args.cpu_seconds)
+        try:
+            cpu["single_thread"] = cpu_baseline_1thread(W, W.eps_by_precision["f64"],
+                                                        args.cpu_seconds / 2)
+        except ImportError:
+            cpu["single_thread"] = None
         for p in paths:
             s = final_sigma(p)
             sig_err[p]["vs_oracle"] = float(np.linalg.norm(s - osig) / np.linalg.norm(osig))
@@ -745,6 +908,7 @@ def main():
         "cpu_baseline": cpu,
         "contraction": contraction,
         "batched": batched,
+        "batched_uneven_512": batched_uneven,
         "sparse_to_mpo": sparse,
         "hilbert": hilbert,
         "other_configs": configs,

@@ -293,18 +293,17 @@ __device__ void wg_gemm_t(int M, int N, int K, double alpha, const double* A, in
 // M <= 16 MB, N <= 16 NBK, on the FP64 matrix cores without LDS staging: the
 // waves take interleaved 16-deep slices of K, each loading its MFMA operands
 // straight from memory (four k-steps in flight) and accumulating all of C;
-// the partial results are then added into acc (LDS, row-major, ld 16 NBK) by
-// LDS atomics.  Within a slice, the lanes of one row (or column) group read
-// four consecutive k each, so a slice of a row is one contiguous 128-byte run;
-// A and B use the same k order, so the sum is unchanged.  acc is cleared
-// here; ends with a barrier.
+// the partial results are then added into acc (LDS, row-major, ld 16 NBK)
+// one wave after the other, in wave order, so the result does not depend on
+// timing.  Within a slice, the lanes of one row (or column) group read four
+// consecutive k each, so a slice of a row is one contiguous 128-byte run; A
+// and B use the same k order, so the sum is unchanged.  Ends with a barrier.
 template <int MB, int NBK>
 __device__ void wg_atb(int M, int N, int K, const double* __restrict__ A, int64_t lda,
                        const double* __restrict__ B, int64_t ldb, double* acc) {
   constexpr int LDC = 16 * NBK;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  for (int e = tid; e < 16 * MB * LDC; e += NT) acc[e] = 0.0;
   dbl4 c[MB][NBK];
 #pragma unroll
   for (int i = 0; i < MB; ++i)
@@ -338,17 +337,22 @@ __device__ void wg_atb(int M, int N, int K, const double* __restrict__ A, int64_
         for (int j = 0; j < NBK; ++j)
           c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], c[i][j], 0, 0, 0);
   }
-  __syncthreads();
+  __syncthreads();   // acc may still be read by the caller's previous step
+  for (int q = 0; q < NW; ++q) {
+    if (w == q) {
 #pragma unroll
-  for (int i = 0; i < MB; ++i)
+      for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int j = 0; j < NBK; ++j)
+        for (int j = 0; j < NBK; ++j)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int row = 16 * i + 4 * jj + q4, col = 16 * j + r16;
-        if (row < M && col < N) atomicAdd(acc + row * LDC + col, c[i][j][jj]);
-      }
-  __syncthreads();
+          for (int jj = 0; jj < 4; ++jj) {
+            const int row = 16 * i + 4 * jj + q4, col = 16 * j + r16;
+            if (row < 16 * MB && col < LDC)
+              acc[row * LDC + col] = (q == 0 ? 0.0 : acc[row * LDC + col]) + c[i][j][jj];
+          }
+    }
+    __syncthreads();
+  }
 }
 
 // C (mp x N, column-major, ld ldc) += alpha A B with A (mp x KK, column-major,

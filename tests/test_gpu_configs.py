@@ -7,7 +7,16 @@
   ranks in [4, 32]; k = 8, p = 8, q = 1, FP32) solved together in one
   persistent launch; the oracle recomputes sampled members one by one (the
   cheapest of the draw, so the CPU side stays within seconds).
+* the three costliest members of the draw (R = 32, 32, 29 with 4 x 4 cores,
+  product ranks up to 1024, right-to-left panels up to 4096 x 1024, so the
+  multi-workgroup path; one with d = 40) interleaved with three cheap ones in
+  one handle, FP32 and FP64, against oracle singular values stored by
+  tests/golden/make_batched_members.py; and the same batch replayed as a
+  captured graph, bit-equal to the eager solve.
 """
+
+import json
+import os
 
 import numpy as np
 import pytest
@@ -19,6 +28,7 @@ from tests.gpu_helpers import omega_for, gpu_solve, rel_err, to_device
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-10, "f32": 1e-5}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batched_members.json")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -65,4 +75,38 @@ def test_batched_uneven_sampled_members():
         print(f"batched member {sel[j]} (d={len(w.cores)}, I={w.cores[0].shape[1]}, "
               f"R={w.cores[1].shape[0]}): {err:.3e}")
         assert err <= TOL["f32"]
+    h.close()
+
+
+def _costly_batch(precision):
+    from paper_1707_07803_amd import TNrSVD
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    Ws = wl.batched(512)
+    members = [m["member"] for m in gold["members"]]
+    h = TNrSVD([to_device(Ws[b].cores, precision) for b in members], gold["k"], gold["p"],
+               gold["q"], seed=gold["seed_base"], precision=precision, max_rank=gold["rmax"])
+    return gold, h
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batched_uneven_costliest_members(precision):
+    gold, h = _costly_batch(precision)
+    sig = h.run()
+    for j, m in enumerate(gold["members"]):
+        err = rel_err(sig[j], m["sigma"])
+        print(f"batched member {m['member']} (d={m['d']}, I={m['I']}, R={m['R']}) {precision}: "
+              f"sigma rel err {err:.3e}")
+        assert err <= TOL[precision]
+    h.close()
+
+
+def test_batched_uneven_costliest_members_graph_replay():
+    gold, h = _costly_batch("f32")
+    eager = h.run()
+    for _ in range(2):
+        rep = h.run_graph()
+        assert np.array_equal(rep, eager)
+        again = h.run()
+        assert np.array_equal(again, eager)
     h.close()
