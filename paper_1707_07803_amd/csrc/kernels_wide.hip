@@ -477,7 +477,7 @@ __global__ __launch_bounds__(NT) void k_wide_panel(const MpoDesc* mpos, const Co
     Vp[e] = r > c ? P0[(int64_t)c * wc.m + r] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  wg_build_t(Vp, mp, jb, taui, Ts, Gs, nullptr);
+  wg_build_t_splitk(Vp, mp, jb, taui, Ts, Gs);
   double* Tb = Wd + cd.wt_off;
   for (int e = tid; e < NB * NB; e += NT) Tb[(int64_t)j * NB * NB + e] = Ts[e];
 }

@@ -410,16 +410,11 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* A, int6
 constexpr int QB = 16;      // block width of the left-to-right pass
 constexpr int QBMAX = 32;   // widest block; Ts and Gs are QBMAX x QBMAX
 
-// Compact WY factor of jb <= QBMAX reflectors held explicitly in Vp (mp x jb,
-// column-major, unit diagonal, zeros above it): H_0 ... H_{jb-1} = I - V T V^T
-// with T upper triangular (row-major in Ts, ld QBMAX).  G = V^T V goes to Gs
-// (split-K on the matrix cores), then the forward recurrence T_ii = tau_i,
-// T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i].  Ends with a barrier.
-__device__ void wg_build_t(const double* Vp, int mp, int jb, const double* tau, double* Ts,
-                           double* Gs, double* lds) {
+// T of the compact WY form from G = V^T V already in Gs: the forward
+// recurrence T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i] (one wave).
+// Ends with a barrier.
+__device__ void wg_t_from_gram(int jb, const double* tau, double* Ts, const double* Gs) {
   const int tid = threadIdx.x;
-  (void)lds;
-  wg_atb<2, 2>(jb, jb, mp, Vp, mp, Vp, mp, Gs);
   if (tid < 64) {
     for (int i = 0; i < jb; ++i) {
       const double ti = tau[i];
@@ -434,6 +429,16 @@ __device__ void wg_build_t(const double* Vp, int mp, int jb, const double* tau, 
     }
   }
   __syncthreads();
+}
+
+// Compact WY factor of jb <= QBMAX reflectors held explicitly in Vp (mp x jb,
+// column-major, unit diagonal, zeros above it): H_0 ... H_{jb-1} = I - V T V^T
+// with T upper triangular (row-major in Ts, ld QBMAX); G = V^T V by the
+// split-K matrix-core product (wg_atb) into Gs, then wg_t_from_gram.
+__device__ void wg_build_t_splitk(const double* Vp, int mp, int jb, const double* tau, double* Ts,
+                                  double* Gs) {
+  wg_atb<2, 2>(jb, jb, mp, Vp, mp, Vp, mp, Gs);
+  wg_t_from_gram(jb, tau, Ts, Gs);
 }
 
 // Blocked Householder QR (same output as wg_geqr2: R on and above the
@@ -489,7 +494,23 @@ __device__ void wg_geqrf_impl(double* X, int m, int n, double* tau, double* v, d
       }
       __syncthreads();
     }
-    wg_build_t(Vp, mp, jb, tau + j0, Ts, Gs, lds);
+    // G = V^T V (jb x jb, row-major in LDS), then T by the forward recurrence
+    //   T_ii = tau_i,  T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
+    wg_gemm<double>(jb, jb, mp, 1.0, Vp, mp, 1, Vp, 1, mp, 0.0, Gs, QBMAX, 1, lds);
+    if (tid < 64) {
+      for (int i = 0; i < jb; ++i) {
+        const double ti = tau[j0 + i];
+        if (tid < i) {
+          double acc = 0.0;
+          for (int c = tid; c < i; ++c) acc += Ts[tid * QBMAX + c] * Gs[c * QBMAX + i];
+          Ts[tid * QBMAX + i] = -ti * acc;
+        } else if (tid < QBMAX) {
+          Ts[tid * QBMAX + i] = tid == i ? ti : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
     double* C = X + (int64_t)(j0 + jb) * ld + j0;  // trailing block (mp x nc), ld ld
     double* Wt = ws + (int64_t)mp * qb;             // W^T = C^T V, nc x jb (ld qb)
     double* Wt2 = Wt + (int64_t)qb * n;             // W^T T, nc x jb (ld qb)
