@@ -250,13 +250,16 @@ def other_configs():
     tf = timed(h, lambda: h.run(False), 1)
     grads = [torch.empty_like(c) for c in cores]
     tb = timed(h, lambda: h.backward(None, grads), 1)
+    tbf = timed(h, lambda: h.backward(None, grads, frozen=True), 1)
     h.close()
     h = TNrSVD(cores, W.k, W.p, W.q, seed=W.omega_seed, precision="f32", max_rank=W.rmax,
                sketch_rank=64)
     ts = timed(h, lambda: h.run(False), 1)
     out["grad"] = {"workload": "d=30, 4x4 cores, ranks 16, k=16 p=8 q=1, FP32; gradient of the "
-                               "sum of the top 16 sigma at fixed singular vectors",
+                               "sum of the top 16 sigma through the whole pipeline (Omega and "
+                               "rounding ranks fixed; FP64 recompute + adjoint)",
                    "forward_s": round(tf, 4), "backward_s": round(tb, 4),
+                   "backward_frozen_subspace_s": round(tbf, 4),
                    "forward_sketch64_s": round(ts, 4)}
     h.close()
     return out

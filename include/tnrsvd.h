@@ -237,24 +237,46 @@ tnrsvd_status tnrsvd_run_graph(tnrsvd_t h, double* sigma);
 tnrsvd_status tnrsvd_refine(tnrsvd_t h, double round_tol, double* sigma);
 
 /*
- * tnrsvd_backward -- gradient of L = sum_{j<k} dsigma_j sigma_j with respect
- * to the ORIGINAL (unmerged) cores of every MPO, with the singular vectors of
- * the last solve held fixed: dL/dA = sum_j dsigma_j u_j v_j^T, written into
- * each core by left and right environments of U, A and V (formed here, not
- * kept from the solve) and, for the trailing cores that tnrsvd_create merged,
- * by the adjoint of the merge.  Differentiation is not part of the paper; this
- * is the derivative of sum_j dsigma_j u_j^T A v_j at fixed (u_j, v_j), which
- * equals the derivative of the solve's output when the computed subspace is
- * exact (rank(A) <= K and nothing truncated).
+ * tnrsvd_backward -- gradient of L = sum_{j<k} dsigma_j sigma_j of the last
+ * solve with respect to the ORIGINAL (unmerged) cores of every MPO: the
+ * derivative of the whole pipeline of Algorithm 5.4 as run (the product Y = A
+ * Omega, the rounding and orthogonalisation after every product with its
+ * ranks frozen at the values the solve chose, the q power steps, the
+ * projection B^T = A^T Q and the SVD of its last core, Sec. 5.4), with Omega
+ * held fixed, followed by the adjoint of the trailing-core merge of
+ * tnrsvd_create.  Differentiation is not part of the paper.  The products and
+ * roundings are computed again here in FP64 from the staged cores and Omega
+ * (nothing but the ranks is kept from the solve); each rounding is
+ * differentiated in its Gram form (right Grams of the product, eigenvectors
+ * of M G M^T for the kept left vectors), which computes the same map as the
+ * QR/SVD sweep of Sec. 3 while staying differentiable on products of lower
+ * rank than their bonds.  Valid where the kept eigenvalues of every rounding
+ * are distinct and separated from the discarded ones, and the last panel of
+ * every orthogonalisation has full column rank.
+ * The last solve must be tnrsvd_run or tnrsvd_run_graph (or the same steps
+ * one by one), not followed by tnrsvd_refine.
  * dsigma: HOST array of batch*k doubles, or NULL for all ones.
  * dcores: DEVICE pointers, one per original core (MPO 0's cores in order,
  *   then MPO 1's, ...); each receives the R x I x J x R' gradient, C order,
  *   in the dtype that MPO's cores had in tnrsvd_create.
- * The first call allocates the workspace; the call synchronises the stream.
- * Errors: E_INVALID (dcores NULL); E_STATE (no solve yet); E_NOMEM; E_SHAPE
- * (a rank beyond its planned capacity).
+ * Allocates its workspace per call; synchronises the stream.
+ * Errors: E_INVALID (dcores NULL); E_STATE (no solve yet, or the last solve
+ * was not a plain Algorithm 5.4 sequence); E_NOMEM; E_SHAPE (a last panel
+ * with fewer rows than K).
  */
 tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores);
+
+/*
+ * tnrsvd_backward_frozen -- the gradient of sum_{j<k} dsigma_j u_j^T A v_j with
+ * the singular vectors (u_j, v_j) of the last solve held FIXED, i.e.
+ * sum_j dsigma_j u_j v_j^T written into each original core by left and right
+ * environments of U, A and V and the merge adjoint.  It equals
+ * tnrsvd_backward where the computed subspace is exact (rank(A) <= K, nothing
+ * truncated) and is much cheaper; elsewhere it is only the fixed-vector part.
+ * Arguments, ownership and errors as tnrsvd_backward; the first call
+ * allocates the workspace.
+ */
+tnrsvd_status tnrsvd_backward_frozen(tnrsvd_t h, const double* dsigma, void* const* dcores);
 
 /*
  * tnrsvd_autotune -- choose the launch shape of the MPO x MPS contraction

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libtnrsvd.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["kernels_contract.hip", "kernels_sweep.hip", "kernels_wide.hip", "kernels_grad.hip",
-           "kernels_sparse.hip", "kernels_round.hip", "tnrsvd_abi.hip"]
+           "kernels_adjoint.hip", "kernels_sparse.hip", "kernels_round.hip", "tnrsvd_abi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -130,6 +130,12 @@ struct tnrsvd_s {
   // the order the one-workgroup-per-MPO sweeps dispatch them in
   int* order_d = nullptr;
   std::vector<int> order;
+  // ranks kept by each rounding of the current solve (slots of d + 1 per MPO),
+  // its product (0: A X, 1: A^T X) and whether it was the solve's SVD, for
+  // tnrsvd_backward
+  int* rhist_d = nullptr;
+  int hist_slots = 0, r_tot = 0;
+  std::vector<int> hist_op, hist_svd;
   bool wide_possible = false;
   double* WV = nullptr;
   int *wflag_d = nullptr, *wneed_d = nullptr, *wcap_d = nullptr, *wplan_d = nullptr;
@@ -550,6 +556,9 @@ static tnrsvd_status create_lib(tnrsvd_t* out, int batch, const tnrsvd_mpo* mpos
   ALLOC(h->V, sizeof(double) * x_tot);
   ALLOC(h->tail, sizeof(double) * tail_tot);
   ALLOC(h->order_d, sizeof(int) * batch);
+  h->hist_slots = 2 * o->q + 5;
+  h->r_tot = r_tot;
+  ALLOC(h->rhist_d, sizeof(int) * r_tot * h->hist_slots);
   if (h->wide_possible) {
     h->wcap.resize((size_t)kWidePlan * h->max_d, 0);
     // one plan slot per rounding of a solve (2q + 2), three more for tnrsvd_refine
@@ -852,6 +861,8 @@ tnrsvd_status load_omega(tnrsvd_t h) {
   h->projected = false;
   h->solved = false;
   h->round_idx = 0;
+  h->hist_op.clear();
+  h->hist_svd.clear();
   return TNRSVD_OK;
 }
 
@@ -967,7 +978,17 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   e = launch_lr_pass(h->mpos_d, h->cores_d, h->batch, op, h->rho, h->ldm, rout, h->W, h->tau,
                      h->scratch, out, odt, h->outs, so, h->tcap, h->mcap_s, h->ucap, h->err,
                      h->wide_possible ? h->wflag_d : nullptr, h->order_d, h->stream);
-  return dev_check(e, "left-to-right sweep");
+  TRY(dev_check(e, "left-to-right sweep"));
+  // the ranks this rounding kept, for tnrsvd_backward
+  const int slot = (int)h->hist_op.size();
+  if (slot < h->hist_slots) {
+    e = hipMemcpyAsync(h->rhist_d + (int64_t)slot * h->r_tot, rout, sizeof(int) * h->r_tot,
+                       hipMemcpyDeviceToDevice, h->stream);
+    TRY(dev_check(e, "record ranks"));
+  }
+  h->hist_op.push_back(op);
+  h->hist_svd.push_back(mode);
+  return TNRSVD_OK;
 }
 
 tnrsvd_status read_sigma(tnrsvd_t h, double* sigma) {
@@ -1288,19 +1309,95 @@ tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice) {
   return TNRSVD_OK;
 }
 
-static tnrsvd_status backward_lib(tnrsvd_t h, const double* dsigma, void* const* dcores) {
+// The derivative of the whole solve (tnrsvd_backward) into the merged-core
+// gradient slab gG, MPO by MPO: the staged cores widened to FP64, the ranks
+// of every rounding read back once, then pipeline_adjoint.
+static tnrsvd_status pipeline_grad_lib(tnrsvd_t h, const double* dsigma) {
+  const int T = 2 * h->opts.q + 2;
+  if (h->refined || (int)h->hist_op.size() != T)
+    return fail(TNRSVD_E_STATE,
+                "the last solve is not a plain Algorithm 5.4 sequence (tnrsvd_run); "
+                "refined solves are not differentiated");
+  for (int t = 0; t < T; ++t) {
+    const int want_op = (t == 0) ? 0 : (t == T - 1 ? 1 : (t % 2 == 1 ? 1 : 0));
+    if (h->hist_op[t] != want_op || h->hist_svd[t] != (t == T - 1 ? 1 : 0))
+      return fail(TNRSVD_E_STATE, "the last solve is not a plain Algorithm 5.4 sequence");
+  }
+  std::vector<int> hist((size_t)T * h->r_tot);
+  TRY(dev_check(hipMemcpyAsync(hist.data(), h->rhist_d, sizeof(int) * hist.size(),
+                               hipMemcpyDeviceToHost, h->stream), "read ranks"));
+  TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+  const int k = h->opts.k, K = h->opts.k + h->opts.p;
+  for (int b = 0; b < h->batch; ++b) {
+    const MpoDesc& md = h->mh[b];
+    const int d = md.d;
+    std::vector<CoreShape> sh(d);
+    std::vector<std::vector<int>> ranks(T, std::vector<int>(d + 1));
+    std::vector<int> ops(h->hist_op.begin(), h->hist_op.end());
+    int64_t a_len = 0;
+    for (int i = 0; i < d; ++i) {
+      const CoreDesc& cd = h->ch[md.c0 + i];
+      sh[i] = {cd.RA, cd.I, cd.J, cd.RA2};
+      a_len = std::max<int64_t>(a_len, (int64_t)cd.RA * cd.I * cd.J * cd.RA2);
+    }
+    for (int t = 0; t < T; ++t)
+      for (int i = 0; i <= d; ++i) ranks[t][i] = hist[(size_t)t * h->r_tot + md.r0 + i];
+    // panels the adjoint cannot take: a last core with fewer rows than K
+    for (int t = 0; t < T; ++t) {
+      const CoreDesc& cl = h->ch[md.c0 + d - 1];
+      const int n = ops[t] == 0 ? cl.I : cl.J;
+      if ((int64_t)ranks[t][d - 1] * n < K || ranks[t][d] != K)
+        return fail(TNRSVD_E_SHAPE, "MPO %d: last panel of rounding %d has fewer rows than K",
+                    b, t);
+    }
+    // FP64 copies of the staged (merged) cores
+    DevArena arena;
+    std::vector<const double*> A(d);
+    std::vector<double*> dA(d);
+    const size_t esz = elem_size(h->dtype);
+    for (int i = 0; i < d; ++i) {
+      const CoreDesc& cd = h->ch[md.c0 + i];
+      const int64_t len = (int64_t)cd.RA * cd.I * cd.J * cd.RA2;
+      double* a64 = arena.get<double>(len);
+      if (arena.e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TNRSVD_E_NOMEM, "gradient workspace");
+      }
+      TRY(dev_check(launch_convert_core((const char*)h->A + esz * cd.a_off, h->dtype, a64, kF64,
+                                        len, h->stream), "widen cores"));
+      A[i] = a64;
+      dA[i] = h->gG + cd.a_off;
+    }
+    const hipError_t e = pipeline_adjoint(d, sh.data(), A.data(), dA.data(), h->om + md.om_off,
+                                          K, k, dsigma ? dsigma + (size_t)b * k : nullptr, ranks,
+                                          ops, h->stream);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return fail(TNRSVD_E_NOMEM, "gradient workspace");
+    }
+    TRY(dev_check(e, "pipeline adjoint"));
+  }
+  return TNRSVD_OK;
+}
+
+static tnrsvd_status backward_lib(tnrsvd_t h, const double* dsigma, void* const* dcores,
+                                  bool pipeline) {
   TRY(check_handle(h));
   if (!dcores) return fail(TNRSVD_E_INVALID, "null gradient pointer array");
   if (!h->solved) return fail(TNRSVD_E_STATE, "no solve to differentiate");
   TRY(plan_grad(h));
   const int k = h->opts.k;
-  std::vector<double> w((size_t)h->batch * k, 1.0);
-  if (dsigma) std::copy(dsigma, dsigma + w.size(), w.begin());
-  TRY(dev_check(hipMemcpyAsync(h->gw, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice,
-                               h->stream), "copy weights"));
-  TRY(dev_check(launch_grad_env(h->mpos_d, h->cores_d, h->gm_d, h->eoff_d, h->batch, h->xr, h->vr,
-                                h->A, h->dtype, h->U, h->V, h->gw, k, h->gws, h->gG, h->err,
-                                h->stream), "environment gradient"));
+  if (pipeline) {
+    TRY(pipeline_grad_lib(h, dsigma));
+  } else {
+    std::vector<double> w((size_t)h->batch * k, 1.0);
+    if (dsigma) std::copy(dsigma, dsigma + w.size(), w.begin());
+    TRY(dev_check(hipMemcpyAsync(h->gw, w.data(), sizeof(double) * w.size(),
+                                 hipMemcpyHostToDevice, h->stream), "copy weights"));
+    TRY(dev_check(launch_grad_env(h->mpos_d, h->cores_d, h->gm_d, h->eoff_d, h->batch, h->xr,
+                                  h->vr, h->A, h->dtype, h->U, h->V, h->gw, k, h->gws, h->gG,
+                                  h->err, h->stream), "environment gradient"));
+  }
   int base = 0;
   for (int b = 0; b < h->batch; ++b) {
     const MpoDesc& md = h->mh[b];
@@ -1370,9 +1467,10 @@ static tnrsvd_status backward_lib(tnrsvd_t h, const double* dsigma, void* const*
 
 // TNRSVD_K_FIRST: gradients are formed in the library's layout in staging
 // buffers, then written reversed (core order and rank legs) to the caller's.
-tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores) {
+static tnrsvd_status backward_any(tnrsvd_t h, const double* dsigma, void* const* dcores,
+                                  bool pipeline) {
   TRY(check_handle(h));
-  if (h->orientation != TNRSVD_K_FIRST) return backward_lib(h, dsigma, dcores);
+  if (h->orientation != TNRSVD_K_FIRST) return backward_lib(h, dsigma, dcores, pipeline);
   if (!dcores) return fail(TNRSVD_E_INVALID, "null gradient pointer array");
   std::vector<void*> tmp;
   auto release = [&]() {
@@ -1392,7 +1490,7 @@ tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dco
       tmp.push_back(t);
     }
   }
-  tnrsvd_status st = backward_lib(h, dsigma, tmp.data());
+  tnrsvd_status st = backward_lib(h, dsigma, tmp.data(), pipeline);
   int base = 0;
   for (int b = 0; b < h->batch && st == TNRSVD_OK; ++b) {
     const auto& ps = h->paper_shape[b];
@@ -1408,6 +1506,14 @@ tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dco
   if (st == TNRSVD_OK) st = dev_check(hipStreamSynchronize(h->stream), "synchronise");
   release();
   return st;
+}
+
+tnrsvd_status tnrsvd_backward(tnrsvd_t h, const double* dsigma, void* const* dcores) {
+  return backward_any(h, dsigma, dcores, true);
+}
+
+tnrsvd_status tnrsvd_backward_frozen(tnrsvd_t h, const double* dsigma, void* const* dcores) {
+  return backward_any(h, dsigma, dcores, false);
 }
 
 tnrsvd_status tnrsvd_get_ranks(tnrsvd_t h, int b, int64_t* host_out, int* d_merged) {

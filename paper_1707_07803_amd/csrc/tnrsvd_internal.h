@@ -302,6 +302,15 @@ hipError_t sparse_round(int d, const int64_t* I, const int64_t* J, int64_t nnz, 
 hipError_t round_mpo(int d, const int64_t* rank, const int64_t* I, const int64_t* J,
                      const double* const* cores, double eps, int rmax, RoundedMpo* out,
                      hipStream_t s);
+// Reverse-mode derivative of the whole solve for one MPO (kernels_adjoint.hip).
+struct CoreShape {
+  int Ra, I, J, Rb;
+};
+hipError_t pipeline_adjoint(int d, const CoreShape* shapes, const double* const* A,
+                            double* const* dA, const double* omega, int K, int k,
+                            const double* dsigma_host,
+                            const std::vector<std::vector<int>>& ranks,
+                            const std::vector<int>& ops, hipStream_t s);
 hipError_t launch_merge_pair_bwd(const double* T, const double* C, const double* dN, double* dT,
                                  double* dC, int a, int I1, int J1, int r, int I2, int J2, int b,
                                  hipStream_t s);

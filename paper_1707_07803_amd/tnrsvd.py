@@ -23,7 +23,8 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16}
 # the C function names exported by the library, in header order
 EXPORTS = [
     "tnrsvd_create", "tnrsvd_mult", "tnrsvd_orthogonalize", "tnrsvd_project",
-    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_refine", "tnrsvd_backward", "tnrsvd_autotune",
+    "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_refine", "tnrsvd_backward",
+    "tnrsvd_backward_frozen", "tnrsvd_autotune",
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_run_graph.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_refine.argtypes = [H, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_backward.argtypes = [H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p)]
+    L.tnrsvd_backward_frozen.argtypes = L.tnrsvd_backward.argtypes
     L.tnrsvd_autotune.argtypes = [H, I, ctypes.POINTER(I)]
     L.tnrsvd_get_factor.argtypes = [H, I, I, I, ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I)]
@@ -219,9 +221,12 @@ class TNrSVD:
                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out.reshape(self.batch, self.k)
 
-    def backward(self, dsigma, grads) -> None:
-        """tnrsvd_backward: write d(sum_j dsigma_j sigma_j)/d(core) into the device
-        tensors ``grads`` (one per original core of every MPO, in order)."""
+    def backward(self, dsigma, grads, frozen: bool = False) -> None:
+        """tnrsvd_backward: write d(sum_j dsigma_j sigma_j)/d(core) of the last solve
+        (the whole pipeline, Omega and the rounding ranks fixed) into the device
+        tensors ``grads`` (one per original core of every MPO, in order).
+        frozen=True: tnrsvd_backward_frozen, the derivative at fixed singular
+        vectors instead."""
         w = None
         if dsigma is not None:
             w = np.ascontiguousarray(np.asarray(dsigma, dtype=np.float64).reshape(-1))
@@ -231,7 +236,8 @@ class TNrSVD:
             if not g.is_cuda or not g.is_contiguous():
                 raise TNrSVDError(-1, "gradients must be contiguous device tensors")
         ptrs = (ctypes.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
-        _check(self._lib.tnrsvd_backward(
+        fn = self._lib.tnrsvd_backward_frozen if frozen else self._lib.tnrsvd_backward
+        _check(fn(
             self._h, None if w is None else w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs))
 
     def autotune(self, reps: int = 5) -> dict:
@@ -579,30 +585,41 @@ def _mpo_struct(cores):
 def _autograd_function():
     import torch
 
+    from torch.autograd.function import once_differentiable
+
     class TNrSVDFunction(torch.autograd.Function):
         """sigma_top_k = TNrSVDFunction.apply(options, *cores) for one MPO.
 
         Forward: one solve in the library (contractions, FP64 sweeps, final SVD).
         Backward: tnrsvd_backward with the incoming gradient of sigma -- the
-        derivative at fixed computed singular vectors (see include/tnrsvd.h).
+        derivative of the whole solve with Omega and the rounding ranks held
+        fixed (see include/tnrsvd.h).  Differentiable once: the handle is
+        released by the backward, or when the graph is dropped without one.
         ``options`` is a dict of TNrSVD keyword arguments (k, p, q, seed,
         precision, round_tol, max_rank).
         """
 
         @staticmethod
         def forward(ctx, options, *cores):
+            import weakref
             h = TNrSVD([c.detach().contiguous() for c in cores], **options)
             sig = h.run()[0]
             ctx.h = h
             ctx.like = [(c.shape, c.dtype) for c in cores]
+            weakref.finalize(ctx, h.close)
             return torch.as_tensor(sig, dtype=torch.float64, device=cores[0].device)
 
         @staticmethod
+        @once_differentiable
         def backward(ctx, gsig):
             h = ctx.h
+            if h is None or getattr(h, "_h", None) is None:
+                raise RuntimeError("TNrSVDFunction can be differentiated once per forward "
+                                   "(its solve handle has been released)")
             grads = [torch.empty(sh, dtype=dt, device="cuda") for sh, dt in ctx.like]
             h.backward(gsig.detach().to("cpu", torch.float64).numpy(), grads)
             h.close()
+            ctx.h = None
             return (None, *grads)
 
     return TNrSVDFunction

@@ -170,8 +170,12 @@ def test_gradient_reversed_and_directional():
     gl = [torch.zeros_like(t) for t in to_device(L)]
     gf = [torch.zeros_like(t) for t in to_device(P)]
     w = np.linspace(1.0, 2.0, k)
-    hl.backward(w, gl)
+    hl.backward(w, gl)                 # the pipeline's derivative
     hf.backward(w, gf)
+    for a, b in zip([g.cpu().numpy() for g in gf], o.reverse_mpo([g.cpu().numpy() for g in gl])):
+        np.testing.assert_array_equal(a, b)
+    hl.backward(w, gl, frozen=True)    # the derivative at fixed singular vectors
+    hf.backward(w, gf, frozen=True)
     gl = [g.cpu().numpy() for g in gl]
     gf = [g.cpu().numpy() for g in gf]
     for a, b in zip(gf, o.reverse_mpo(gl)):
