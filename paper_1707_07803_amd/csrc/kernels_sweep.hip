@@ -694,6 +694,87 @@ __device__ void wg_apply_q_reg(const double* __restrict__ V, const double* __res
   __syncthreads();
 }
 
+// The same product with CPW columns of Y per wave (columns cb + w + NW q of
+// each batch of CPW NW columns), so every staged reflector is read once for
+// all of them: V has leading dimension ldv (its column j holds reflector j
+// below row j), Y leading dimension ldy.
+template <int MT, int CPW>
+__device__ void wg_apply_q_cols(const double* __restrict__ V, int64_t ldv,
+                                const double* __restrict__ tau, int m, int k, double* Y, int ldy,
+                                int s, double* stage, int cap, double* tstage) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = wave_id();
+  int CH = cap / m;
+  if (CH > 64) CH = 64;
+  if (CH < 1) CH = 1;
+  __syncthreads();   // Y may have just been written by other threads
+  for (int cb = 0; cb < s; cb += CPW * NW) {
+    double y[CPW][MT];
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      const int c = cb + w + NW * q;
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const int r = lane + 64 * t;
+        const bool ok = c < s && r < m;
+        const double raw = Y[ok ? (int64_t)c * ldy + r : 0];
+        y[q][t] = ok ? raw : 0.0;
+      }
+    }
+    for (int hi = k; hi > 0; hi -= CH) {
+      const int lo = hi - CH > 0 ? hi - CH : 0;
+      const int cnt = hi - lo;
+      __syncthreads();
+      for (int64_t e = tid; e < (int64_t)cnt * m; e += NT) {
+        const int j = (int)(e / m), r = (int)(e - (int64_t)j * m);
+        stage[e] = V[(int64_t)(lo + j) * ldv + r];
+      }
+      for (int e = tid; e < cnt; e += NT) tstage[e] = tau[lo + e];
+      __syncthreads();
+      for (int j = hi - 1; j >= lo; --j) {
+        const double tj = tstage[j - lo];
+        if (tj == 0.0) continue;
+        const double* vj = stage + (int64_t)(j - lo) * m;
+        double v[MT];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          const int r = lane + 64 * t;
+          const double raw = vj[r < m ? r : m - 1];   // in-bounds read, masked below
+          v[t] = (r > j && r < m) ? raw : (r == j ? 1.0 : 0.0);
+        }
+        double part[CPW];
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) {
+          double a = 0.0;
+#pragma unroll
+          for (int t = 0; t < MT; ++t) a += v[t] * y[q][t];
+          part[q] = a;
+        }
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) part[q] = wave_sum(part[q]);
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) {
+          const double f = tj * part[q];
+#pragma unroll
+          for (int t = 0; t < MT; ++t) y[q][t] -= f * v[t];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      const int c = cb + w + NW * q;
+      if (c < s) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          const int r = lane + 64 * t;
+          if (r < m) Y[(int64_t)c * ldy + r] = y[q][t];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // M^T = Q_thin [T^T; 0] for a panel factorised by the right-to-left pass's
 // TSQR (n columns, m rows, nc leaves): the nodes of the merge tree are applied
 // top down, each splitting its output between its two ranges; then every leaf
@@ -915,14 +996,14 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
     if (i < d - 1) {
       double* U = (nvg * nvg <= LR_UB) ? Ub : SL.U;
       // A panel in global memory with fewer rows than columns is first reduced
-      // by a QR of its transpose, M^T = Q R (blocked Householder, in place):
+      // by a QR of its transpose, M^T = Q R (blocked Householder, in place,
+      // its panels staged in the free M and V carve):
       // the rows of M and of R^T have the same inner products, so the one-sided
       // Jacobi runs on the nv x nv R^T in LDS with the same rotations, and the
       // carried factor U^T M = (U^T R^T) Q^T is recovered by applying Q.
       // R^T stays in LDS when it fits with U, else it goes to the scratch after
       // the QR's scalars (the Jacobi then works from L2)
-      const bool pre_lds = nv * nv <= LR_MB && nvg * nvg <= LR_UB &&
-                           (int64_t)rn * (QB + 1) <= LR_VB;
+      const bool pre_lds = nv * nv <= LR_MB && nvg * nvg <= LR_UB;
       // larger R^T (up to 128 x 128) over the whole M, V and U carve, with U in
       // the scratch; past that R^T goes to the scratch too
       const bool pre_wide = !pre_lds && nv * nv <= LR_MB + LR_VB + LR_UB && nvg * nvg > LR_UB &&
@@ -936,7 +1017,8 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       int blen = rn, bld = ld;
       double* tauP = SL.Q + (int64_t)rn * QB + 2 * QB * nv;
       if (pre) {
-        wg_geqrf(M, rn, nv, tauP, Vb, red, SL.Q, Vb, LR_VB, Ub, Ub + QBMAX * QBMAX, ld, QB);
+        wg_geqrf(M, rn, nv, tauP, Mb, red, SL.Q, Mb, LR_MB + LR_VB, Ub, Ub + QBMAX * QBMAX, ld,
+                 QB);
         double* Bt = (pre_lds || pre_wide) ? Mb : tauP + nv;
         for (int e = tid; e < nv * nv; e += NT) {
           const int p = e / nv, c = e - p * nv;
@@ -947,7 +1029,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         blen = nv;
         bld = nv;
       }
-      wg_jacobi(B, nv, blen, bld, U, ibuf, red, delta * delta / (double)nv);
+      wg_jacobi_lr(B, nv, blen, bld, U, ibuf, red, delta * delta / (double)nv, B == Mb, U == Ub);
       wg_norms_sorted(B, nv, blen, bld, sig, perm, nrmb);
       if (tid == 0) {
         const int kk = nv < rn ? nv : rn;
@@ -985,8 +1067,17 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
           const int k = (int)(o / rn), f = (int)(o % rn);
           SL.T[o] = f < nv ? B[(int64_t)perm[k] * nv + f] * sgn[k] : 0.0;
         }
-        __syncthreads();
-        wg_apply_q(M, tauP, rn, nv, SL.T, rnew, ld);
+        // the whole LDS carve is free again (R^T and U were last read above)
+        if (rn <= 512)
+          wg_apply_q_cols<8, 4>(M, ld, tauP, rn, nv, SL.T, rn, rnew, Mb, LR_MB + LR_VB + LR_UB,
+                                tst);
+        else if (rn <= 1024)
+          wg_apply_q_cols<16, 2>(M, ld, tauP, rn, nv, SL.T, rn, rnew, Mb, LR_MB + LR_VB + LR_UB,
+                                 tst);
+        else {
+          __syncthreads();
+          wg_apply_q(M, tauP, rn, nv, SL.T, rnew, ld);
+        }
       } else {
         for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
           const int k = (int)(o / rn), f = (int)(o % rn);

@@ -310,23 +310,42 @@ __device__ void wg_atb(int M, int N, int K, const double* __restrict__ A, int64_
 #pragma unroll
     for (int j = 0; j < NBK; ++j) c[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 16 * w; k0 < K; k0 += 16 * NW) {
-    double a[4][MB], b[4][NBK];
+    // each lane reads its four consecutive k (two 16-byte loads when all four
+    // are in range), so a load instruction covers whole 128-byte lines
+    const int kb = k0 + 4 * q4;
+    double a[MB][4], b[NBK][4];
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int k = k0 + 4 * q4 + st;
+    for (int i = 0; i < MB; ++i) {
+      const int row = 16 * i + r16;
+      const double* p = A + (int64_t)(row < M ? row : 0) * lda + kb;
+      if (row < M && kb + 3 < K) {
+        double2 u0, u1;
+        __builtin_memcpy(&u0, p, 16);
+        __builtin_memcpy(&u1, p + 2, 16);
+        a[i][0] = u0.x;
+        a[i][1] = u0.y;
+        a[i][2] = u1.x;
+        a[i][3] = u1.y;
+      } else {
 #pragma unroll
-      for (int i = 0; i < MB; ++i) {
-        const int row = 16 * i + r16;
-        const bool ok = k < K && row < M;
-        const double v = A[ok ? (int64_t)row * lda + k : 0];
-        a[st][i] = ok ? v : 0.0;
+        for (int st = 0; st < 4; ++st) a[i][st] = (row < M && kb + st < K) ? p[st] : 0.0;
       }
+    }
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) {
-        const int col = 16 * j + r16;
-        const bool ok = k < K && col < N;
-        const double v = B[ok ? (int64_t)col * ldb + k : 0];
-        b[st][j] = ok ? v : 0.0;
+    for (int j = 0; j < NBK; ++j) {
+      const int col = 16 * j + r16;
+      const double* p = B + (int64_t)(col < N ? col : 0) * ldb + kb;
+      if (col < N && kb + 3 < K) {
+        double2 u0, u1;
+        __builtin_memcpy(&u0, p, 16);
+        __builtin_memcpy(&u1, p + 2, 16);
+        b[j][0] = u0.x;
+        b[j][1] = u0.y;
+        b[j][2] = u1.x;
+        b[j][3] = u1.y;
+      } else {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) b[j][st] = (col < N && kb + st < K) ? p[st] : 0.0;
       }
     }
 #pragma unroll
@@ -335,7 +354,7 @@ __device__ void wg_atb(int M, int N, int K, const double* __restrict__ A, int64_
       for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < NBK; ++j)
-          c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], c[i][j], 0, 0, 0);
+          c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][st], b[j][st], c[i][j], 0, 0, 0);
   }
   __syncthreads();   // acc may still be read by the caller's previous step
   for (int q = 0; q < NW; ++q) {
@@ -366,7 +385,10 @@ __device__ void wg_ab_rows(int mp, int N, int KK, double alpha, const double* __
                            int64_t ldc) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  double b[8][NBK];
+  // the 16 x 16 blocks are formed transposed, C^T = B^T A^T, so that a lane's
+  // four results are four columns of one row and every read-modify-write
+  // instruction covers 16 consecutive rows of four columns
+  double b[8][NBK];   // B^T[col][k] = B[k][col], col = 16 j + r16, k = 4 st + q4
 #pragma unroll
   for (int st = 0; st < 8; ++st) {
     const int k = 4 * st + q4;
@@ -386,16 +408,17 @@ __device__ void wg_ab_rows(int mp, int N, int KK, double alpha, const double* __
       const int k = 4 * st + q4;
       const bool ok = k < KK && row < mp;
       const double v = A[ok ? (int64_t)k * lda + row : 0];
-      const double a = ok ? v : 0.0;
+      const double a = ok ? v : 0.0;   // A^T[k][row]
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[st][j], c[j], 0, 0, 0);
+      for (int j = 0; j < NBK; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[st][j], a, c[j], 0, 0, 0);
     }
+    // c[j][jj] = (A B)[row][16 j + 4 jj + q4]
 #pragma unroll
     for (int j = 0; j < NBK; ++j)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const int rr = r0 + 4 * jj + q4, col = 16 * j + r16;
-        if (rr < mp && col < N) C[(int64_t)col * ldc + rr] += alpha * c[j][jj];
+        const int col = 16 * j + 4 * jj + q4;
+        if (row < mp && col < N) C[(int64_t)col * ldc + row] += alpha * c[j][jj];
       }
   }
 }
@@ -706,6 +729,160 @@ __device__ int wg_jacobi(double* B, int nv, int len, int ldb, double* U, int* fl
     if (!any) break;
   }
   return sweep;
+}
+
+// The same one-sided Jacobi for the left-to-right pass, with each pair's
+// vectors held in registers between the inner products and the rotation, and
+// B and U addressed as LDS when they live there (ds reads the compiler can
+// batch, instead of flat accesses that wait on both memory counters).  A
+// pair takes one 16-lane DPP row (LN = 16, 32 pairs at once) or one wave
+// (LN = 64); lane li holds elements li + LN i (i < E) of the two vectors and
+// li + LN i (i < EU) of their rotation rows.  Same pairs, rotations and
+// stopping rule as wg_jacobi, with the orthogonality test taken on squares.
+typedef __attribute__((address_space(3))) double lds_double;
+template <bool L>
+struct jac_ptr {
+  using type = double*;
+};
+template <>
+struct jac_ptr<true> {
+  using type = lds_double*;
+};
+
+template <int LN, int E, int EU, bool BL, bool UL>
+__device__ int jacobi_regs(double* Bg, int nv, int len, int ldb, double* Ug, int* flag,
+                           double tiny, double skip2, double tol) {
+  using PB = typename jac_ptr<BL>::type;
+  using PU = typename jac_ptr<UL>::type;
+  PB B = (PB)Bg;
+  PU U = (PU)Ug;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = tid / LN, li = tid & (LN - 1);
+  constexpr int NG = NT / LN;
+  const int src = (lane & ~15) | 15;
+  const double tol2 = tol * tol;
+  const int nn = nv + (nv & 1);
+  int sweep = 0;
+  for (; sweep < 40; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < nn - 1; ++rnd) {
+      for (int t = g; t < nn / 2; t += NG) {
+        int p, q;
+        if (t == 0) {
+          p = nn - 1;
+          q = rnd;
+        } else {
+          p = (rnd + t) % (nn - 1);
+          q = (rnd - t + nn - 1) % (nn - 1);
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q >= nv) continue;
+        PB bp = B + (int64_t)p * ldb;
+        PB bq = B + (int64_t)q * ldb;
+        double x[E], y[E];
+        double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int e = li + LN * i;
+          const bool ok = e < len;
+          const double xv = bp[ok ? e : 0], yv = bq[ok ? e : 0];
+          x[i] = ok ? xv : 0.0;
+          y[i] = ok ? yv : 0.0;
+          a += x[i] * x[i];
+          b += y[i] * y[i];
+          c += x[i] * y[i];
+        }
+        if constexpr (LN == 16) {
+          a = row16_sum(a, src);
+          b = row16_sum(b, src);
+          c = row16_sum(c, src);
+        } else {
+          a = wave_sum(a);
+          b = wave_sum(b);
+          c = wave_sum(c);
+        }
+        if (a <= tiny || b <= tiny || a + b <= skip2 || c * c <= tol2 * a * b) continue;
+        const double zeta = (b - a) / (2.0 * c);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int e = li + LN * i;
+          if (e < len) {
+            bp[e] = cs * x[i] - sn * y[i];
+            bq[e] = sn * x[i] + cs * y[i];
+          }
+        }
+        PU up = U + (int64_t)p * nv;
+        PU uq = U + (int64_t)q * nv;
+        double ux[EU], uy[EU];
+#pragma unroll
+        for (int i = 0; i < EU; ++i) {
+          const int e = li + LN * i;
+          const bool ok = e < nv;
+          const double xv = up[ok ? e : 0], yv = uq[ok ? e : 0];
+          ux[i] = xv;
+          uy[i] = yv;
+        }
+#pragma unroll
+        for (int i = 0; i < EU; ++i) {
+          const int e = li + LN * i;
+          if (e < nv) {
+            up[e] = cs * ux[i] - sn * uy[i];
+            uq[e] = sn * ux[i] + cs * uy[i];
+          }
+        }
+        if (li == 0) *flag = 1;
+      }
+      __syncthreads();
+    }
+    const int any = *flag;
+    __syncthreads();
+    if (!any) break;
+  }
+  return sweep;
+}
+
+template <bool BL, bool UL>
+__device__ int jacobi_pick(double* B, int nv, int len, int ldb, double* U, int* flag, double tiny,
+                           double skip2, double tol) {
+  const int nn = nv + (nv & 1);
+  const int mx = len > nv ? len : nv;
+  if (nn / 2 > NW) {
+    if (mx <= 64) return jacobi_regs<16, 4, 4, BL, UL>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+    if (mx <= 128) return jacobi_regs<16, 8, 8, BL, UL>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+    return jacobi_regs<16, 16, 16, BL, UL>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+  }
+  if (mx <= 64) return jacobi_regs<64, 1, 1, BL, UL>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+  if (mx <= 128) return jacobi_regs<64, 2, 2, BL, UL>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+  return jacobi_regs<64, 4, 4, BL, UL>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+}
+
+// wg_jacobi for vectors of at most 256 entries (b_lds / u_lds: B / U lie in
+// LDS); longer ones take wg_jacobi itself.
+__device__ int wg_jacobi_lr(double* B, int nv, int len, int ldb, double* U, int* flag,
+                            double* red, double skip2, bool b_lds, bool u_lds) {
+  if (len > 256 || nv > 256) return wg_jacobi(B, nv, len, ldb, U, flag, red, skip2);
+  const int tid = threadIdx.x;
+  for (int t = tid; t < nv * nv; t += NT) U[t] = ((t % nv) == (t / nv)) ? 1.0 : 0.0;
+  __syncthreads();
+  if (nv < 2) return 0;
+  double part = 0.0;
+  for (int e = tid; e < nv * len; e += NT) {
+    const double x = B[(int64_t)(e / len) * ldb + e % len];
+    part += x * x;
+  }
+  const double tiny = 256.0 * 4.930380657631324e-32 * block_sum(part, red);
+  const double tol = 2.220446049250313e-16 * (double)(len > 16 ? len : 16);
+  if (b_lds && u_lds) return jacobi_pick<true, true>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+  if (b_lds) return jacobi_pick<true, false>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+  if (u_lds) return jacobi_pick<false, true>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+  return jacobi_pick<false, false>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
 }
 
 // Norms of the nv vectors, then a stable descending sort: sig[pos], perm[pos].
