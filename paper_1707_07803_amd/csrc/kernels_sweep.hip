@@ -1020,14 +1020,19 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         wg_geqrf(M, rn, nv, tauP, Mb, red, SL.Q, Mb, LR_MB + LR_VB, Ub, Ub + QBMAX * QBMAX, ld,
                  QB);
         double* Bt = (pre_lds || pre_wide) ? Mb : tauP + nv;
+        // in LDS, rows 16 doubles (mod 32) apart put the four rows a wave
+        // reads at once (one per 16-lane group) on two bank halves, not one
+        const int cap = pre_lds ? LR_MB : LR_MB + LR_VB + LR_UB;
+        const int pld = nv + ((16 - nv % 32) + 32) % 32;
+        const int bst = ((pre_lds || pre_wide) && nv * pld <= cap) ? pld : nv;
         for (int e = tid; e < nv * nv; e += NT) {
           const int p = e / nv, c = e - p * nv;
-          Bt[e] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T
+          Bt[p * bst + c] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T
         }
         __syncthreads();
         B = Bt;
         blen = nv;
-        bld = nv;
+        bld = bst;
       }
       wg_jacobi_lr(B, nv, blen, bld, U, ibuf, red, delta * delta / (double)nv, B == Mb, U == Ub);
       wg_norms_sorted(B, nv, blen, bld, sig, perm, nrmb);
@@ -1065,7 +1070,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         // T^T (rn x rnew, column-major = T row-major) = Q [B_sel^T; 0]
         for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
           const int k = (int)(o / rn), f = (int)(o % rn);
-          SL.T[o] = f < nv ? B[(int64_t)perm[k] * nv + f] * sgn[k] : 0.0;
+          SL.T[o] = f < nv ? B[(int64_t)perm[k] * bld + f] * sgn[k] : 0.0;
         }
         // the whole LDS carve is free again (R^T and U were last read above)
         if (rn <= 512)

@@ -47,29 +47,106 @@ __device__ __forceinline__ void cfor(F&& f) {
   }
 }
 
-// Sums of NV per-thread values over the workgroup, returned to every thread:
-// DPP sums within each wave, one row of NV per wave in red; for NV = 1 every
-// thread then adds the NW rows (one barrier), otherwise NV threads add them
-// and every thread reads the NV totals (two barriers, far fewer LDS reads).
-// red holds NW NV + NV doubles; callers alternate two such buffers.  The
-// barriers order LDS only, so global loads issued before them (the next
-// reflector) stay in flight.
+// Partner of this lane at butterfly step STEP (its value of x): lane ^ STEP
+// for 32 and 16 (LDS crossbar), the mirror within 16 or 8 lanes for 8 and 4,
+// lane ^ 2 and lane ^ 1 for 2 and 1 (DPP).  Each pairs lanes that differ in
+// bit log2(STEP) and agree in every higher bit.
+template <int STEP>
+__device__ __forceinline__ double bfly_partner(double x, int lane) {
+  if constexpr (STEP == 32 || STEP == 16) {
+    const int a = (lane ^ STEP) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(x));
+    const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(x));
+    return __hiloint2double(hi, lo);
+  } else if constexpr (STEP == 8) {
+    return dpp_d<0x140>(x);   // row_mirror
+  } else if constexpr (STEP == 4) {
+    return dpp_d<0x141>(x);   // row_half_mirror
+  } else if constexpr (STEP == 2) {
+    return dpp_d<0x4E>(x);    // quad_perm [2,3,0,1]
+  } else {
+    return dpp_d<0xB1>(x);    // quad_perm [1,0,3,2]
+  }
+}
+
+// One halving step of the transposed wave sum: the lane keeps the half of its
+// N values selected by bit log2(STEP) of its id and adds its partner's copy of
+// that half (the partner keeps the other half).
+template <int N, int STEP>
+__device__ __forceinline__ void bfly_halve(double* v, int lane) {
+  const bool up = (lane & STEP) != 0;
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const double send = up ? v[i] : v[i + N / 2];
+    const double keep = up ? v[i + N / 2] : v[i];
+    v[i] = keep + bfly_partner<STEP>(send, lane);
+  }
+}
+
+// Sums over the 64 lanes of a wave of each of NV (8, 16 or 32) per-lane
+// values, transposed: halving steps with partners inside a 16-lane row (DPP:
+// mirrors at 8 and 4, swaps at 2 and 1) leave one value per lane, then lanes
+// holding the same column are folded (the steps left of 1, then 16 and 32
+// through the LDS crossbar).  Lane l ends with the total of column
+// wave_tsum_col<NV>(l); wave_tsum_writer<NV>(l) picks one lane per column.
+template <int NV>
+__device__ __forceinline__ int wave_tsum_col(int lane) {
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  if constexpr (NV == 32)
+    return 16 * b3 + 8 * b2 + 4 * b1 + 2 * b0 + ((lane >> 4) & 1);
+  else if constexpr (NV == 16)
+    return 8 * b3 + 4 * b2 + 2 * b1 + b0;
+  else
+    return 4 * b3 + 2 * b2 + b1;
+}
+
+template <int NV>
+__device__ __forceinline__ bool wave_tsum_writer(int lane) {
+  if constexpr (NV == 32) return lane < 32;
+  else if constexpr (NV == 16) return lane < 16;
+  else return (lane & 0x31) == 0;
+}
+
+template <int NV>
+__device__ __forceinline__ double wave_tsum(double (&v)[NV], int lane) {
+  static_assert(NV == 8 || NV == 16 || NV == 32, "transposed wave sum of 8, 16 or 32 values");
+  double t[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) t[i] = v[i];
+  bfly_halve<NV, 8>(t, lane);
+  bfly_halve<NV / 2, 4>(t, lane);
+  bfly_halve<NV / 4, 2>(t, lane);
+  if constexpr (NV >= 16) bfly_halve<NV / 8, 1>(t, lane);
+  else t[0] += bfly_partner<1>(t[0], lane);
+  if constexpr (NV >= 32) bfly_halve<NV / 16, 16>(t, lane);
+  else t[0] += bfly_partner<16>(t[0], lane);
+  t[0] += bfly_partner<32>(t[0], lane);
+  return t[0];
+}
+
+// Sums of NV per-thread values over the workgroup, returned to every thread.
+// NV = 1: DPP sum within each wave, one value per wave in red, every thread
+// adds the NW of them (one barrier).  NV > 1: the transposed wave sum leaves
+// each column's wave total in a few lanes, one of which writes it to red;
+// NV threads add the NW rows and every thread reads the NV totals (two
+// barriers).  red holds NW NV + NV doubles; callers alternate two such
+// buffers.  The barriers order LDS only, so global loads issued before them
+// (the next reflector) stay in flight.
 template <int NV>
 __device__ __forceinline__ void wg_sums(double (&v)[NV], double* red) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[w * NV + k] = v[k];
-  }
-  lds_barrier();
   if constexpr (NV == 1) {
+    v[0] = wave_sum(v[0]);
+    if (lane == 0) red[w] = v[0];
+    lds_barrier();
     double t = red[0];
 #pragma unroll
     for (int q = 1; q < NW; ++q) t += red[q];
     v[0] = t;
   } else {
+    const double s = wave_tsum<NV>(v, lane);
+    if (wave_tsum_writer<NV>(lane)) red[w * NV + wave_tsum_col<NV>(lane)] = s;
+    lds_barrier();
     if (tid < NV) {
       double t = red[tid];
 #pragma unroll
