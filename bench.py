@@ -155,7 +155,12 @@ def time_path(W, precision, eps, steps, warmup, batch=1, graph=False, refine_tol
     h = TNrSVD(mpos, W.k, W.p, W.q, seed=W.omega_seed, precision=precision, round_tol=eps,
                max_rank=W.rmax, sketch_rank=sketch)
     del cores
-    tuned = h.autotune(3) if autotune else None
+    tuned = None
+    if autotune:
+        tuned = h.autotune(3)
+        # the sweep launch choice, timed afresh (no cache, so runs are comparable)
+        tuned["sweeps"] = {k: v for k, v in h.autotune_sweeps(reps=1, cache=None).items()
+                           if k in ("wmin", "lpt")}
     if refine_tol is None:
         step = h.run_graph if graph else h.run
     else:
@@ -237,7 +242,15 @@ def other_configs():
     dt = timed(h, lambda: h.run(False), 1)
     res["f32+sketch48"] = (dt, h.run()[0])
     h.close()
+    # the same FP32 solve after the sweep autotuner's choice (timed, not cached)
+    h = TNrSVD(dev(W.cores, "f32"), W.k, W.p, W.q, seed=W.omega_seed, precision="f32",
+               round_tol=W.eps, max_rank=W.rmax)
+    tune = h.autotune_sweeps(reps=1, cache=None)
+    dt = timed(h, lambda: h.run(False), 1)
+    res["f32_sweeps_autotuned"] = (dt, h.run()[0])
+    h.close()
     out["large"] = {"workload": "d=50, 2x2 cores, ranks 10, k=10 p=10 q=2, r_max=32 (2^50 x 2^50)",
+                    "sweep_autotune": {k: tune[k] for k in ("wmin", "lpt")},
                     "solves_per_s": {p: round(1.0 / res[p][0], 4) for p in res},
                     "sigma_rel_diff_f32_vs_f64": float(np.linalg.norm(res["f32"][1] - res["f64"][1])
                                                        / np.linalg.norm(res["f64"][1])),

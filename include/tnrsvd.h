@@ -295,6 +295,40 @@ tnrsvd_status tnrsvd_backward_frozen(tnrsvd_t h, const double* dsigma, void* con
 tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice);
 
 /*
+ * tnrsvd_autotune_sweeps -- choose how the rounding sweeps (Sec. 3 rounding,
+ * Algorithms 5.2 and 5.3 as used in Sec. 5.4) are launched on this handle by
+ * timing whole solves (tnrsvd_run: one warm-up, then `reps` timed) under each
+ * candidate and keeping the fastest (batching support; not part of the
+ * paper).  A choice is a pair {wmin, lpt}:
+ *   wmin  the fewest product columns (P) that send an MPO's right-to-left
+ *         pass to the multi-workgroup launches: 129 (every panel wider than
+ *         the one-workgroup register path), 257, 513, or 0 (never: the
+ *         one-workgroup blocked path takes every panel); 513 and 0 are tried
+ *         only when no product can exceed 512 columns (the one-workgroup
+ *         path is far slower beyond), and only 0 when no product can exceed
+ *         the register path;
+ *   lpt   1: the one-workgroup sweeps dispatch the MPOs costliest first
+ *         (sum over cores of n P^2), 0: in batch order; with one MPO only 1.
+ * Every choice computes the same factorisations (the paths differ only in
+ * the order of floating-point sums).  Afterwards the results of the handle
+ * are invalid as after tnrsvd_autotune, and a captured graph is recaptured
+ * on the next tnrsvd_run_graph.
+ * choice: NULL or 2 ints receiving {wmin, lpt}.  The call synchronises.
+ * Errors: E_INVALID (reps < 1); E_STATE (profiling on); those of tnrsvd_run.
+ */
+tnrsvd_status tnrsvd_autotune_sweeps(tnrsvd_t h, int reps, int* choice);
+
+/*
+ * tnrsvd_set_sweep_config -- apply a choice {wmin, lpt} of
+ * tnrsvd_autotune_sweeps without timing (e.g. one kept in a cache keyed by
+ * the shapes, precision and device).  choice: HOST array of 2 ints, wmin 0
+ * or > 128, lpt 0 or 1.  Results of the handle become invalid as after
+ * tnrsvd_autotune.  The default is {129, 1}.
+ * Errors: E_INVALID (NULL or out-of-range choice).
+ */
+tnrsvd_status tnrsvd_set_sweep_config(tnrsvd_t h, const int* choice);
+
+/*
  * tnrsvd_get_factor -- borrow a device pointer to one core of a result.
  *   which 0: U (row space, last core (r, I, K)), available after solve;
  *   which 1: V (column space, last core (s, J, K)), after solve; U and V

@@ -47,6 +47,19 @@ __device__ __forceinline__ void cfor(F&& f) {
   }
 }
 
+// Workgroups are dealt to the 8 XCDs in turn by linear id, and each XCD has
+// its own L2.  For a (gx, gy) grid launched with gy rounded up to a multiple
+// of 8, this maps the linear id so that every workgroup of one MPO (one
+// logical y) runs on the same XCD and shares its reads of that MPO's
+// reflectors or factor through one L2: logical x = (id / 8) % gx, y = id % 8
+// + 8 ((id / 8) / gx).
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+  const int id = blockIdx.x + gridDim.x * blockIdx.y;
+  const int slot = id >> 3;
+  bx = slot % gridDim.x;
+  by = (id & 7) + 8 * (slot / gridDim.x);
+}
+
 // Partner of this lane at butterfly step STEP (its value of x): lane ^ STEP
 // for 32 and 16 (LDS crossbar), the mirror within 16 or 8 lanes for 8 and 4,
 // lane ^ 2 and lane ^ 1 for 2 and 1 (DPP).  Each pairs lanes that differ in
@@ -338,10 +351,14 @@ __device__ __forceinline__ void wg_panel_qr(double* P0, int mp, int jb, int64_t 
 
 // True when core i's panel is wider than the one-workgroup register path:
 // more than 128 columns, or a last-core panel taller than the TSQR leaves.
-__device__ __forceinline__ bool wide_core(int i, int d, int n, int P, int rnext) {
+// Whether core i sends its MPO to the wide launches: a panel wider than the
+// register path and at least wmin columns, or (only at the default wmin) a
+// last-core panel beyond the TSQR leaves.  Larger wmin leave more MPOs on the
+// one-workgroup path (a choice of the sweep autotuner).
+__device__ __forceinline__ bool wide_core(int i, int d, int n, int P, int rnext, int wmin) {
   if (i == 0) return false;
-  if (P > kRegCols) return true;
-  return i == d - 1 && n * rnext > kTsqrLeavesMax * kRegRows;
+  if (P > kRegCols && P >= wmin) return true;
+  return wmin <= kRegCols + 1 && i == d - 1 && n * rnext > kTsqrLeavesMax * kRegRows;
 }
 
 // One workgroup: need[t * kWidePlan + .] = maxima over the wide MPOs of
@@ -351,7 +368,8 @@ __device__ __forceinline__ bool wide_core(int i, int d, int n, int P, int rnext)
 __global__ __launch_bounds__(512) void k_wide_classify(const MpoDesc* mpos,
                                                        const CoreDesc* cores, int batch, int op,
                                                        const int* pr, const int* plan,
-                                                       int max_d, int* wflag, int* need) {
+                                                       int max_d, int wmin, int* wflag,
+                                                       int* need) {
   for (int e = threadIdx.x; e < max_d * kWidePlan; e += blockDim.x) need[e] = 0;
   __syncthreads();
   for (int b = threadIdx.x; b < batch; b += blockDim.x) {
@@ -366,7 +384,7 @@ __global__ __launch_bounds__(512) void k_wide_classify(const MpoDesc* mpos,
       const int64_t m = (int64_t)n * rn;
       // shapes the one-workgroup path rejects stay there (it reports them)
       if (P < 1 || P > cd.RA * cd.xcap || m > md.wmcap || m > RCAP) ok = false;
-      if (wide_core(i, d, n, P, rn)) wide = true;
+      if (wide_core(i, d, n, P, rn, wmin)) wide = true;
       rn = (int)(m < P ? m : P);
     }
     if (!(wide && ok)) {
@@ -404,10 +422,11 @@ __global__ __launch_bounds__(NT) void k_wide_load(const MpoDesc* mpos, const Cor
                                                   int op, const int* pr, const int* rho,
                                                   const int* wflag, int t, int tf_n, int tp_n,
                                                   const T* __restrict__ Z, double* Wd,
-                                                  const double* L) {
+                                                  const double* L, int batch) {
   __shared__ double lds[GEMM_LDS];
-  const int b = blockIdx.y;
-  if (!wflag[b]) return;
+  int bx, b;
+  xcd_tile(bx, b);
+  if (b >= batch || !wflag[b]) return;
   const MpoDesc md = mpos[b];
   const int i = md.d - 1 - t;
   if (i < 0) return;
@@ -419,14 +438,14 @@ __global__ __launch_bounds__(NT) void k_wide_load(const MpoDesc* mpos, const Cor
   if (i == md.d - 1) {
     // Zt^T = Z^T: the (P, n, K) core read as the column-major (n K) x P panel
     const int64_t tot = (int64_t)n * md.K * P;
-    for (int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x; o < tot; o += (int64_t)gridDim.x * NT)
+    for (int64_t o = (int64_t)bx * NT + threadIdx.x; o < tot; o += (int64_t)gridDim.x * NT)
       Xt[o] = (double)Zc[o];
     return;
   }
   const int rnext = rho[md.r0 + i + 1];
   const int Pn = pr[md.r0 + i + 1];
   const int m = n * rnext;
-  int x = blockIdx.x;
+  int x = bx;
   const int tp = x % tp_n;
   x /= tp_n;
   const int tf = x % tf_n;
@@ -467,11 +486,12 @@ __device__ __forceinline__ bool wide_core_at(const MpoDesc& md, const CoreDesc* 
 __global__ __launch_bounds__(NT, 4) void k_wide_update(const MpoDesc* mpos, const CoreDesc* cores,
                                                     int op, const int* pr, const int* rho,
                                                     const int* wflag, int t, int j, double* Wd,
-                                                    const double* WV) {
+                                                    const double* WV, int batch) {
   __shared__ double sm[2 * SW * NB + NB * NB];
   const int tid = threadIdx.x;
-  const int b = blockIdx.y;
-  if (!wflag[b]) return;
+  int bx, b;
+  xcd_tile(bx, b);
+  if (b >= batch || !wflag[b]) return;
   const MpoDesc md = mpos[b];
   CoreDesc cd;
   WideCore wc;
@@ -480,7 +500,7 @@ __global__ __launch_bounds__(NT, 4) void k_wide_update(const MpoDesc* mpos, cons
   if (j0 >= wc.kmax) return;
   const int jb = wc.kmax - j0 < NB ? wc.kmax - j0 : NB;
   const int mp = wc.m - j0;
-  const int c0 = j0 + jb + SW * (int)blockIdx.x;
+  const int c0 = j0 + jb + SW * bx;
   const int cs = wc.P - c0 < SW ? wc.P - c0 : SW;
   if (cs <= 0) return;
   double* Wt = sm;                  // C^T V, cs x jb (ld NB)
@@ -609,9 +629,9 @@ __global__ __launch_bounds__(NT) void k_wide_finish(const MpoDesc* mpos, const C
 }  // namespace
 
 hipError_t launch_wide_classify(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
-                                const int* pr, const int* plan, int max_d, int* wflag, int* need,
-                                hipStream_t s) {
-  k_wide_classify<<<1, 512, 0, s>>>(mpos, cores, batch, op, pr, plan, max_d, wflag, need);
+                                const int* pr, const int* plan, int max_d, int wmin, int* wflag,
+                                int* need, hipStream_t s) {
+  k_wide_classify<<<1, 512, 0, s>>>(mpos, cores, batch, op, pr, plan, max_d, wmin, wflag, need);
   return hipGetLastError();
 }
 
@@ -632,10 +652,11 @@ hipError_t launch_rl_wide_step(const MpoDesc* mpos, const CoreDesc* cores, int b
   } else {
     gx = nm * tf_n * tp_n;
   }
+  const int gy = (batch + 7) / 8 * 8;   // whole groups of 8 for the XCD mapping
   by_dtype(dtype, [&](auto* tp) {
     using T = elem_t<decltype(tp)>;
-    k_wide_load<T><<<dim3(gx, batch), NT, 0, s>>>(mpos, cores, op, pr, rho, wflag, t, tf_n, tp_n,
-                                                  (const T*)Z, Wd, L);
+    k_wide_load<T><<<dim3(gx, gy), NT, 0, s>>>(mpos, cores, op, pr, rho, wflag, t, tf_n, tp_n,
+                                               (const T*)Z, Wd, L, batch);
   });
   const bool big = mm > 8 * NT;   // some panel taller than the register path
   // update(jj) after the panel of block jj: the columns right of it, which
@@ -643,8 +664,8 @@ hipError_t launch_rl_wide_step(const MpoDesc* mpos, const CoreDesc* cores, int b
   auto update = [&](int jj) {
     const int rest = Pm - NB * jj - 1;
     if (rest > 0)
-      k_wide_update<<<dim3((rest + SW - 1) / SW, batch), NT, 0, s>>>(mpos, cores, op, pr, rho,
-                                                                     wflag, t, jj, Wd, WV);
+      k_wide_update<<<dim3((rest + SW - 1) / SW, gy), NT, 0, s>>>(mpos, cores, op, pr, rho,
+                                                                  wflag, t, jj, Wd, WV, batch);
   };
   for (int j = 0; j < nb; ++j) {
     if (j > 0) update(j - 1);

@@ -11,6 +11,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <chrono>
+#include <climits>
 #include <vector>
 
 #include "../../include/tnrsvd.h"
@@ -130,6 +132,11 @@ struct tnrsvd_s {
   // the order the one-workgroup-per-MPO sweeps dispatch them in
   int* order_d = nullptr;
   std::vector<int> order;
+  // sweep launch choices (tnrsvd_autotune_sweeps / tnrsvd_set_sweep_config):
+  // the fewest product columns that send an MPO to the wide launches (above
+  // the register path), and whether the sweeps dispatch costliest MPOs first
+  int wide_min_p = kRegCols + 1;
+  bool lpt = true;
   // ranks kept by each rounding of the current solve (slots of d + 1 per MPO),
   // its product (0: A X, 1: A^T X) and whether it was the solve's SVD, for
   // tnrsvd_backward
@@ -925,7 +932,7 @@ tnrsvd_status rl_sweep(tnrsvd_t h, int op) {
       }
     }
     e = launch_wide_classify(h->mpos_d, h->cores_d, h->batch, op, h->pr, plan_d, h->max_d,
-                             h->wflag_d, h->wneed_d, h->stream);
+                             h->wide_min_p, h->wflag_d, h->wneed_d, h->stream);
     TRY(dev_check(e, "classify panels"));
     if (!capturing) {
       std::vector<int> need(nplan);
@@ -949,7 +956,8 @@ tnrsvd_status rl_sweep(tnrsvd_t h, int op) {
   {
     Timed tm(h, 1);
     e = launch_rl_pass(h->mpos_d, h->cores_d, h->batch, op, h->pr, h->rho, h->ldm, h->Z, h->dtype,
-                       h->W, h->L, h->tau, h->err, h->leaf_nc, wflag, h->order_d, h->stream);
+                       h->W, h->L, h->tau, h->err, h->leaf_nc, wflag,
+                       h->lpt ? h->order_d : nullptr, h->stream);
     TRY(dev_check(e, "right-to-left sweep"));
     if (plan) {
       for (int t = 0; t < h->max_d; ++t) {
@@ -977,7 +985,8 @@ tnrsvd_status do_sweep(tnrsvd_t h, int op, int mode) {
   int* rout = mode == 0 ? h->xr : h->vr;
   e = launch_lr_pass(h->mpos_d, h->cores_d, h->batch, op, h->rho, h->ldm, rout, h->W, h->tau,
                      h->scratch, out, odt, h->outs, so, h->tcap, h->mcap_s, h->ucap, h->err,
-                     h->wide_possible ? h->wflag_d : nullptr, h->order_d, h->stream);
+                     h->wide_possible ? h->wflag_d : nullptr, h->lpt ? h->order_d : nullptr,
+                     h->stream);
   TRY(dev_check(e, "left-to-right sweep"));
   // the ranks this rounding kept, for tnrsvd_backward
   const int slot = (int)h->hist_op.size();
@@ -1235,6 +1244,24 @@ tnrsvd_status plan_grad(tnrsvd_t h) {
 
 extern "C" {
 
+// After a change of launch choices: drop any captured graph (it holds the
+// old launches) and the solve state, so the next call starts afresh.
+static void forget_solve(tnrsvd_t h) {
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  h->space = kNone;
+  h->pending = -1;
+  h->projected = false;
+  h->solved = false;
+  h->y0_valid = false;
+}
+
 tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice) {
   TRY(check_handle(h));
   if (reps < 1) return fail(TNRSVD_E_INVALID, "reps must be >= 1");
@@ -1292,20 +1319,74 @@ tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice) {
     choice[2] = h->ct_threads[1];
     choice[3] = h->ct_cap[1];
   }
-  // a captured graph holds the old launch shapes: capture again on next use
-  if (h->gexec) {
-    (void)hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
+  forget_solve(h);
+  return TNRSVD_OK;
+}
+
+// Sweep launch choices, each a pair {wmin, lpt}: wmin = the fewest product
+// columns that send an MPO to the wide (multi-workgroup) right-to-left
+// launches, 0 for never; lpt = 1 to dispatch the one-workgroup sweeps
+// costliest MPO first.
+static void apply_sweep_config(tnrsvd_t h, const int* c) {
+  h->wide_min_p = c[0] <= 0 ? INT_MAX : std::max(c[0], kRegCols + 1);
+  h->lpt = c[1] != 0;
+  // the kept panel plans and any captured graph follow the old choice
+  for (auto& p : h->wplan) p.clear();
+}
+
+tnrsvd_status tnrsvd_set_sweep_config(tnrsvd_t h, const int* choice) {
+  TRY(check_handle(h));
+  if (!choice) return fail(TNRSVD_E_INVALID, "null sweep configuration");
+  if (choice[0] < 0 || (choice[0] > 0 && choice[0] <= kRegCols) || (choice[1] != 0 && choice[1] != 1))
+    return fail(TNRSVD_E_INVALID, "sweep configuration {%d, %d}: wmin must be 0 or > %d, lpt 0 or 1",
+                choice[0], choice[1], kRegCols);
+  apply_sweep_config(h, choice);
+  forget_solve(h);
+  return TNRSVD_OK;
+}
+
+tnrsvd_status tnrsvd_autotune_sweeps(tnrsvd_t h, int reps, int* choice) {
+  TRY(check_handle(h));
+  if (reps < 1) return fail(TNRSVD_E_INVALID, "reps must be >= 1");
+  if (h->profiling) return fail(TNRSVD_E_STATE, "disable profiling before autotuning");
+  // product-rank capacity over all cores: the one-workgroup path is offered
+  // panels up to 4 kRegCols columns only (beyond that it is known to be far
+  // slower, and one timed solve there can take minutes)
+  int64_t pcap = 0;
+  for (const CoreDesc& cd : h->ch) pcap = std::max<int64_t>(pcap, (int64_t)cd.RA * cd.xcap);
+  std::vector<std::array<int, 2>> cand;
+  const int wm[4] = {kRegCols + 1, 2 * kRegCols + 1, 4 * kRegCols + 1, 0};
+  const int lim[4] = {INT_MAX, INT_MAX, 4 * kRegCols, 4 * kRegCols};
+  for (int a = 0; a < (h->wide_possible ? 4 : 1); ++a) {
+    if (h->wide_possible && pcap > lim[a]) continue;
+    for (int l = 1; l >= 0; --l) {
+      if (h->batch == 1 && l == 0) continue;   // one MPO: the order does not matter
+      cand.push_back({h->wide_possible ? wm[a] : 0, l});
+    }
   }
-  if (h->graph) {
-    (void)hipGraphDestroy(h->graph);
-    h->graph = nullptr;
+  const int keep[2] = {h->wide_min_p == INT_MAX ? 0 : h->wide_min_p, h->lpt ? 1 : 0};
+  double best = 1e300;
+  std::array<int, 2> pick = {keep[0], keep[1]};
+  for (const auto& c : cand) {
+    apply_sweep_config(h, c.data());
+    forget_solve(h);
+    TRY(tnrsvd_run(h, nullptr));   // warm-up (and the panel plans of this choice)
+    TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps; ++r) TRY(tnrsvd_run(h, nullptr));
+    TRY(dev_check(hipStreamSynchronize(h->stream), "synchronise"));
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (dt < best) {
+      best = dt;
+      pick = c;
+    }
   }
-  h->space = kNone;
-  h->pending = -1;
-  h->projected = false;
-  h->solved = false;
-  h->y0_valid = false;
+  apply_sweep_config(h, pick.data());
+  forget_solve(h);
+  if (choice) {
+    choice[0] = pick[0];
+    choice[1] = pick[1];
+  }
   return TNRSVD_OK;
 }
 

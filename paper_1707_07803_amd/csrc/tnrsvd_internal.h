@@ -205,8 +205,8 @@ hipError_t launch_rl_pass(const MpoDesc* mpos, const CoreDesc* cores, int batch,
 constexpr int kWidePlan = 5;
 constexpr int kWideNB = 32;   // column block of the multi-workgroup QR
 hipError_t launch_wide_classify(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
-                                const int* pr, const int* plan, int max_d, int* wflag, int* need,
-                                hipStream_t s);
+                                const int* pr, const int* plan, int max_d, int wmin, int* wflag,
+                                int* need, hipStream_t s);
 hipError_t launch_rl_wide_step(const MpoDesc* mpos, const CoreDesc* cores, int batch, int op,
                                const int* pr, int* rho, int* ldm, const int* wflag, const void* Z,
                                int dtype, double* Wd, double* WV, double* L, double* tau, int t,

@@ -24,7 +24,8 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16": BF16}
 EXPORTS = [
     "tnrsvd_create", "tnrsvd_mult", "tnrsvd_orthogonalize", "tnrsvd_project",
     "tnrsvd_solve", "tnrsvd_run", "tnrsvd_run_graph", "tnrsvd_refine", "tnrsvd_backward",
-    "tnrsvd_backward_frozen", "tnrsvd_autotune",
+    "tnrsvd_backward_frozen", "tnrsvd_autotune", "tnrsvd_autotune_sweeps",
+    "tnrsvd_set_sweep_config",
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
@@ -38,6 +39,54 @@ KERNELS = {"contract": 0, "rl_sweep": 1, "lr_sweep": 2, "form_u": 3, "load_omega
 
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_STATE", -4: "E_NOMEM",
           -5: "E_DEVICE", -6: "E_NONFINITE"}
+
+
+def _bucket(x: int, edges) -> str:
+    for e in edges:
+        if x <= e:
+            return f"<={e}"
+    return f">{edges[-1]}"
+
+
+def sweep_shape_class(shapes, k: int, p: int, q: int, round_tol: float, max_rank: int,
+                      sketch_rank: int, orientation: str) -> str:
+    """The shape class a sweep launch choice is cached under: the batch size and
+    the largest core count, mode and bond of the MPOs (bucketed), and the solve
+    options that set the ranks of the products."""
+    d = max(len(s) for s in shapes)
+    n = max(max(c[1], c[2]) for s in shapes for c in s)
+    r = max(max(c[0], c[3]) for s in shapes for c in s)
+    return (f"batch{_bucket(len(shapes), [1, 16, 256, 4096])}|d{_bucket(d, [8, 16, 32, 64])}"
+            f"|n{n}|R{_bucket(r, [4, 8, 16, 32, 64])}|K{k + p}|q{q}|rmax{max_rank}"
+            f"|tol{'>0' if round_tol > 0 else '0'}|sketch{sketch_rank}|{orientation}")
+
+
+def sweep_cache_path() -> str:
+    return os.environ.get("TNRSVD_SWEEP_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "tnrsvd", "sweeps.json"))
+
+
+def read_sweep_cache(path: str) -> dict:
+    import json
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    return {k: [int(v[0]), int(v[1])] for k, v in table.items()
+            if isinstance(v, list) and len(v) == 2}
+
+
+def write_sweep_cache(path: str, key: str, choice) -> None:
+    """Add one entry (read, update, write to a temporary file, rename)."""
+    import json
+    table = read_sweep_cache(path)
+    table[key] = [int(choice[0]), int(choice[1])]
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 class TNrSVDError(RuntimeError):
@@ -92,6 +141,8 @@ def load_library(path: str = LIB_PATH):
     L.tnrsvd_backward.argtypes = [H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p)]
     L.tnrsvd_backward_frozen.argtypes = L.tnrsvd_backward.argtypes
     L.tnrsvd_autotune.argtypes = [H, I, ctypes.POINTER(I)]
+    L.tnrsvd_autotune_sweeps.argtypes = [H, I, ctypes.POINTER(I)]
+    L.tnrsvd_set_sweep_config.argtypes = [H, ctypes.POINTER(I)]
     L.tnrsvd_get_factor.argtypes = [H, I, I, I, ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I)]
     L.tnrsvd_copy_factor.argtypes = [H, I, I, I, ctypes.c_void_p]
@@ -165,6 +216,9 @@ class TNrSVD:
         self.K = k + p
         self.batch = len(mpos)
         self.precision = precision
+        self._shape_class = sweep_shape_class(
+            [[tuple(int(x) for x in c.shape) for c in cores] for cores in mpos], k, p, q,
+            float(round_tol), int(max_rank), int(sketch_rank), orientation)
         keep = []
         structs = (_Mpo * self.batch)()
         for b, cores in enumerate(mpos):
@@ -246,6 +300,36 @@ class TNrSVD:
         _check(self._lib.tnrsvd_autotune(self._h, int(reps), out))
         return {"A_X": {"threads": out[0], "blocks_per_core_cap": out[1]},
                 "At_X": {"threads": out[2], "blocks_per_core_cap": out[3]}}
+
+    def set_sweep_config(self, choice) -> None:
+        """tnrsvd_set_sweep_config: apply a sweep launch choice {wmin, lpt}."""
+        arr = (ctypes.c_int * 2)(int(choice[0]), int(choice[1]))
+        _check(self._lib.tnrsvd_set_sweep_config(self._h, arr))
+
+    def autotune_sweeps(self, reps: int = 1, cache: Optional[str] = "default") -> dict:
+        """tnrsvd_autotune_sweeps, with a cache of choices keyed by the shape class,
+        precision and device architecture (sweep_cache_key).  cache: a JSON file
+        path, "default" (TNRSVD_SWEEP_CACHE or ~/.cache/tnrsvd/sweeps.json) or None
+        (always time).  Returns {"wmin", "lpt", "key", "cached"}."""
+        path = sweep_cache_path() if cache == "default" else cache
+        key = self.sweep_cache_key()
+        table = read_sweep_cache(path) if path else {}
+        if key in table:
+            choice = table[key]
+            self.set_sweep_config(choice)
+            return {"wmin": choice[0], "lpt": choice[1], "key": key, "cached": True}
+        out = (ctypes.c_int * 2)()
+        _check(self._lib.tnrsvd_autotune_sweeps(self._h, int(reps), out))
+        choice = [int(out[0]), int(out[1])]
+        if path:
+            write_sweep_cache(path, key, choice)
+        return {"wmin": choice[0], "lpt": choice[1], "key": key, "cached": False}
+
+    def sweep_cache_key(self) -> str:
+        import torch
+        arch = getattr(torch.cuda.get_device_properties(torch.cuda.current_device()),
+                       "gcnArchName", "unknown").split(":")[0]
+        return f"{arch}|{self.precision}|{self._shape_class}"
 
     def run_graph(self, want_sigma: bool = True) -> Optional[np.ndarray]:
         """tnrsvd_run captured once into a HIP graph, replayed on later calls."""
