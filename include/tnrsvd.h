@@ -527,6 +527,20 @@ tnrsvd_status tnrsvd_round_mpo(const tnrsvd_mpo* a, double round_tol, int max_ra
  */
 tnrsvd_status tnrsvd_complex_embed(const tnrsvd_mpo* a, void* const* out, void* stream);
 /*
+ * tnrsvd_solve_complex -- top-k singular values of a complex MPO in one call
+ * (cores allowed complex in Sec. 2; the embedding is not the paper's): the
+ * real form of tnrsvd_complex_embed, in device buffers this call allocates
+ * and frees, solved by tnrsvd_run with k' = 2 opts->k and p' = 2 opts->p
+ * (each value of A appears twice in the real form), every other value
+ * returned.  a: as for tnrsvd_complex_embed; opts: the complex problem's
+ * options (k, p of A; q, seed, precision, tolerance, rank cap, stream,
+ * orientation and sketch rank as for tnrsvd_create, applied to the real
+ * form); sigma: HOST array of opts->k doubles, descending.  Synchronises the
+ * stream.  Errors: those of tnrsvd_complex_embed, tnrsvd_create (with k' and
+ * p') and tnrsvd_run; E_INVALID (null argument, opts->k < 1, opts->p < 0).
+ */
+tnrsvd_status tnrsvd_solve_complex(const tnrsvd_mpo* a, const tnrsvd_opts* opts, double* sigma);
+/*
  * tnrsvd_mpo_add -- the MPO of the sum of two matrices given as MPOs with the
  * same row and column modes (Sec. 3: ranks add).  a and b: device cores
  * (r, I, J, r') of the same dtype (F64 or F32), rank[0] = rank[d] = 1.  The

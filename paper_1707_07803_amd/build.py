@@ -65,6 +65,49 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(outdir: str, verbose: bool = False) -> str:
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer on
+    its HOST code (device code is not instrumented), for host-only tests of the
+    argument checks.  Rebuilt only when a source changed; returns the path."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOURCES + ["tnrsvd_internal.h", "wg_linalg.h"]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "tnrsvd.h"), "rb").read())
+    tag = h.hexdigest()[:16]
+    os.makedirs(outdir, exist_ok=True)
+    lib = os.path.join(outdir, f"libtnrsvd_san_{tag}.so")
+    if os.path.exists(lib):
+        return lib
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + [
+        "-O1", "-g", "-fno-omit-frame-pointer",
+        "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+        "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+    def comp(src):
+        obj = os.path.join(outdir, os.path.splitext(src)[0] + f"_{tag}.o")
+        r = subprocess.run([hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
+        objs = list(ex.map(comp, SOURCES))
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host",
+           "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", *objs, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, lib)
+    for o in objs:
+        os.remove(o)
+    if verbose:
+        print("built", lib)
+    return lib
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

@@ -2055,6 +2055,76 @@ tnrsvd_status tnrsvd_complex_embed(const tnrsvd_mpo* a, void* const* out, void* 
   return dev_check(hipStreamSynchronize(s), "synchronise");
 }
 
+tnrsvd_status tnrsvd_solve_complex(const tnrsvd_mpo* a, const tnrsvd_opts* opts, double* sigma) {
+  g_err.clear();
+  if (!a || !opts || !sigma) return fail(TNRSVD_E_INVALID, "null argument");
+  if (opts->k < 1 || opts->p < 0) return fail(TNRSVD_E_INVALID, "k must be >= 1 and p >= 0");
+  if (a->d < 1 || !a->rank || !a->rows || !a->cols)
+    return fail(TNRSVD_E_INVALID, "null rank/rows/cols array or d < 1");
+  if (a->dtype != TNRSVD_F64 && a->dtype != TNRSVD_F32)
+    return fail(TNRSVD_E_INVALID, "core dtype must be F64 or F32 (interleaved complex)");
+  const int d = a->d;
+  if (!a->core) return fail(TNRSVD_E_INVALID, "null core array");
+  if (a->rank[0] != 1 || a->rank[d] != 1) return fail(TNRSVD_E_SHAPE, "rank[0] and rank[d] must be 1");
+  for (int k = 0; k < d; ++k)
+    if (a->rank[k + 1] < 1 || a->rows[k] < 1 || a->cols[k] < 1 || !a->core[k])
+      return fail(TNRSVD_E_SHAPE, "core %d: bad shape or null pointer", k);
+  // shapes of the real form: inner ranks doubled, 2 I on the first core, 2 J
+  // on the last
+  std::vector<int64_t> rank(d + 1), rows(d), cols(d);
+  for (int k = 0; k <= d; ++k) rank[k] = (k == 0 || k == d) ? 1 : 2 * a->rank[k];
+  for (int k = 0; k < d; ++k) {
+    rows[k] = (k == 0 ? 2 : 1) * a->rows[k];
+    cols[k] = (k == d - 1 ? 2 : 1) * a->cols[k];
+  }
+  const size_t esz = a->dtype == TNRSVD_F64 ? sizeof(double) : sizeof(float);
+  std::vector<void*> buf(d, nullptr);
+  auto release_all = [&]() {
+    (void)hipStreamSynchronize((hipStream_t)opts->stream);
+    for (void* q : buf) (void)hipFree(q);
+  };
+  for (int k = 0; k < d; ++k) {
+    const int64_t n = sat_mul(sat_mul(sat_mul(rank[k], rows[k]), cols[k]), rank[k + 1]);
+    if (n >= kSat || n < 1) {
+      release_all();
+      return fail(TNRSVD_E_SHAPE, "core %d of the real form too large", k);
+    }
+    if (hipMalloc(&buf[k], esz * (size_t)n) != hipSuccess) {
+      (void)hipGetLastError();
+      release_all();
+      return fail(TNRSVD_E_NOMEM, "real form of core %d", k);
+    }
+  }
+  tnrsvd_status st = tnrsvd_complex_embed(a, buf.data(), opts->stream);
+  if (st != TNRSVD_OK) {
+    release_all();
+    return st;
+  }
+  tnrsvd_mpo real;
+  real.d = d;
+  real.rank = rank.data();
+  real.rows = rows.data();
+  real.cols = cols.data();
+  real.core = (const void* const*)buf.data();
+  real.dtype = a->dtype;
+  tnrsvd_opts o = *opts;
+  o.k = 2 * opts->k;
+  o.p = 2 * opts->p;
+  tnrsvd_t h = nullptr;
+  st = tnrsvd_create(&h, 1, &real, &o);
+  std::vector<double> s2((size_t)o.k);
+  if (st == TNRSVD_OK) st = tnrsvd_run(h, s2.data());
+  if (h) {
+    const std::string keep = g_err;   // destroy must not hide the first error
+    (void)tnrsvd_destroy(h);
+    g_err = keep;
+  }
+  release_all();
+  if (st != TNRSVD_OK) return st;
+  for (int j = 0; j < opts->k; ++j) sigma[j] = s2[(size_t)2 * j];
+  return TNRSVD_OK;
+}
+
 tnrsvd_status tnrsvd_mpo_add(const tnrsvd_mpo* a, const tnrsvd_mpo* b, void* const* out,
                              void* stream) {
   g_err.clear();

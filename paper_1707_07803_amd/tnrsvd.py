@@ -29,7 +29,7 @@ EXPORTS = [
     "tnrsvd_get_factor", "tnrsvd_copy_factor",
     "tnrsvd_get_omega", "tnrsvd_set_omega", "tnrsvd_get_ranks", "tnrsvd_destroy",
     "tnrsvd_profile", "tnrsvd_profile_read", "tnrsvd_get_product_ranks",
-    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_to_mpo_noalloc", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_complex_embed", "tnrsvd_mpo_add", "tnrsvd_rounded_ranks",
+    "tnrsvd_sparse_to_mpo", "tnrsvd_sparse_to_mpo_noalloc", "tnrsvd_sparse_round", "tnrsvd_round_mpo", "tnrsvd_complex_embed", "tnrsvd_solve_complex", "tnrsvd_mpo_add", "tnrsvd_rounded_ranks",
     "tnrsvd_rounded_copy", "tnrsvd_rounded_destroy", "tnrsvd_last_error", "tnrsvd_version",
 ]
 
@@ -168,6 +168,8 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(ctypes.c_void_p)]
     L.tnrsvd_complex_embed.argtypes = [ctypes.POINTER(_Mpo), ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.c_void_p]
+    L.tnrsvd_solve_complex.argtypes = [ctypes.POINTER(_Mpo), ctypes.POINTER(_Opts),
+                                       ctypes.POINTER(ctypes.c_double)]
     L.tnrsvd_mpo_add.argtypes = [ctypes.POINTER(_Mpo), ctypes.POINTER(_Mpo),
                                  ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
     L.tnrsvd_rounded_ranks.argtypes = [ctypes.c_void_p, P64]
@@ -628,13 +630,32 @@ def mpo_add(a, b):
 
 def solve_complex(cores, k: int, p: int = 0, q: int = 0, seed: int = 0, precision: str = "f64",
                   round_tol: float = 0.0, max_rank: int = 0, sketch_rank: int = 0):
-    """Top-k singular values of a complex MPO: TNrSVD of its real form with
-    k' = 2k and p' = 2p (each value appears twice), every other value taken."""
-    real = complex_embed(cores)
-    with TNrSVD(real, 2 * k, 2 * p, q, seed, precision, round_tol, max_rank,
-                sketch_rank=sketch_rank) as h:
-        sig = h.run()[0]
-    return sig[0::2].copy()
+    """Top-k singular values of a complex MPO (device tensors (R, I, J, R') of
+    complex128 or complex64) by tnrsvd_solve_complex: the library embeds it in
+    its real form, solves that with k' = 2k and p' = 2p and returns every other
+    value."""
+    import torch
+    L = load_library()
+    if cores[0].dtype not in (torch.complex128, torch.complex64):
+        raise TNrSVDError(-1, "cores must be complex128 or complex64")
+    real = [torch.view_as_real(c.contiguous()) for c in cores]      # (..., 2) interleaved
+    d = len(cores)
+    st = _Mpo()
+    ra = (ctypes.c_int64 * (d + 1))(*([int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores]))
+    ro = (ctypes.c_int64 * d)(*[int(c.shape[1]) for c in cores])
+    co = (ctypes.c_int64 * d)(*[int(c.shape[2]) for c in cores])
+    pt = (ctypes.c_void_p * d)(*[c.data_ptr() for c in real])
+    st.d, st.rank, st.rows, st.cols, st.core = d, ra, ro, co, pt
+    st.dtype = F64 if cores[0].dtype == torch.complex128 else F32
+    stream = torch.cuda.current_stream()
+    opts = _Opts(k=k, p=p, q=q, seed=seed, precision=PRECISIONS[precision],
+                 round_tol=float(round_tol), max_rank=int(max_rank), check_finite=0,
+                 stream=ctypes.c_void_p(stream.cuda_stream), orientation=0,
+                 sketch_rank=int(sketch_rank))
+    out = np.zeros(k, dtype=np.float64)
+    _check(L.tnrsvd_solve_complex(ctypes.byref(st), ctypes.byref(opts),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
 
 
 def _mpo_struct(cores):

@@ -113,8 +113,8 @@ def test_binding_structs_match_the_header(tmp_path):
 
 def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
     """tnrsvd_create (orientation, sketch_rank), tnrsvd_round_mpo,
-    tnrsvd_complex_embed and tnrsvd_mpo_add check their arguments before any
-    device call."""
+    tnrsvd_complex_embed, tnrsvd_solve_complex and tnrsvd_mpo_add check their
+    arguments before any device call."""
     from paper_1707_07803_amd import tnrsvd as binding
     P64 = ctypes.c_int64
     Mpo, Opts = binding._Mpo, binding._Opts
@@ -177,6 +177,24 @@ def test_new_entry_points_reject_bad_arguments_on_the_host(lib):
     assert emb(ctypes.byref(mpo([1, 2, 2], [2, 2], [2, 2])), outs, None) == -2
     assert emb(ctypes.byref(mpo([1, 2, 1], [2, 2], [2, 2], dtype=2)), outs, None) == -1
     assert emb(ctypes.byref(good), (ctypes.c_void_p * 2)(8, None), None) == -2
+
+    sc = lib.tnrsvd_solve_complex
+    sc.argtypes = [ctypes.POINTER(Mpo), ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_double)]
+    sig = (ctypes.c_double * 4)()
+    oc = Opts(k=2, p=2, q=0, seed=1, precision=0, round_tol=0.0, max_rank=0, check_finite=0,
+              stream=None)
+    assert sc(None, ctypes.byref(oc), sig) == -1
+    assert sc(ctypes.byref(good), None, sig) == -1
+    assert sc(ctypes.byref(good), ctypes.byref(oc), None) == -1
+    for kw in (dict(k=0, p=2), dict(k=2, p=-1)):
+        ob = Opts(q=0, seed=1, precision=0, round_tol=0.0, max_rank=0, check_finite=0,
+                  stream=None, **kw)
+        assert sc(ctypes.byref(good), ctypes.byref(ob), sig) == -1, kw
+    assert sc(ctypes.byref(mpo([1, 2, 1], [2, 2], [2, 2], dtype=2)), ctypes.byref(oc), sig) == -1
+    assert sc(ctypes.byref(mpo([1, 2, 2], [2, 2], [2, 2])), ctypes.byref(oc), sig) == -2
+    assert sc(ctypes.byref(mpo([1, 0, 1], [2, 2], [2, 2])), ctypes.byref(oc), sig) == -2
+    assert sc(ctypes.byref(mpo([1, 2, 1], [2, 2], [2, 2], cores=[core, None])), ctypes.byref(oc),
+              sig) == -2
 
     add = lib.tnrsvd_mpo_add
     add.argtypes = [ctypes.POINTER(Mpo), ctypes.POINTER(Mpo), ctypes.POINTER(ctypes.c_void_p),
