@@ -1013,6 +1013,14 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       const bool pre = !m_in_lds && nv < rn && (pre_lds || pre_wide || pre_glob) &&
                        2 * QBMAX * QBMAX <= LR_UB &&
                        (int64_t)rn * QB + 2 * QB * nv + nv <= so.qcap;
+      // Where U would sit in the scratch (R^T over the whole LDS carve), the
+      // Jacobi runs on the rows of R instead and keeps no rotations: the
+      // normalised rows of J R are the left singular vectors of R^T (so of
+      // M), re-orthonormalised by a small QR, and the carried factor is
+      // formed from R itself.  Needs room in LDS for that QR.
+      int rsel = so.rmax > 0 && so.rmax < nv ? so.rmax : nv;
+      if (cd.xcap2 < rsel) rsel = cd.xcap2;
+      const bool noacc = pre && pre_wide && 2 * nv * rsel + nv <= LR_MB + LR_VB + LR_UB;
       double* B = M;
       int blen = rn, bld = ld;
       double* tauP = SL.Q + (int64_t)rn * QB + 2 * QB * nv;
@@ -1027,14 +1035,21 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         const int bst = ((pre_lds || pre_wide) && nv * pld <= cap) ? pld : nv;
         for (int e = tid; e < nv * nv; e += NT) {
           const int p = e / nv, c = e - p * nv;
-          Bt[p * bst + c] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T
+          if (noacc)
+            Bt[p * bst + c] = c >= p ? M[(int64_t)c * ld + p] : 0.0;   // row p of R
+          else
+            Bt[p * bst + c] = c <= p ? M[(int64_t)p * ld + c] : 0.0;   // row p of R^T
         }
         __syncthreads();
         B = Bt;
         blen = nv;
         bld = bst;
       }
-      wg_jacobi_lr(B, nv, blen, bld, U, ibuf, red, delta * delta / (double)nv, B == Mb, U == Ub);
+      if (noacc)
+        jacobi_rows_lr(B, nv, bld, ibuf, red, delta * delta / (double)nv);
+      else
+        wg_jacobi_lr(B, nv, blen, bld, U, ibuf, red, delta * delta / (double)nv, B == Mb,
+                     U == Ub);
       wg_norms_sorted(B, nv, blen, bld, sig, perm, nrmb);
       if (tid == 0) {
         const int kk = nv < rn ? nv : rn;
@@ -1059,19 +1074,59 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       }
       __syncthreads();
       const int rnew = ibuf[1];
-      for (int k = tid; k < rnew; k += NT) sgn[k] = sign_of_max(U + (int64_t)perm[k] * nv, nv, 1);
-      __syncthreads();
       TO* xo = Xout + cd.x_off;
-      for (int64_t o = tid; o < (int64_t)nv * rnew; o += NT) {
-        const int row = (int)(o / rnew), k = (int)(o % rnew);
-        xo[o] = (TO)(U[(int64_t)perm[k] * nv + row] * sgn[k]);
+      if (noacc) {
+        // the kept rows of J R normalised (column k of Us, nv x rnew)
+        double* Us = SL.U;
+        for (int64_t o = tid; o < (int64_t)nv * rnew; o += NT) {
+          const int k = (int)(o / nv), c = (int)(o % nv);
+          const double sk = sig[k];
+          Us[o] = sk > 0.0 ? B[(int64_t)perm[k] * bld + c] / sk : 0.0;
+        }
+        __syncthreads();
+        // Householder QR (diag(R) >= 0) of Us in LDS, then E = Q [I; 0]
+        double* Ul = Mb;
+        double* vq = Mb + (int64_t)nv * rnew;
+        double* E = vq + nv;
+        for (int64_t o = tid; o < (int64_t)nv * rnew; o += NT) {
+          Ul[o] = Us[o];
+          E[o] = (o % nv) == (o / nv) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        wg_geqr2(Ul, nv, rnew, nrmb, vq, red, nv);
+        wg_apply_q(Ul, nrmb, nv, rnew, E, rnew, nv);
+        for (int k = tid; k < rnew; k += NT) sgn[k] = sign_of_max(E + (int64_t)k * nv, nv, 1);
+        __syncthreads();
+        for (int64_t o = tid; o < (int64_t)nv * rnew; o += NT) {
+          const int row = (int)(o / rnew), k = (int)(o % rnew);
+          xo[o] = (TO)(E[(int64_t)k * nv + row] * sgn[k]);
+        }
+        // T^T (rn x rnew) = Q_M [R E sgn; 0], R read from the factorised panel
+        for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
+          const int k = (int)(o / rn), f = (int)(o % rn);
+          double acc = 0.0;
+          if (f < nv) {
+            const double* ek = E + (int64_t)k * nv;
+            for (int c = f; c < nv; ++c) acc += M[(int64_t)c * ld + f] * ek[c];
+          }
+          SL.T[o] = acc * sgn[k];
+        }
+      } else {
+        for (int k = tid; k < rnew; k += NT)
+          sgn[k] = sign_of_max(U + (int64_t)perm[k] * nv, nv, 1);
+        __syncthreads();
+        for (int64_t o = tid; o < (int64_t)nv * rnew; o += NT) {
+          const int row = (int)(o / rnew), k = (int)(o % rnew);
+          xo[o] = (TO)(U[(int64_t)perm[k] * nv + row] * sgn[k]);
+        }
       }
       if (pre) {
         // T^T (rn x rnew, column-major = T row-major) = Q [B_sel^T; 0]
-        for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
-          const int k = (int)(o / rn), f = (int)(o % rn);
-          SL.T[o] = f < nv ? B[(int64_t)perm[k] * bld + f] * sgn[k] : 0.0;
-        }
+        if (!noacc)
+          for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
+            const int k = (int)(o / rn), f = (int)(o % rn);
+            SL.T[o] = f < nv ? B[(int64_t)perm[k] * bld + f] * sgn[k] : 0.0;
+          }
         // the whole LDS carve is free again (R^T and U were last read above)
         if (rn <= 512)
           wg_apply_q_cols<8, 4>(M, ld, tauP, rn, nv, SL.T, rn, rnew, Mb, LR_MB + LR_VB + LR_UB,

@@ -749,7 +749,7 @@ struct jac_ptr<true> {
   using type = lds_double*;
 };
 
-template <int LN, int E, int EU, bool BL, bool UL>
+template <int LN, int E, int EU, bool BL, bool UL, bool ACC = true>
 __device__ int jacobi_regs(double* Bg, int nv, int len, int ldb, double* Ug, int* flag,
                            double tiny, double skip2, double tol) {
   using PB = typename jac_ptr<BL>::type;
@@ -818,23 +818,25 @@ __device__ int jacobi_regs(double* Bg, int nv, int len, int ldb, double* Ug, int
             bq[e] = sn * x[i] + cs * y[i];
           }
         }
-        PU up = U + (int64_t)p * nv;
-        PU uq = U + (int64_t)q * nv;
-        double ux[EU], uy[EU];
+        if constexpr (ACC) {
+          PU up = U + (int64_t)p * nv;
+          PU uq = U + (int64_t)q * nv;
+          double ux[EU], uy[EU];
 #pragma unroll
-        for (int i = 0; i < EU; ++i) {
-          const int e = li + LN * i;
-          const bool ok = e < nv;
-          const double xv = up[ok ? e : 0], yv = uq[ok ? e : 0];
-          ux[i] = xv;
-          uy[i] = yv;
-        }
+          for (int i = 0; i < EU; ++i) {
+            const int e = li + LN * i;
+            const bool ok = e < nv;
+            const double xv = up[ok ? e : 0], yv = uq[ok ? e : 0];
+            ux[i] = xv;
+            uy[i] = yv;
+          }
 #pragma unroll
-        for (int i = 0; i < EU; ++i) {
-          const int e = li + LN * i;
-          if (e < nv) {
-            up[e] = cs * ux[i] - sn * uy[i];
-            uq[e] = sn * ux[i] + cs * uy[i];
+          for (int i = 0; i < EU; ++i) {
+            const int e = li + LN * i;
+            if (e < nv) {
+              up[e] = cs * ux[i] - sn * uy[i];
+              uq[e] = sn * ux[i] + cs * uy[i];
+            }
           }
         }
         if (li == 0) *flag = 1;
@@ -864,7 +866,8 @@ __device__ int jacobi_pick(double* B, int nv, int len, int ldb, double* U, int* 
 }
 
 // wg_jacobi for vectors of at most 256 entries (b_lds / u_lds: B / U lie in
-// LDS); longer ones take wg_jacobi itself.
+// LDS); longer ones take wg_jacobi itself.  jacobi_rows_lr: the same on the
+// nv (<= 256) rows of B in LDS without accumulating the rotations (U unused).
 __device__ int wg_jacobi_lr(double* B, int nv, int len, int ldb, double* U, int* flag,
                             double* red, double skip2, bool b_lds, bool u_lds) {
   if (len > 256 || nv > 256) return wg_jacobi(B, nv, len, ldb, U, flag, red, skip2);
@@ -883,6 +886,31 @@ __device__ int wg_jacobi_lr(double* B, int nv, int len, int ldb, double* U, int*
   if (b_lds) return jacobi_pick<true, false>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
   if (u_lds) return jacobi_pick<false, true>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
   return jacobi_pick<false, false>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
+}
+
+__device__ int jacobi_rows_lr(double* B, int nv, int ldb, int* flag, double* red, double skip2) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (nv < 2) return 0;
+  double part = 0.0;
+  for (int e = tid; e < nv * nv; e += NT) {
+    const double x = B[(int64_t)(e / nv) * ldb + e % nv];
+    part += x * x;
+  }
+  const double tiny = 256.0 * 4.930380657631324e-32 * block_sum(part, red);
+  const double tol = 2.220446049250313e-16 * (double)(nv > 16 ? nv : 16);
+  const int nn = nv + (nv & 1);
+  if (nn / 2 > NW) {
+    if (nv <= 64)
+      return jacobi_regs<16, 4, 1, true, false, false>(B, nv, nv, ldb, nullptr, flag, tiny, skip2,
+                                                       tol);
+    if (nv <= 128)
+      return jacobi_regs<16, 8, 1, true, false, false>(B, nv, nv, ldb, nullptr, flag, tiny, skip2,
+                                                       tol);
+    return jacobi_regs<16, 16, 1, true, false, false>(B, nv, nv, ldb, nullptr, flag, tiny, skip2,
+                                                      tol);
+  }
+  return jacobi_regs<64, 1, 1, true, false, false>(B, nv, nv, ldb, nullptr, flag, tiny, skip2, tol);
 }
 
 // Norms of the nv vectors, then a stable descending sort: sig[pos], perm[pos].
