@@ -483,7 +483,7 @@ __device__ __forceinline__ bool wide_core_at(const MpoDesc& md, const CoreDesc* 
 // trailing columns takes C <- (I - V T V^T)^T C = C - V (C^T V T)^T with the
 // explicit reflectors V of block j (buffer j & 1) and its T.  A small LDS
 // footprint keeps two workgroups per compute unit.
-__global__ __launch_bounds__(NT, 4) void k_wide_update(const MpoDesc* mpos, const CoreDesc* cores,
+__global__ __launch_bounds__(NT, 2) void k_wide_update(const MpoDesc* mpos, const CoreDesc* cores,
                                                     int op, const int* pr, const int* rho,
                                                     const int* wflag, int t, int j, double* Wd,
                                                     const double* WV, int batch) {

@@ -387,30 +387,42 @@ __device__ void wg_ab_rows(int mp, int N, int KK, double alpha, const double* __
   const int r16 = lane & 15, q4 = lane >> 4;
   // the 16 x 16 blocks are formed transposed, C^T = B^T A^T, so that a lane's
   // four results are four columns of one row and every read-modify-write
-  // instruction covers 16 consecutive rows of four columns
-  double b[8][NBK];   // B^T[col][k] = B[k][col], col = 16 j + r16, k = 4 st + q4
-#pragma unroll
-  for (int st = 0; st < 8; ++st) {
-    const int k = 4 * st + q4;
-#pragma unroll
-    for (int j = 0; j < NBK; ++j) {
-      const int col = 16 * j + r16;
-      b[st][j] = (k < KK && col < N) ? B[k * sbk + col * sbj] : 0.0;
-    }
-  }
+  // instruction covers 16 consecutive rows of four columns; B (small, usually
+  // LDS) is read at each product rather than held, to leave registers for the
+  // old values of C
   for (int r0 = 16 * w; r0 < mp; r0 += 16 * NW) {
-    dbl4 c[NBK];
-#pragma unroll
-    for (int j = 0; j < NBK; ++j) c[j] = dbl4{0.0, 0.0, 0.0, 0.0};
     const int row = r0 + r16;
+    // the old values of C are loaded first, so their reads overlap the products
+    double old[NBK][4];
+#pragma unroll
+    for (int j = 0; j < NBK; ++j)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int col = 16 * j + 4 * jj + q4;
+        const bool ok = row < mp && col < N;
+        const double v = C[ok ? (int64_t)col * ldc + row : 0];
+        old[j][jj] = v;
+      }
+    double av[8];
 #pragma unroll
     for (int st = 0; st < 8; ++st) {
       const int k = 4 * st + q4;
       const bool ok = k < KK && row < mp;
       const double v = A[ok ? (int64_t)k * lda + row : 0];
-      const double a = ok ? v : 0.0;   // A^T[k][row]
+      av[st] = ok ? v : 0.0;   // A^T[k][row]
+    }
+    dbl4 c[NBK];
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[st][j], a, c[j], 0, 0, 0);
+    for (int j = 0; j < NBK; ++j) c[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int k = 4 * st + q4;
+#pragma unroll
+      for (int j = 0; j < NBK; ++j) {
+        const int col = 16 * j + r16;   // B^T[col][k] = B[k][col]
+        const double bv = (k < KK && col < N) ? B[k * sbk + col * sbj] : 0.0;
+        c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av[st], c[j], 0, 0, 0);
+      }
     }
     // c[j][jj] = (A B)[row][16 j + 4 jj + q4]
 #pragma unroll
@@ -418,7 +430,7 @@ __device__ void wg_ab_rows(int mp, int N, int KK, double alpha, const double* __
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
         const int col = 16 * j + 4 * jj + q4;
-        if (row < mp && col < N) C[(int64_t)col * ldc + row] += alpha * c[j][jj];
+        if (row < mp && col < N) C[(int64_t)col * ldc + row] = old[j][jj] + alpha * c[j][jj];
       }
   }
 }
