@@ -1021,6 +1021,17 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       int rsel = so.rmax > 0 && so.rmax < nv ? so.rmax : nv;
       if (cd.xcap2 < rsel) rsel = cd.xcap2;
       const bool noacc = pre && pre_wide && 2 * nv * rsel + nv <= LR_MB + LR_VB + LR_UB;
+      // Likewise without the QR, when the panel has no more columns than rows
+      // and U would sit in the scratch: the Jacobi runs on the columns of M
+      // (rows of M^T, copied to LDS), whose normalised results are M's left
+      // singular vectors; the carried factor is then U^T M from M itself.
+      // M^T and the later small QR use the LDS after M (the V and U carve)
+      // when M itself sits in LDS, else the whole carve.
+      const int cst = nv + ((16 - nv % 32) + 32) % 32;
+      double* wk = m_in_lds ? Vb : Mb;
+      const int wcap = m_in_lds ? LR_VB + LR_UB : LR_MB + LR_VB + LR_UB;
+      const bool cols = !pre && nvg * nvg > LR_UB && rn <= nv && nv <= 256 &&
+                        (int64_t)rn * cst <= wcap && 2 * nv * rsel + nv <= wcap;
       double* B = M;
       int blen = rn, bld = ld;
       double* tauP = SL.Q + (int64_t)rn * QB + 2 * QB * nv;
@@ -1045,12 +1056,24 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         blen = nv;
         bld = bst;
       }
-      if (noacc)
-        jacobi_rows_lr(B, nv, bld, ibuf, red, delta * delta / (double)nv);
+      int nvec = nv;   // the vectors the Jacobi rotates (rows of B)
+      if (cols) {
+        // B = M^T in LDS: row f holds column f of the panel
+        for (int64_t e = tid; e < (int64_t)rn * nv; e += NT) {
+          const int f = (int)(e / nv), r = (int)(e - (int64_t)f * nv);
+          wk[(int64_t)f * cst + r] = M[(int64_t)r * ld + f];
+        }
+        B = wk;
+        nvec = rn;
+        blen = nv;
+        bld = cst;
+      }
+      if (noacc || cols)
+        jacobi_rows_lr(B, nvec, blen, bld, ibuf, red, delta * delta / (double)nv);
       else
         wg_jacobi_lr(B, nv, blen, bld, U, ibuf, red, delta * delta / (double)nv, B == Mb,
                      U == Ub);
-      wg_norms_sorted(B, nv, blen, bld, sig, perm, nrmb);
+      wg_norms_sorted(B, nvec, blen, bld, sig, perm, nrmb);
       if (tid == 0) {
         const int kk = nv < rn ? nv : rn;
         const double d2 = delta * delta;
@@ -1075,8 +1098,8 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       __syncthreads();
       const int rnew = ibuf[1];
       TO* xo = Xout + cd.x_off;
-      if (noacc) {
-        // the kept rows of J R normalised (column k of Us, nv x rnew)
+      if (noacc || cols) {
+        // the kept rows of J R (or of M^T J) normalised: column k of Us, nv x rnew
         double* Us = SL.U;
         for (int64_t o = tid; o < (int64_t)nv * rnew; o += NT) {
           const int k = (int)(o / nv), c = (int)(o % nv);
@@ -1085,8 +1108,8 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         }
         __syncthreads();
         // Householder QR (diag(R) >= 0) of Us in LDS, then E = Q [I; 0]
-        double* Ul = Mb;
-        double* vq = Mb + (int64_t)nv * rnew;
+        double* Ul = wk;
+        double* vq = wk + (int64_t)nv * rnew;
         double* E = vq + nv;
         for (int64_t o = tid; o < (int64_t)nv * rnew; o += NT) {
           Ul[o] = Us[o];
@@ -1101,12 +1124,15 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
           const int row = (int)(o / rnew), k = (int)(o % rnew);
           xo[o] = (TO)(E[(int64_t)k * nv + row] * sgn[k]);
         }
-        // T^T (rn x rnew) = Q_M [R E sgn; 0], R read from the factorised panel
+        // noacc: T^T (rn x rnew) = Q_M [R E sgn; 0], R read from the factorised
+        // panel; cols: T (rnew x rn, row-major) = (E sgn)^T M
         for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
           const int k = (int)(o / rn), f = (int)(o % rn);
+          const double* ek = E + (int64_t)k * nv;
           double acc = 0.0;
-          if (f < nv) {
-            const double* ek = E + (int64_t)k * nv;
+          if (cols) {
+            for (int r = 0; r < nv; ++r) acc += ek[r] * M[(int64_t)r * ld + f];
+          } else if (f < nv) {
             for (int c = f; c < nv; ++c) acc += M[(int64_t)c * ld + f] * ek[c];
           }
           SL.T[o] = acc * sgn[k];
@@ -1138,7 +1164,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
           __syncthreads();
           wg_apply_q(M, tauP, rn, nv, SL.T, rnew, ld);
         }
-      } else {
+      } else if (!cols) {
         for (int64_t o = tid; o < (int64_t)rnew * rn; o += NT) {
           const int k = (int)(o / rn), f = (int)(o % rn);
           SL.T[o] = M[(int64_t)perm[k] * ld + f] * sgn[k];

@@ -879,7 +879,8 @@ __device__ int jacobi_pick(double* B, int nv, int len, int ldb, double* U, int* 
 
 // wg_jacobi for vectors of at most 256 entries (b_lds / u_lds: B / U lie in
 // LDS); longer ones take wg_jacobi itself.  jacobi_rows_lr: the same on the
-// nv (<= 256) rows of B in LDS without accumulating the rotations (U unused).
+// nv rows (of len <= 256 entries) of B in LDS without accumulating the
+// rotations (U unused).
 __device__ int wg_jacobi_lr(double* B, int nv, int len, int ldb, double* U, int* flag,
                             double* red, double skip2, bool b_lds, bool u_lds) {
   if (len > 256 || nv > 256) return wg_jacobi(B, nv, len, ldb, U, flag, red, skip2);
@@ -900,29 +901,37 @@ __device__ int wg_jacobi_lr(double* B, int nv, int len, int ldb, double* U, int*
   return jacobi_pick<false, false>(B, nv, len, ldb, U, flag, tiny, skip2, tol);
 }
 
-__device__ int jacobi_rows_lr(double* B, int nv, int ldb, int* flag, double* red, double skip2) {
+__device__ int jacobi_rows_lr(double* B, int nv, int len, int ldb, int* flag, double* red,
+                              double skip2) {
   const int tid = threadIdx.x;
   __syncthreads();
   if (nv < 2) return 0;
   double part = 0.0;
-  for (int e = tid; e < nv * nv; e += NT) {
-    const double x = B[(int64_t)(e / nv) * ldb + e % nv];
+  for (int e = tid; e < nv * len; e += NT) {
+    const double x = B[(int64_t)(e / len) * ldb + e % len];
     part += x * x;
   }
   const double tiny = 256.0 * 4.930380657631324e-32 * block_sum(part, red);
-  const double tol = 2.220446049250313e-16 * (double)(nv > 16 ? nv : 16);
+  const double tol = 2.220446049250313e-16 * (double)(len > 16 ? len : 16);
   const int nn = nv + (nv & 1);
   if (nn / 2 > NW) {
-    if (nv <= 64)
-      return jacobi_regs<16, 4, 1, true, false, false>(B, nv, nv, ldb, nullptr, flag, tiny, skip2,
+    if (len <= 64)
+      return jacobi_regs<16, 4, 1, true, false, false>(B, nv, len, ldb, nullptr, flag, tiny, skip2,
                                                        tol);
-    if (nv <= 128)
-      return jacobi_regs<16, 8, 1, true, false, false>(B, nv, nv, ldb, nullptr, flag, tiny, skip2,
+    if (len <= 128)
+      return jacobi_regs<16, 8, 1, true, false, false>(B, nv, len, ldb, nullptr, flag, tiny, skip2,
                                                        tol);
-    return jacobi_regs<16, 16, 1, true, false, false>(B, nv, nv, ldb, nullptr, flag, tiny, skip2,
+    return jacobi_regs<16, 16, 1, true, false, false>(B, nv, len, ldb, nullptr, flag, tiny, skip2,
                                                       tol);
   }
-  return jacobi_regs<64, 1, 1, true, false, false>(B, nv, nv, ldb, nullptr, flag, tiny, skip2, tol);
+  if (len <= 64)
+    return jacobi_regs<64, 1, 1, true, false, false>(B, nv, len, ldb, nullptr, flag, tiny, skip2,
+                                                     tol);
+  if (len <= 128)
+    return jacobi_regs<64, 2, 1, true, false, false>(B, nv, len, ldb, nullptr, flag, tiny, skip2,
+                                                     tol);
+  return jacobi_regs<64, 4, 1, true, false, false>(B, nv, len, ldb, nullptr, flag, tiny, skip2,
+                                                   tol);
 }
 
 // Norms of the nv vectors, then a stable descending sort: sig[pos], perm[pos].
