@@ -1020,7 +1020,7 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       // formed from R itself.  Needs room in LDS for that QR.
       int rsel = so.rmax > 0 && so.rmax < nv ? so.rmax : nv;
       if (cd.xcap2 < rsel) rsel = cd.xcap2;
-      const bool noacc = pre && pre_wide && 2 * nv * rsel + nv <= LR_MB + LR_VB + LR_UB;
+      const bool noacc = pre && (pre_wide || pre_lds) && 2 * nv * rsel + nv <= LR_MB + LR_VB + LR_UB;
       // Likewise without the QR, when the panel has no more columns than rows
       // and U would sit in the scratch: the Jacobi runs on the columns of M
       // (rows of M^T, copied to LDS), whose normalised results are M's left
@@ -1030,8 +1030,8 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       const int cst = nv + ((16 - nv % 32) + 32) % 32;
       double* wk = m_in_lds ? Vb : Mb;
       const int wcap = m_in_lds ? LR_VB + LR_UB : LR_MB + LR_VB + LR_UB;
-      const bool cols = !pre && nvg * nvg > LR_UB && rn <= nv && nv <= 256 &&
-                        (int64_t)rn * cst <= wcap && 2 * nv * rsel + nv <= wcap;
+      const bool cols = !pre && rn <= nv && nv <= 256 && (int64_t)rn * cst <= wcap &&
+                        2 * nv * rsel + nv <= wcap && (int64_t)nv * rsel <= ucap;
       double* B = M;
       int blen = rn, bld = ld;
       double* tauP = SL.Q + (int64_t)rn * QB + 2 * QB * nv;
