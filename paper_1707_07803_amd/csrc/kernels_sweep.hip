@@ -158,10 +158,11 @@ __device__ __forceinline__ void reg_geqr(double (&x)[QMR][QNC], int m, int n, do
       if (4 * w + 3 + QOWN * u > j && 4 * w + QOWN * u < n) {
         const int c = o + QOWN * u;
         if (tj != 0.0) {
-          double acc = 0.0;
+          // four partial sums shorten the dependent FP64 chain
+          double ac4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int t = 0; t < QMR; ++t) acc += vh[16 * t] * x[t][u];
-          acc = row16_sum(acc);
+          for (int t = 0; t < QMR; ++t) ac4[t & 3] += vh[16 * t] * x[t][u];
+          const double acc = row16_sum((ac4[0] + ac4[1]) + (ac4[2] + ac4[3]));
           const double f = (c > j && c < n) ? tj * acc : 0.0;
 #pragma unroll
           for (int t = 0; t < QMR; ++t) x[t][u] -= f * vh[16 * t];
