@@ -41,6 +41,7 @@ constexpr int QCOLS = QOWN * QNC;
 constexpr int ARENA = 19456;           // doubles of static LDS per workgroup (152 KiB)
 static_assert(2 * QROWS + QCOLS + QCOLS * QCOLS <= ARENA - 32,
               "register QR: reflector buffers, diagonal, R gather");
+static_assert(QOWN * QROWS + QOWN <= QCOLS * QCOLS, "register QR: a block's reflectors in the R gather");
 
 // Sum over the 16 lanes of a DPP row; every lane of the row receives it.
 __device__ __forceinline__ double row16_sum(double v) {
@@ -49,6 +50,18 @@ __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<0x141>(v);   // row_half_mirror
   v += dpp_d<0x140>(v);   // row_mirror
   return v;
+}
+
+// Two such sums in lockstep (independent DPP chains interleave).
+__device__ __forceinline__ void row16_sum2(double& a, double& b) {
+  a += dpp_d<0xB1>(a);
+  b += dpp_d<0xB1>(b);
+  a += dpp_d<0x4E>(a);
+  b += dpp_d<0x4E>(b);
+  a += dpp_d<0x141>(a);
+  b += dpp_d<0x141>(b);
+  a += dpp_d<0x140>(a);
+  b += dpp_d<0x140>(b);
 }
 
 // Compile-time loop: f(integral_constant<int, B>), ..., f(<E - 1>).
@@ -63,23 +76,22 @@ __device__ __forceinline__ void static_for(F&& f) {
 // Householder reflector of column jj, held in col by the calling owner row
 // (Parlett's form: diag(R) >= 0, v[jj] = 1).  Writes v (zeros above the
 // diagonal, 1 on it) to LDS, tau to LDS and to tau_g, and the diagonal entry
-// of R to bt[jj].  Sums use two partial accumulators to keep the dependent
-// FP64 chain short.
+// of R to bt[jj].  Sums use partial accumulators to keep the dependent FP64
+// chains short.
 __device__ __forceinline__ void reg_reflect(const double (&col)[QMR], int jj, int m, int h,
                                             double* v, double* tbs, double* tau_g, double* bt) {
-  double sq[2] = {0.0, 0.0}, dg[2] = {0.0, 0.0};
+  double sq[4] = {0.0, 0.0, 0.0, 0.0}, dg[2] = {0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < QMR; ++t) {
     const int r = h + 16 * t;
     const double c = col[t];
     const double cm = (r > jj && r < m) ? c : 0.0;
-    sq[t & 1] += cm * cm;
+    sq[t & 3] += cm * cm;
     dg[t & 1] += (r == jj) ? c : 0.0;
   }
-  sq[0] += sq[1];
-  dg[0] += dg[1];
-  const double s2 = row16_sum(sq[0]);
-  const double al = row16_sum(dg[0]);
+  double s2 = (sq[0] + sq[1]) + (sq[2] + sq[3]);
+  double al = dg[0] + dg[1];
+  row16_sum2(s2, al);
   double tj, beta, inv_v0;
   if (s2 == 0.0) {
     inv_v0 = 0.0;
@@ -91,10 +103,19 @@ __device__ __forceinline__ void reg_reflect(const double (&col)[QMR], int jj, in
       beta = -al;
     }
   } else {
+    // v0 = al - nrm (for al > 0 as -s2 / (al + nrm), without cancellation);
+    // 1 / v0 and tau = 2 v0^2 / (s2 + v0^2) = -v0 / nrm are both formed from
+    // nrm, so a single division lies on the path to v
     const double nrm = sqrt(al * al + s2);
-    const double v0 = (al <= 0.0) ? al - nrm : -s2 / (al + nrm);
-    inv_v0 = 1.0 / v0;
-    tj = 2.0 * v0 * v0 / (s2 + v0 * v0);
+    if (al <= 0.0) {
+      const double v0 = al - nrm;
+      inv_v0 = 1.0 / v0;
+      tj = -v0 / nrm;
+    } else {
+      const double ap = al + nrm;
+      inv_v0 = -ap / s2;
+      tj = s2 / (ap * nrm);
+    }
     beta = nrm;
   }
 #pragma unroll
@@ -110,73 +131,105 @@ __device__ __forceinline__ void reg_reflect(const double (&col)[QMR], int jj, in
   }
 }
 
-// Householder QR of the register panel with one-step look-ahead: during the
-// update by reflector j, the row group holding column j + 1 builds reflector
-// j + 1 (into the other LDS buffer) as soon as that column is updated, so
-// building a reflector overlaps the other groups' updates.  A wave that does not hold column j + 1 copies reflector j from LDS
-// to V (column-major, ld ldv, whole column: zeros above the diagonal, 1 on
-// it).  R (row-major k x n, k = min(m, n), zero lower triangle) is read off the
+// Householder QR of the register panel, blocked by column slots: block ub is
+// the columns 32 ub .. 32 ub + 31 (slot ub of every owner row).  Within a
+// block, one barrier per column step: the owner of column j + 1 builds its
+// reflector (look-ahead) as soon as reflector j has updated it, and only the
+// block's own columns are updated step by step.  The reflectors of the block
+// stay in LDS (over the R gather buffer, free until the end) and are then
+// applied in order to the columns right of the block, with no barrier between
+// them; the next block starts after one barrier.  Every column still receives
+// the reflectors in the unblocked order, so the arithmetic per element is the
+// same.  A wave that does not hold column j + 1 copies reflector j from LDS to
+// V (column-major, ld ldv, whole column: zeros above the diagonal, 1 on it).
+// R (row-major k x n, k = min(m, n), zero lower triangle) is read off the
 // registers at the end: rows above the diagonal of column c are final once
 // reflectors 0..c-1 are applied, the diagonal comes from bt.  It is gathered in
 // LDS (Rl, k n doubles) and written out coalesced.
-__device__ __forceinline__ void reg_geqr(double (&x)[QMR][QNC], int m, int n, double* vb,
-                                         double* tb, double* tau_g, double* V, int ldv,
-                                         double* R, double* bt, double* Rl) {
+__device__ __forceinline__ void reg_geqr(double (&x)[QMR][QNC], int m, int n, double* tau_g,
+                                         double* V, int ldv, double* R, double* bt, double* Rl) {
   const int tid = threadIdx.x, lane = tid & 63, h = lane & 15, g = lane >> 4;
   const int w = wave_id();
   const int o = 4 * w + g;
   const int kmax = m < n ? m : n;
-  if (kmax > 0 && o == 0) {
-    double col[QMR];
+  double* Vk = Rl;                    // QOWN reflectors of QROWS rows
+  double* Tk = Rl + QOWN * QROWS;     // and their scalars
+  static_for<0, QNC>([&](auto UB) {
+    constexpr int ub = decltype(UB)::value;
+    constexpr int j0 = QOWN * ub;
+    if (j0 >= kmax) return;
+    const int jend = (j0 + QOWN) < kmax ? (j0 + QOWN) : kmax;
+    // the previous block's reflectors are no longer read
+    if (ub > 0) lds_barrier();
+    if (o == 0) {
+      double col[QMR];
 #pragma unroll
-    for (int t = 0; t < QMR; ++t) col[t] = x[t][0];
-    reg_reflect(col, 0, m, h, vb, tb, tau_g, bt);
-  }
-  for (int j = 0; j < kmax; ++j) {
-    const int buf = j & 1;
-    lds_barrier();
-    const double tj = tb[buf];
-    const double* vh = vb + buf * QROWS + h;
-    double* vnext = vb + (buf ^ 1) * QROWS;
-    const int jn = j + 1, on = jn % QOWN, un = jn / QOWN;
-    const bool la = jn < kmax && (on >> 2) == w;   // this wave holds column j + 1
-    if (!la && w == ((((j % QOWN) >> 2) + NW / 2) % NW)) {
-      // reflector j to global memory (rows lane + 64 k)
-      double* Vc = V + j * ldv;
-#pragma unroll
-      for (int k = 0; k < QROWS / 64; ++k) {
-        const int r = lane + 64 * k;
-        if (r < m) Vc[r] = vh[r - h];
-      }
+      for (int t = 0; t < QMR; ++t) col[t] = x[t][ub];
+      reg_reflect(col, j0, m, h, Vk, Tk, tau_g, bt);
     }
-    static_for<0, QNC>([&](auto U) {
-      constexpr int u = decltype(U)::value;
-      // compiler-only fence: the reflector is re-read from LDS for every slot
-      // instead of being held in 16 more registers (no hardware wait)
-      asm volatile("" ::: "memory");
-      // some column of this wave in slot u lies right of j (wave uniform)
-      if (4 * w + 3 + QOWN * u > j && 4 * w + QOWN * u < n) {
-        const int c = o + QOWN * u;
+    for (int j = j0; j < jend; ++j) {
+      lds_barrier();
+      const int k = j - j0;
+      const double tj = Tk[k];
+      const double* vh = Vk + k * QROWS + h;
+      const int jn = j + 1;
+      const bool la = jn < jend && ((jn - j0) >> 2) == w;   // this wave holds column j + 1
+      if (!la && w == (((k >> 2) + NW / 2) % NW)) {
+        // reflector j to global memory (rows lane + 64 r)
+        double* Vc = V + j * ldv;
+#pragma unroll
+        for (int r4 = 0; r4 < QROWS / 64; ++r4) {
+          const int r = lane + 64 * r4;
+          if (r < m) Vc[r] = vh[r - h];
+        }
+      }
+      // some column of this wave in slot ub lies right of j (wave uniform)
+      if (4 * w + 3 + j0 > j && 4 * w + j0 < n) {
+        const int c = o + j0;
         if (tj != 0.0) {
           // four partial sums shorten the dependent FP64 chain
           double ac4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int t = 0; t < QMR; ++t) ac4[t & 3] += vh[16 * t] * x[t][u];
+          for (int t = 0; t < QMR; ++t) ac4[t & 3] += vh[16 * t] * x[t][ub];
           const double acc = row16_sum((ac4[0] + ac4[1]) + (ac4[2] + ac4[3]));
           const double f = (c > j && c < n) ? tj * acc : 0.0;
 #pragma unroll
-          for (int t = 0; t < QMR; ++t) x[t][u] -= f * vh[16 * t];
+          for (int t = 0; t < QMR; ++t) x[t][ub] -= f * vh[16 * t];
         }
-        // look-ahead: column j + 1 is in slot u of this wave (wave uniform)
-        if (la && un == u && o == on) {
+        if (la && o == jn - j0) {
           double col[QMR];
 #pragma unroll
-          for (int t = 0; t < QMR; ++t) col[t] = x[t][u];
-          reg_reflect(col, jn, m, h, vnext, tb + (buf ^ 1), tau_g, bt);
+          for (int t = 0; t < QMR; ++t) col[t] = x[t][ub];
+          reg_reflect(col, jn, m, h, Vk + (k + 1) * QROWS, Tk + k + 1, tau_g, bt);
+        }
+      }
+    }
+    // the block's reflectors, in order, to the columns right of it (every
+    // reflector was published before the last step's barrier)
+    const int nb = jend - j0;
+    static_for<ub + 1, QNC>([&](auto U) {
+      constexpr int u = decltype(U)::value;
+      if (4 * w + QOWN * u < n) {
+        const bool live = o + QOWN * u < n;
+        for (int k = 0; k < nb; ++k) {
+          // compiler-only fence: the reflector is re-read from LDS for every
+          // slot instead of being held in 16 more registers
+          asm volatile("" ::: "memory");
+          const double tk = Tk[k];
+          if (tk != 0.0) {
+            const double* vh = Vk + k * QROWS + h;
+            double ac4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < QMR; ++t) ac4[t & 3] += vh[16 * t] * x[t][u];
+            const double acc = row16_sum((ac4[0] + ac4[1]) + (ac4[2] + ac4[3]));
+            const double f = live ? tk * acc : 0.0;
+#pragma unroll
+            for (int t = 0; t < QMR; ++t) x[t][u] -= f * vh[16 * t];
+          }
         }
       }
     });
-  }
+  });
   lds_barrier();
   // R off the registers: rows above the diagonal as they stand, the diagonal
   // from bt, zeros below
@@ -363,7 +416,7 @@ __global__ __launch_bounds__(NT) void k_rl_leaves(const MpoDesc* mpos, const Cor
   const int mrows = (m - r0) < QROWS ? (m - r0) : QROWS;
   double x[QMR][QNC];
   reg_load_plain<T>(x, Z + cd.z_off, m, P, r0, mrows);
-  reg_geqr(x, mrows, P, arena, arena + ARENA - 32, ws_tau + (int64_t)c * P,
+  reg_geqr(x, mrows, P, ws_tau + (int64_t)c * P,
            Xt + (int64_t)c * QROWS * P, mrows, Rdst, arena + 2 * QROWS,
            arena + 2 * QROWS + QCOLS);
 }
@@ -435,7 +488,7 @@ __global__ __launch_bounds__(NT) void k_rl_merge_level(const MpoDesc* mpos, cons
   double x[QMR][QNC];
   double* Rdst;
   const int mrows = tsqr_stack(x, Xt, m, P, nc, c, &Rdst);
-  reg_geqr(x, mrows, P, arena, arena + ARENA - 32, ws_tau + (int64_t)(nc + c) * P,
+  reg_geqr(x, mrows, P, ws_tau + (int64_t)(nc + c) * P,
            Xt + (int64_t)(nc + c) * QROWS * P, mrows, Rdst, arena + 2 * QROWS,
            arena + 2 * QROWS + QCOLS);
 }
@@ -523,7 +576,7 @@ __global__ __launch_bounds__(NT) void k_rl_pass(const MpoDesc* mpos, const CoreD
           Rdst = L + cd.l_off;
           taud = ws_tau + (int64_t)(nc + c) * P;
         }
-        reg_geqr(x, mrows, P, vb, tb, taud, Vdst, ldv, Rdst, arena + 2 * QROWS,
+        reg_geqr(x, mrows, P, taud, Vdst, ldv, Rdst, arena + 2 * QROWS,
                  arena + 2 * QROWS + QCOLS);
         __syncthreads();
       }
