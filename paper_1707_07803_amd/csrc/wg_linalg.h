@@ -37,6 +37,35 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Three wave sums in lockstep (their DPP chains interleave); every lane
+// receives the totals.
+__device__ __forceinline__ void wave_sum3(double& a, double& b, double& c) {
+  a += dpp_d<0x111>(a);
+  b += dpp_d<0x111>(b);
+  c += dpp_d<0x111>(c);
+  a += dpp_d<0x112>(a);
+  b += dpp_d<0x112>(b);
+  c += dpp_d<0x112>(c);
+  a += dpp_d<0x114>(a);
+  b += dpp_d<0x114>(b);
+  c += dpp_d<0x114>(c);
+  a += dpp_d<0x118>(a);
+  b += dpp_d<0x118>(b);
+  c += dpp_d<0x118>(c);
+  a += dpp_d<0x142, 0xa>(a);
+  b += dpp_d<0x142, 0xa>(b);
+  c += dpp_d<0x142, 0xa>(c);
+  a += dpp_d<0x143, 0xc>(a);
+  b += dpp_d<0x143, 0xc>(b);
+  c += dpp_d<0x143, 0xc>(c);
+  a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a), 63),
+                       __builtin_amdgcn_readlane(__double2loint(a), 63));
+  b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(b), 63),
+                       __builtin_amdgcn_readlane(__double2loint(b), 63));
+  c = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(c), 63),
+                       __builtin_amdgcn_readlane(__double2loint(c), 63));
+}
+
 // Sum over the 16 lanes of each DPP row, returned to every lane of the row:
 // shift-adds within the row leave the total in its lane 15 (src), which is
 // then read back by the row's lanes.
@@ -48,6 +77,29 @@ __device__ __forceinline__ double row16_sum(double v, int src) {
   const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
   const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
   return __hiloint2double(hi, lo);
+}
+
+// Three row sums in lockstep, as row16_sum.
+__device__ __forceinline__ void row16_sum3(double& a, double& b, double& c, int src) {
+  a += dpp_d<0x111>(a);
+  b += dpp_d<0x111>(b);
+  c += dpp_d<0x111>(c);
+  a += dpp_d<0x112>(a);
+  b += dpp_d<0x112>(b);
+  c += dpp_d<0x112>(c);
+  a += dpp_d<0x114>(a);
+  b += dpp_d<0x114>(b);
+  c += dpp_d<0x114>(c);
+  a += dpp_d<0x118>(a);
+  b += dpp_d<0x118>(b);
+  c += dpp_d<0x118>(c);
+  const int s4 = src << 2;
+  a = __hiloint2double(__builtin_amdgcn_ds_bpermute(s4, __double2hiint(a)),
+                       __builtin_amdgcn_ds_bpermute(s4, __double2loint(a)));
+  b = __hiloint2double(__builtin_amdgcn_ds_bpermute(s4, __double2hiint(b)),
+                       __builtin_amdgcn_ds_bpermute(s4, __double2loint(b)));
+  c = __hiloint2double(__builtin_amdgcn_ds_bpermute(s4, __double2hiint(c)),
+                       __builtin_amdgcn_ds_bpermute(s4, __double2loint(c)));
 }
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -796,6 +848,21 @@ __device__ int jacobi_regs(double* Bg, int nv, int len, int ldb, double* Ug, int
         if (q >= nv) continue;
         PB bp = B + (int64_t)p * ldb;
         PB bq = B + (int64_t)q * ldb;
+        // the rotation rows are loaded with the vectors, off the path that
+        // waits for the sums
+        PU up = nullptr, uq = nullptr;
+        double ux[ACC ? EU : 1], uy[ACC ? EU : 1];
+        if constexpr (ACC) {
+          up = U + (int64_t)p * nv;
+          uq = U + (int64_t)q * nv;
+#pragma unroll
+          for (int i = 0; i < EU; ++i) {
+            const int e = li + LN * i;
+            const bool ok = e < nv;
+            ux[i] = up[ok ? e : 0];
+            uy[i] = uq[ok ? e : 0];
+          }
+        }
         double x[E], y[E];
         double a = 0.0, b = 0.0, c = 0.0;
 #pragma unroll
@@ -809,19 +876,14 @@ __device__ int jacobi_regs(double* Bg, int nv, int len, int ldb, double* Ug, int
           b += y[i] * y[i];
           c += x[i] * y[i];
         }
-        if constexpr (LN == 16) {
-          a = row16_sum(a, src);
-          b = row16_sum(b, src);
-          c = row16_sum(c, src);
-        } else {
-          a = wave_sum(a);
-          b = wave_sum(b);
-          c = wave_sum(c);
-        }
+        if constexpr (LN == 16)
+          row16_sum3(a, b, c, src);
+        else
+          wave_sum3(a, b, c);
         if (a <= tiny || b <= tiny || a + b <= skip2 || c * c <= tol2 * a * b) continue;
         const double zeta = (b - a) / (2.0 * c);
         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           const int e = li + LN * i;
@@ -831,17 +893,6 @@ __device__ int jacobi_regs(double* Bg, int nv, int len, int ldb, double* Ug, int
           }
         }
         if constexpr (ACC) {
-          PU up = U + (int64_t)p * nv;
-          PU uq = U + (int64_t)q * nv;
-          double ux[EU], uy[EU];
-#pragma unroll
-          for (int i = 0; i < EU; ++i) {
-            const int e = li + LN * i;
-            const bool ok = e < nv;
-            const double xv = up[ok ? e : 0], yv = uq[ok ? e : 0];
-            ux[i] = xv;
-            uy[i] = yv;
-          }
 #pragma unroll
           for (int i = 0; i < EU; ++i) {
             const int e = li + LN * i;
