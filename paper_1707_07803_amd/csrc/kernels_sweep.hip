@@ -1228,9 +1228,11 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       s = rnew;
       __syncthreads();
     } else {
-      // last core: the (s n) x K panel as a column-major copy C
+      // last core: the (s n) x K panel as a column-major copy C, in LDS over
+      // the V and U carve when it fits (the panel M, read while C is formed,
+      // may sit in the M carve, which is free afterwards), else in the scratch
       const int64_t ck = (int64_t)nv * K;
-      double* C = (ck <= LR_UB) ? Ub : SL.U;
+      double* C = (ck <= LR_VB + LR_UB) ? Vb : SL.U;
       for (int64_t o = tid; o < ck; o += NT) {
         const int row = (int)(o % nv), kap = (int)(o / nv);
         C[o] = M[(int64_t)row * ld + kap];
@@ -1243,8 +1245,8 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
       if (so.mode == 0) {
         // thin Householder QR (Algorithm 5.2, mirrored): Q_d and the K x K R
         double* tauK = sig;
-        double* E = (ck <= LR_VB) ? Vb : SL.U + ck + K;
-        double* vtmp = (ck <= LR_UB && nv <= LR_MB) ? Mb : SL.M;
+        double* E = (ck <= LR_MB) ? Mb : SL.U + ck + K;
+        double* vtmp = (nv <= LR_SC) ? nrmb : SL.M;
         wg_geqr2(C, nv, K, tauK, vtmp, red);
         for (int64_t o = tid; o < (int64_t)K * K; o += NT) {
           const int r = (int)(o / K), c = (int)(o % K);
@@ -1262,8 +1264,8 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
         }
       } else {
         // economical SVD (Algorithm 5.3, mirrored): C W = X diag(sigma)
-        double* Wr = ((int64_t)K * K <= LR_VB) ? Vb : SL.U + ck;
-        wg_jacobi(C, K, nv, nv, Wr, ibuf, red);
+        double* Wr = ((int64_t)K * K <= LR_MB) ? Mb : SL.U + ck;
+        wg_jacobi_lr(C, K, nv, nv, Wr, ibuf, red, 0.0, C == Vb, Wr == Mb);
         wg_norms_sorted(C, K, nv, nv, sig, perm, nrmb);
         for (int k = tid; k < K; k += NT) sgn[k] = sign_of_max(C + (int64_t)perm[k] * nv, nv, 1);
         __syncthreads();

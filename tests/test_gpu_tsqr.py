@@ -90,3 +90,44 @@ def test_tall_last_core_f32_and_graph_replay():
         torch.cuda.synchronize()
         _ = torch.ones(1000, device="cuda").sum().item()
     h.close()
+
+
+def test_batch_mixing_tree_depths_equals_oracle():
+    """A 16-leaf tree (4096 rows) sharing the level launches with a 6-leaf
+    tree (1408 rows, a partial right subtree) and a 3-leaf one (640 rows):
+    the smaller trees stop at their own root levels while the big one goes on."""
+    from paper_1707_07803_amd import TNrSVD, omega_flat
+    k, p, q = 10, 6, 1
+    K = k + p
+    mpos = [tall_mpo(256, 11), tall_mpo(88, 12), tall_mpo(40, 13)]
+    oms = [omega_for(c, K, 70 + b) for b, c in enumerate(mpos)]
+    h = TNrSVD([to_device(c) for c in mpos], k, p, q)
+    for b, om in enumerate(oms):
+        h.set_omega(omega_flat(*om), b)
+    sig = h.run()
+    for b, c in enumerate(mpos):
+        ref = o.tnrsvd(c, k, p, q, omega=oms[b]).sigma
+        print(f"tree member {b}: {c[-1].shape[1] * K} rows, sigma rel err {rel_err(sig[b], ref):.2e}")
+        assert rel_err(sig[b], ref) <= 1e-10, b
+    h.close()
+
+
+def test_tall_last_core_factors_against_oracle():
+    """The singular vectors after the 6-leaf tree's replay in the
+    left-to-right pass: U and V densified are orthonormal and match the
+    oracle's column by column (sign conventions fixed on both sides)."""
+    from tests.gpu_helpers import cores_np
+    k, p, q = 20, 12, 1
+    A = tall_mpo(44, 84)
+    om = omega_for(A, k + p, 7)
+    ref = o.tnrsvd(A, k, p, q, omega=om)
+    sig, h = gpu_solve(A, k, p, q, omega=om)
+    assert rel_err(sig, ref.sigma) <= 1e-10
+    for which, R in ((0, ref.U), (1, ref.V)):
+        F = cores_np(h.factor(which))
+        F[-1] = F[-1][:, :, :k]
+        D, Dr = o.mps_to_dense(F), o.mps_to_dense(R)
+        assert D.shape == Dr.shape
+        np.testing.assert_allclose(D.T @ D, np.eye(k), atol=1e-12)
+        np.testing.assert_allclose(D, Dr, atol=1e-8)
+    h.close()
