@@ -1036,10 +1036,10 @@ __global__ __launch_bounds__(NT) void k_lr_pass(const MpoDesc* mpos, const CoreD
                    ((int64_t)2 * ri * s <= LR_UB) ? Ub : SL.U);
       } else if (wide && s <= 32) {
         wg_apply_wy(Wd + cd.w_off, Wd + cd.wt_off, mp, ri, M, s, Vb, Ub, Ub + 1024, Ub + 2048);
-      } else if (mp <= 256)
-        wg_apply_q_reg<4>(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB, tst);
+      } else if (mp <= 256)   // reflectors staged over the V and U carve (U is free here)
+        wg_apply_q_reg<4>(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB + LR_UB, tst);
       else if (mp <= 1024)
-        wg_apply_q_reg<16>(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB, tst);
+        wg_apply_q_reg<16>(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB + LR_UB, tst);
       else if (mp <= LR_VB)
         wg_apply_q_staged(Wd + cd.w_off, tau + cd.tau_off, mp, ri, M, s, Vb, LR_VB, tst);
       else
