@@ -212,6 +212,25 @@ def test_rectangular_uneven_cores():
         h.close()
 
 
+@pytest.mark.parametrize("k,p", [(24, 16), (64, 32)])
+def test_last_core_panel_layouts(k, p):
+    """The left-to-right pass keeps the last core's (s n) x K panel in LDS up
+    to 10240 entries.  K = 40 (s n = 256): the panel exactly at that limit,
+    its explicit Q in the scratch, the SVD rotations in LDS; K = 96: all
+    three in the scratch.  Both against the oracle, q = 1 (three roundings
+    with the QR of the last core, one with its SVD)."""
+    rng = np.random.default_rng(21)
+    d, R = 8, 4
+    cores = [rng.standard_normal((1 if i == 0 else R, 2, 2, 1 if i == d - 1 else R))
+             for i in range(d)]
+    om = omega_for(cores, k + p, 5)
+    ref = o.tnrsvd(cores, k, p, 1, omega=om)
+    sig, h = gpu_solve(cores, k, p, 1, omega=om)
+    print(f"K={k + p}: sigma rel err {rel_err(sig, ref.sigma):.2e}")
+    assert rel_err(sig, ref.sigma) <= TOL["f64"]
+    h.close()
+
+
 def test_zero_matrix():
     W = wl.small()
     Z = [np.zeros_like(c) for c in W.cores]
