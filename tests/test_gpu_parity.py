@@ -231,6 +231,25 @@ def test_last_core_panel_layouts(k, p):
     h.close()
 
 
+@pytest.mark.parametrize("R,rmax", [(16, 8), (12, 8), (10, 7)])
+def test_register_qr_panel_widths(R, rmax):
+    """Products of 128 (the register QR's widest panel, 256 rows), 96 (three
+    full 32-column blocks) and 70 columns (a 6-column last block) through the
+    right-to-left sweep, against the oracle."""
+    d, k, p = 10, 8, 8
+    rng = np.random.default_rng(5)
+    cores = [rng.standard_normal((1 if i == 0 else R, 2, 2, 1 if i == d - 1 else R)) / np.sqrt(R)
+             for i in range(d)]
+    om = omega_for(cores, k + p, 3)
+    ref = o.tnrsvd(cores, k, p, 1, omega=om, rmax=rmax)
+    sig, h = gpu_solve(cores, k, p, 1, omega=om, rmax=rmax)
+    P, _ = h.product_ranks()
+    print(f"R={R} rmax={rmax}: product ranks {P}, sigma rel err {rel_err(sig, ref.sigma):.2e}")
+    assert max(P) == R * rmax
+    assert rel_err(sig, ref.sigma) <= TOL["f64"]
+    h.close()
+
+
 def test_zero_matrix():
     W = wl.small()
     Z = [np.zeros_like(c) for c in W.cores]
