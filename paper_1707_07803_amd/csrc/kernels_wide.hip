@@ -21,8 +21,9 @@
 // left behind (reflectors below the diagonal of the panel, tau, R, rho, ldm)
 // is what the one-workgroup path leaves, so the left-to-right pass reads both
 // alike.  k_wide_classify decides per MPO, from the ranks on the device,
-// whether some core's panel is wider than the register path (P > 128, or a
-// last-core panel beyond the TSQR leaves); only those MPOs take these kernels,
+// whether some core's panel is wider than the register path (P > 128; for
+// the last core P > 256), or its last-core panel lies beyond the TSQR leaves;
+// only those MPOs take these kernels,
 // and only when the launch plan covers them (otherwise the one-workgroup path
 // keeps them).
 #include "tnrsvd_internal.h"
@@ -349,15 +350,16 @@ __device__ __forceinline__ void wg_panel_qr(double* P0, int mp, int jb, int64_t 
   }
 }
 
-// True when core i's panel is wider than the one-workgroup register path:
-// more than 128 columns, or a last-core panel taller than the TSQR leaves.
 // Whether core i sends its MPO to the wide launches: a panel wider than the
 // register path and at least wmin columns, or (only at the default wmin) a
-// last-core panel beyond the TSQR leaves.  Larger wmin leave more MPOs on the
-// one-workgroup path (a choice of the sweep autotuner).
+// last-core panel beyond the TSQR leaves.  A last core of at most 256 columns
+// does not count: it stays with the rest of its MPO on the one-workgroup path
+// (one blocked QR there costs less than taking every core of the MPO through
+// the wide launches).  Larger wmin leave more MPOs on the one-workgroup path
+// (a choice of the sweep autotuner).
 __device__ __forceinline__ bool wide_core(int i, int d, int n, int P, int rnext, int wmin) {
   if (i == 0) return false;
-  if (P > kRegCols && P >= wmin) return true;
+  if (P > kRegCols && P >= wmin && (i < d - 1 || P > 2 * kRegCols)) return true;
   return wmin <= kRegCols + 1 && i == d - 1 && n * rnext > kTsqrLeavesMax * kRegRows;
 }
 
