@@ -306,7 +306,8 @@ tnrsvd_status tnrsvd_autotune(tnrsvd_t h, int reps, int* choice);
  *         one-workgroup blocked path takes every panel); 513 and 0 are tried
  *         only when no product can exceed 512 columns (the one-workgroup
  *         path is far slower beyond), and only 0 when no product can exceed
- *         the register path;
+ *         the register path; a last core of at most 256 columns never sends
+ *         its MPO there (its blocked QR stays on the one-workgroup path);
  *   lpt   1: the one-workgroup sweeps dispatch the MPOs costliest first
  *         (sum over cores of n P^2), 0: in batch order; with one MPO only 1.
  * Every choice computes the same factorisations (the paths differ only in
